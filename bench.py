@@ -1,0 +1,218 @@
+"""Throughput of one differentiable-rendering gradient step on one MI355X.
+
+Workload (the reverse-mode configuration at 1024x1024): the Cornell-box-like
+scene with a GGX conductor, a 4096x4096x3 float32 albedo texture on the back
+wall and one roughness scalar; 1024x1024 pixels, 16 spp, max depth 3, no
+Russian roulette.  One step = primal render (seed A) -> L2 loss and
+image-space adjoint -> replayed adjoint (seed B) scattering texel and
+roughness gradients -> Adam on texture and roughness (gradients re-zeroed by
+the same kernel).  Inputs are resident in HBM before timing starts.
+
+Reported: Msamples/s = 1024*1024*16 / step time; the adjoint kernel's
+roofline (ALU bound; algorithmic FLOPs from the traversal/shading counters of
+a stats run, divided by its HIP-event launch duration); the FP64 CPU oracle's
+throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Algorithmic work per counted unit (derivation in the design notes):
+FLOP_PER_NODE = 40.0      # two child slab tests
+FLOP_PER_TRI = 40.0       # one watertight triangle test
+FLOP_PER_VERTEX = 200.0   # shading a scattering vertex: frame, BSDF eval + sample, light sample, MIS
+PEAK_FP32_VALU = 78.6     # TFLOP/s: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--spp", type=int, default=16)
+    ap.add_argument("--tex", type=int, default=4096)
+    ap.add_argument("--target-spp", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-aux", action="store_true", help="skip the 1M-triangle primal figure")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how the gradient step would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2202_01284_amd as drt
+    import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    R, SPP, D = args.res, args.spp, 3
+    sc = scenes.cornell(tex_size=args.tex, width=R, height=R, conductor=True)
+    gs = drt.Scene(sc)
+    cams = sc.cameras
+    tex = torch.full((args.tex, args.tex, 3), 0.5, dtype=torch.float32, device=dev)
+    rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
+    # target: seeded random texture, roughness 0.2, rendered once at high spp
+    tex_t = torch.from_numpy(scenes.random_texture(args.tex)).to(dev)
+    rough_t = torch.tensor([0.2], dtype=torch.float32, device=dev)
+    target = drt.render_forward(gs, [tex_t], rough_t, cams, args.target_spp, D, seed=1284)
+    del tex_t
+    gtex = torch.zeros_like(tex)
+    grough = torch.zeros_like(rough)
+    m_t, v_t = torch.zeros_like(tex), torch.zeros_like(tex)
+    m_r, v_r = torch.zeros_like(rough), torch.zeros_like(rough)
+    img = torch.empty((1, R, R, 3), dtype=torch.float32, device=dev)
+    adj = torch.empty_like(img)
+    ws = torch.empty(int(drt.lib.drt_loss_workspace_floats(img.numel())), dtype=torch.float32,
+                     device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ev = []
+
+    def step(k, timed):
+        drt.render_forward(gs, [tex], rough, cams, SPP, D, seed=2 * k + 1, out=img)
+        drt.loss_l2(img, target, adj=adj)
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+        drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * k + 2,
+                           grad_textures=[gtex], grad_roughness=grough)
+        if timed:
+            e1.record()
+            ev.append((e0, e1))
+        drt.adam_step(tex, gtex, m_t, v_t, k + 1, lr=1e-2, lo=0.0, hi=1.0, zero_grad=True)
+        drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=1e-2, lo=0.01, hi=1.0, zero_grad=True)
+
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    samples = R * R * SPP
+    value = samples / (ms * 1e-3) / 1e6
+    adj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    # algorithmic work of one adjoint launch (stats run, not timed)
+    stats = drt.new_stats()
+    drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * args.warmup + 2,
+                       grad_textures=[torch.zeros_like(tex)], grad_roughness=torch.zeros_like(rough),
+                       stats=stats)
+    st = drt.read_stats(stats)
+    flops = st["nodes"] * FLOP_PER_NODE + st["tris"] * FLOP_PER_TRI + st["vertices"] * FLOP_PER_VERTEX
+    achieved = flops / (adj_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_render_adjoint", "bound": "alu", "achieved": round(achieved, 4),
+                "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
+                "traffic": None, "launch_ms": round(adj_ms, 3),
+                "units_per_launch": {k: st[k] for k in ("rays", "shadow_rays", "nodes", "tris",
+                                                         "vertices", "scatter", "samples")}}
+
+    aux = None
+    if not args.no_aux:
+        aux = aux_primal_1m(drt, scenes, torch)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc, R, SPP, D, args.cpu_seconds)
+
+    line = {
+        "metric": "Msamples/s primal+adjoint at 1024^2 (gradient step)",
+        "value": round(value, 3),
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded procedural scene and textures)",
+        "config": {"workload": "cornell-box + GGX conductor, 4096^2x3 texture + 1 roughness, "
+                               "primal+L2+replayed adjoint+Adam",
+                   "width": R, "height": R, "spp": SPP, "max_depth": D, "russian_roulette": False,
+                   "texture": [args.tex, args.tex, 3], "triangles": sc.n_triangles,
+                   "target_spp": args.target_spp},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "aux": aux,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def aux_primal_1m(drt, scenes, torch):
+    """Primal Msamples/s on the ~1M-triangle procedural scene (1024^2, 64 spp,
+    depth 6, Russian roulette from 3): reported beside the headline."""
+    t = time.perf_counter()
+    sc = scenes.procedural()
+    gs = drt.Scene(sc)
+    build_s = time.perf_counter() - t
+    tex = [torch.from_numpy(x).cuda() for x in sc.textures]
+    rough = torch.from_numpy(sc.roughness).cuda()
+    img = torch.empty((1, 1024, 1024, 3), dtype=torch.float32, device="cuda")
+    drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=1, out=img)
+    torch.cuda.synchronize()
+    reps = 2
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(reps):
+        drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=2 + k, out=img)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    stats = drt.new_stats()
+    drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=2, out=img, stats=stats)
+    st = drt.read_stats(stats)
+    rays = st["rays"] + st["shadow_rays"]
+    return {"workload": "procedural ~1M triangles, 8 BSDFs, env + 16 quad lights, 1024^2 64spp D6 RR3",
+            "triangles": sc.n_triangles, "primal_msamples_s": round(1024 * 1024 * 64 / ms / 1e3, 2),
+            "primal_ms": round(ms, 2), "mrays_s": round(rays / ms / 1e3, 1),
+            "nodes_per_ray": round(st["nodes"] / max(rays, 1), 2),
+            "tris_per_ray": round(st["tris"] / max(rays, 1), 2),
+            "bvh": {k: gs.info[k] for k in ("n_nodes", "max_depth", "forced_leaves")},
+            "host_build_s": round(build_s, 2)}
+
+
+def cpu_baseline(sc, R, SPP, D, budget_s):
+    """FP64 oracle on a bounded, seeded sample of the workload's pixels:
+    primal (seed A) + adjoint (seed B) per pixel, all host threads."""
+    import oracle
+    orc = oracle.OracleScene(sc)
+    threads = oracle.n_threads_default()
+    rng = np.random.default_rng(1284)
+    n = 256
+    total_t, total_pix = 0.0, 0
+    while True:
+        n = min(n, R * R)
+        ids = rng.choice(R * R, n, replace=False).astype(np.int64)
+        adj = rng.normal(size=(n, 3)) * 1e-6
+        t = time.perf_counter()
+        orc.render(spp=SPP, max_depth=D, seed=1, pixel_ids=ids, threads=threads)
+        orc.adjoint(adj, spp=SPP, max_depth=D, seed=2, pixel_ids=ids, threads=threads)
+        dt = time.perf_counter() - t
+        total_t += dt
+        total_pix += n
+        if total_t >= 0.5 * budget_s or total_pix >= R * R:
+            break
+        # next batch sized to land near the budget
+        n = int(max(256, n * (budget_s - total_t) / max(dt, 1e-3)))
+    return {"value": round(total_pix * SPP / total_t / 1e6, 5), "unit": "Msamples/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{total_pix} random pixels x {SPP} spp of the same scene/texture "
+                      f"(primal + reverse-sweep adjoint), {total_t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

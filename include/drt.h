@@ -1,0 +1,260 @@
+/*
+ * drt.h -- C ABI of the MI355X differentiable path tracer.
+ *
+ * The library implements the data-parallel hot path of Path Replay
+ * Backpropagation as described in the Dr.Jit paper (Jakob, Speierer, Roussel,
+ * Vicini, "Dr.Jit: A Just-In-Time Compiler for Differentiable Rendering",
+ * ACM TOG 41(4), 2022):
+ *   - a primal path-tracing megakernel (megakernel #1 of Fig. "prb-structure",
+ *     Sec. "Physically Based Differentiable Rendering"),
+ *   - a replayed adjoint megakernel that regenerates every sample, recovers
+ *     the incident radiance at each vertex by subtraction ("arithmetic
+ *     invertibility"), and scatter-adds parameter gradients with atomics
+ *     (megakernels #2 and #3 of the same figure, fused; Sec. "Differentiating
+ *     polymorphism" on implicit reads becoming atomic scatter-reductions;
+ *     Sec. "AD tape surgery" on detached sampling),
+ *   - the image loss and the optimiser step around them.
+ *
+ * Conventions
+ *   - Every function returns a drt_status and never throws.  On failure the
+ *     thread-local message drt_last_error() says why.
+ *   - Argument errors return DRT_EINVAL before anything is enqueued.
+ *   - GPU work is enqueued asynchronously on `hip_stream` (a hipStream_t, or
+ *     NULL for the default stream); errors inside kernels surface at the next
+ *     synchronisation.  A launch failure returns DRT_EHIP.
+ *   - "device" pointers are HIP device memory owned by the caller (PyTorch
+ *     tensors in the Python binding); they must stay valid until the stream
+ *     work that uses them has completed.  "host" pointers are read during the
+ *     call only.
+ *   - Images are float32 [n_cams][height][width][3], row 0 at the top.
+ *     Textures are float32 [height][width][3].
+ */
+#ifndef DRT_H
+#define DRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DRT_OK = 0,
+  DRT_EINVAL = -1,      /* invalid argument (nothing was enqueued) */
+  DRT_ENOMEM = -2,      /* host allocation failed */
+  DRT_EHIP = -3,        /* a HIP call or kernel launch failed */
+  DRT_ESTATE = -4,      /* object in the wrong state */
+  DRT_EUNSUPPORTED = -5 /* valid request beyond this build's limits */
+} drt_status;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* drt_last_error(void);
+
+/* Library version string. */
+const char* drt_version(void);
+
+enum { DRT_MAX_TEXTURES = 8, DRT_MAX_CAMERAS = 32 };
+
+/* BSDF types of the material switch (the paper's polymorphic BSDF call,
+ * Sec. "Running example", dispatched here by a switch on this id). */
+enum {
+  DRT_BSDF_NULL = 0,             /* pass-through, counts as a vertex, skipped by shadow rays */
+  DRT_BSDF_DIFFUSE = 1,          /* Lambertian rho/pi (albedo constant or textured) */
+  DRT_BSDF_DIFFUSE_TEXTURED = 2, /* Lambertian with a texture (texture >= 0 required) */
+  DRT_BSDF_CONDUCTOR = 3,        /* GGX microfacet reflection, Schlick Fresnel with f0 */
+  DRT_BSDF_DIELECTRIC = 4,       /* rough GGX dielectric, exact Fresnel, index eta */
+  DRT_BSDF_PLASTIC = 5,          /* GGX coat (index eta) over a Lambertian base */
+  DRT_BSDF_TWOSIDED = 6,         /* Lambertian on both sides */
+  DRT_BSDF_MASK = 7              /* Lambertian with stochastic opacity, else pass-through */
+};
+
+/* Emitter types. */
+enum {
+  DRT_EMITTER_AREA = 0,        /* one-sided quad p0 + u e1 + v e2, front = e1 x e2 */
+  DRT_EMITTER_ENV = 1,         /* latitude-longitude environment map of the scene */
+  DRT_EMITTER_DIRECTIONAL = 2  /* p0 = unit direction towards the light, radiance = irradiance */
+};
+
+/* Render flags. */
+enum {
+  DRT_FLAG_NO_NEE = 1 /* BSDF sampling only (no next-event estimation, no MIS) */
+};
+
+typedef struct {
+  int32_t type;          /* DRT_BSDF_* */
+  int32_t texture;       /* albedo texture index, or -1 for the constant albedo */
+  int32_t rough_slot;    /* index into the roughness parameter array, or -1 for alpha */
+  int32_t reserved;
+  float albedo[3];       /* constant albedo */
+  float alpha;           /* constant GGX roughness (not squared) */
+  float f0[3];           /* conductor reflectance at normal incidence */
+  float eta;             /* dielectric / plastic index of refraction */
+  float opacity;         /* mask opacity in [0, 1] */
+  float reserved2[3];
+} drt_material;
+
+typedef struct {
+  int32_t type;          /* DRT_EMITTER_* */
+  int32_t reserved[3];
+  float p0[3], e1[3], e2[3];
+  float radiance[3];
+} drt_emitter;
+
+typedef struct {
+  int32_t width, height;
+} drt_texture_desc;
+
+/* Scene description: host arrays, read during drt_scene_plan/upload only. */
+typedef struct {
+  int32_t n_vertices, n_triangles;
+  const float* positions;        /* [n_vertices][3] */
+  const float* uvs;              /* [n_vertices][2], or NULL (all zero) */
+  const int32_t* indices;        /* [n_triangles][3]; winding gives the geometric normal */
+  const int32_t* tri_material;   /* [n_triangles] */
+  const int32_t* tri_emitter;    /* [n_triangles], -1 if the triangle does not emit */
+  int32_t n_materials;
+  const drt_material* materials;
+  int32_t n_emitters;
+  const drt_emitter* emitters;
+  int32_t n_textures;            /* <= DRT_MAX_TEXTURES */
+  const drt_texture_desc* textures;
+  int32_t n_roughness;           /* length of the roughness parameter array */
+  const float* envmap;           /* [env_height][env_width][3], or NULL */
+  int32_t env_width, env_height;
+} drt_scene_desc;
+
+typedef struct drt_scene drt_scene; /* opaque, library-owned host object */
+
+typedef struct {
+  int32_t n_nodes, n_leaves, max_depth, forced_leaves;
+  int32_t n_triangles, n_materials, n_emitters, n_textures, n_roughness;
+  int32_t env_width, env_height;
+  float eps;                     /* ray-spawn offset: 1e-4 x largest extent of the scene box */
+  float bounds_lo[3], bounds_hi[3];
+  uint64_t device_bytes;         /* bytes of the scene's device buffer actually used */
+} drt_scene_info;
+
+/* Upper bound of the device bytes a scene needs (no BVH build). */
+drt_status drt_scene_plan(const drt_scene_desc* desc, uint64_t* device_bytes);
+
+/* Build the scene on the host -- binned-SAH BVH flattened to 64-byte
+ * two-child nodes and 48-byte triangle records, material/emitter tables
+ * (the paper's closure-data array, appendix "Dynamic dispatch to closures"),
+ * environment sampling tables -- and copy it into the caller's device buffer
+ * (>= drt_scene_plan bytes, 256-byte aligned).  Blocks until the copy is done.
+ * The device buffer must outlive the scene object. */
+drt_status drt_scene_upload(const drt_scene_desc* desc, void* device_buffer, uint64_t buffer_bytes,
+                            void* hip_stream, drt_scene** out);
+
+/* Same build, written into a HOST buffer instead (for inspection/caching). */
+drt_status drt_scene_pack(const drt_scene_desc* desc, void* host_buffer, uint64_t buffer_bytes,
+                          drt_scene** out);
+
+drt_status drt_scene_info_get(const drt_scene* scene, drt_scene_info* out);
+drt_status drt_scene_destroy(drt_scene* scene);
+
+typedef struct {
+  float origin[3], target[3], up[3];
+  float fov_y_deg;               /* vertical field of view */
+  int32_t width, height;         /* all cameras of one call share width and height */
+} drt_camera;
+
+/* Differentiable parameters (device, caller-owned). */
+typedef struct {
+  const float* textures[DRT_MAX_TEXTURES]; /* [H][W][3] each, per scene texture */
+  const float* roughness;                  /* [n_roughness], or NULL if n_roughness == 0 */
+} drt_params;
+
+/* Gradient outputs (device, caller-owned).  The adjoint ADDS into them; the
+ * caller zeroes them.  A NULL entry skips that parameter. */
+typedef struct {
+  float* textures[DRT_MAX_TEXTURES];
+  float* roughness;
+} drt_grads;
+
+typedef struct {
+  int32_t spp;        /* samples per pixel, >= 1 */
+  int32_t max_depth;  /* D: path segments including the camera ray, >= 1 */
+  int32_t rr_depth;   /* Russian roulette after sampling at vertex k >= rr_depth */
+  uint32_t flags;     /* DRT_FLAG_* */
+  uint64_t seed;      /* Philox key */
+  uint64_t* stats;    /* device uint64[8] accumulators, or NULL (see drt_stat_*) */
+} drt_render_opts;
+
+/* Indices into drt_render_opts.stats. */
+enum {
+  DRT_STAT_RAYS = 0,      /* closest-hit rays traced */
+  DRT_STAT_SHADOW = 1,    /* shadow rays traced */
+  DRT_STAT_NODES = 2,     /* BVH nodes visited */
+  DRT_STAT_TRIS = 3,      /* ray/triangle tests */
+  DRT_STAT_VERTICES = 4,  /* scattering vertices shaded */
+  DRT_STAT_SCATTER = 5,   /* gradient atomics issued (adjoint) */
+  DRT_STAT_LREM_MAX = 6,  /* adjoint: max over samples of |L_rem| at path end, as float bits */
+  DRT_STAT_SAMPLES = 7    /* samples traced */
+};
+
+/* Primal rendering (Fig. "prb-structure", megakernel #1): for each pixel
+ * the mean of spp path-traced samples (box filter of one-pixel support).
+ * Sample s of pixel (cam, x, y) draws Philox4x32-10 blocks with key = seed
+ * and counter = (g_lo, g_hi, b, dim), g = ((cam*H + y)*W + x)*spp + s.
+ * image: device float [n_cams][H][W][3], overwritten. */
+drt_status drt_render_forward(const drt_scene* scene, const drt_params* params,
+                              const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                              float* image, void* hip_stream);
+
+/* Reverse-mode derivative of sum_p <adj_image_p, I_p> (megakernels #2 and
+ * #3 fused): each sample is traced once to get its radiance L, then replayed
+ * with the same random numbers, subtracting each vertex's emission and
+ * next-event term from L to recover the radiance arriving over the sampled
+ * direction; with detached sampling the gradient of a vertex is
+ * dL . (d NEE_k + L_rem * (d f_k) / f_k).  opts->seed is the replay seed (use
+ * a seed different from the primal's for a decorrelated gradient).
+ * adj_image: device float [n_cams][H][W][3].  Gradients are added. */
+drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
+                              const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                              const float* adj_image, const drt_grads* grads, void* hip_stream);
+
+/* Ray queries against the scene BVH.
+ * rays: device float [n][8] = (ox, oy, oz, tmin, dx, dy, dz, tmax), d unit length.
+ * mode 0 (closest): hits[i] = {t, b1, b2, prim} with prim = -1 on a miss;
+ *   ties in t go to the lowest triangle id.
+ * mode 1 (any): prim = 1 if any non-null triangle is hit in (tmin, tmax), else -1. */
+typedef struct {
+  float t, b1, b2;
+  int32_t prim;
+} drt_hit;
+drt_status drt_trace(const drt_scene* scene, const float* rays, int64_t n, int32_t mode,
+                     drt_hit* hits, void* hip_stream);
+
+/* Philox4x32-10: out[i] = philox(counter[i], key[i]).
+ * counters: device uint32 [n][4]; keys: device uint32 [n][2]; out: device uint32 [n][4]. */
+drt_status drt_philox(const uint32_t* counters, const uint32_t* keys, int64_t n, uint32_t* out,
+                      void* hip_stream);
+
+/* L2 image loss l = (1/n) sum (img - target)^2 and its adjoint
+ * adj = 2 (img - target) / n (the image-space adjoint that drives the
+ * adjoint pass).  img, target, adj: device float [n]; loss: device float [1];
+ * workspace: device float [drt_loss_workspace_floats(n)]. */
+int64_t drt_loss_workspace_floats(int64_t n);
+drt_status drt_loss_l2(const float* img, const float* target, int64_t n, float* adj, float* loss,
+                       float* workspace, void* hip_stream);
+
+/* Adam (Kingma & Ba) step t >= 1 with bias correction, then clamp to [lo, hi]:
+ * param, m, v updated in place; grad read, and reset to zero afterwards if
+ * zero_grad != 0 (ready for the next adjoint, which accumulates).
+ * All device float [n]. */
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t step;
+  float lo, hi;
+  int32_t zero_grad;
+} drt_adam_opts;
+drt_status drt_adam_step(float* param, float* grad, float* m, float* v, int64_t n,
+                         const drt_adam_opts* opts, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRT_H */

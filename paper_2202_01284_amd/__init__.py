@@ -1,0 +1,488 @@
+"""MI355X differentiable path tracer: thin Python binding of the C ABI.
+
+Every step of the rendering path runs in the HIP library ``libdrt.so``
+(built for gfx950 by ``paper_2202_01284_amd.build``); this module only
+marshals arguments.  PyTorch supplies device memory and the stream.  If the
+library is missing the import fails -- there is no fallback.
+
+Functions keep the C names without the ``drt_`` prefix where they wrap one
+entry point (``render_forward``, ``render_adjoint``, ``trace``, ``philox``,
+``loss_l2``, ``adam_step``, ``scene_upload``); ``RenderFn`` exposes the
+primal/adjoint pair as a ``torch.autograd.Function`` (the paper's custom
+adjoint, Sec. "Custom adjoints").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdrt.so")
+
+MAX_TEXTURES = 8
+MAX_CAMERAS = 32
+FLAG_NO_NEE = 1
+STAT_NAMES = ["rays", "shadow_rays", "nodes", "tris", "vertices", "scatter", "lrem_max", "samples"]
+
+_c_i32 = ctypes.c_int32
+_c_u32 = ctypes.c_uint32
+_c_i64 = ctypes.c_int64
+_c_u64 = ctypes.c_uint64
+_c_f = ctypes.c_float
+_vp = ctypes.c_void_p
+
+
+class drt_material(ctypes.Structure):
+    _fields_ = [("type", _c_i32), ("texture", _c_i32), ("rough_slot", _c_i32), ("reserved", _c_i32),
+                ("albedo", _c_f * 3), ("alpha", _c_f), ("f0", _c_f * 3), ("eta", _c_f),
+                ("opacity", _c_f), ("reserved2", _c_f * 3)]
+
+
+class drt_emitter(ctypes.Structure):
+    _fields_ = [("type", _c_i32), ("reserved", _c_i32 * 3), ("p0", _c_f * 3), ("e1", _c_f * 3),
+                ("e2", _c_f * 3), ("radiance", _c_f * 3)]
+
+
+class drt_texture_desc(ctypes.Structure):
+    _fields_ = [("width", _c_i32), ("height", _c_i32)]
+
+
+class drt_scene_desc(ctypes.Structure):
+    _fields_ = [("n_vertices", _c_i32), ("n_triangles", _c_i32), ("positions", _vp), ("uvs", _vp),
+                ("indices", _vp), ("tri_material", _vp), ("tri_emitter", _vp),
+                ("n_materials", _c_i32), ("materials", _vp), ("n_emitters", _c_i32),
+                ("emitters", _vp), ("n_textures", _c_i32), ("textures", _vp),
+                ("n_roughness", _c_i32), ("envmap", _vp), ("env_width", _c_i32),
+                ("env_height", _c_i32)]
+
+
+class drt_scene_info(ctypes.Structure):
+    _fields_ = [("n_nodes", _c_i32), ("n_leaves", _c_i32), ("max_depth", _c_i32),
+                ("forced_leaves", _c_i32), ("n_triangles", _c_i32), ("n_materials", _c_i32),
+                ("n_emitters", _c_i32), ("n_textures", _c_i32), ("n_roughness", _c_i32),
+                ("env_width", _c_i32), ("env_height", _c_i32), ("eps", _c_f),
+                ("bounds_lo", _c_f * 3), ("bounds_hi", _c_f * 3), ("device_bytes", _c_u64)]
+
+
+class drt_camera(ctypes.Structure):
+    _fields_ = [("origin", _c_f * 3), ("target", _c_f * 3), ("up", _c_f * 3), ("fov_y_deg", _c_f),
+                ("width", _c_i32), ("height", _c_i32)]
+
+
+class drt_params(ctypes.Structure):
+    _fields_ = [("textures", _vp * MAX_TEXTURES), ("roughness", _vp)]
+
+
+class drt_grads(ctypes.Structure):
+    _fields_ = [("textures", _vp * MAX_TEXTURES), ("roughness", _vp)]
+
+
+class drt_render_opts(ctypes.Structure):
+    _fields_ = [("spp", _c_i32), ("max_depth", _c_i32), ("rr_depth", _c_i32), ("flags", _c_u32),
+                ("seed", _c_u64), ("stats", _vp)]
+
+
+class drt_hit(ctypes.Structure):
+    _fields_ = [("t", _c_f), ("b1", _c_f), ("b2", _c_f), ("prim", _c_i32)]
+
+
+class drt_adam_opts(ctypes.Structure):
+    _fields_ = [("lr", _c_f), ("beta1", _c_f), ("beta2", _c_f), ("eps", _c_f), ("step", _c_i32),
+                ("lo", _c_f), ("hi", _c_f), ("zero_grad", _c_i32)]
+
+
+# Every entry point of include/drt.h with its ctypes signature.
+_SIGS = {
+    "drt_last_error": (ctypes.c_char_p, []),
+    "drt_version": (ctypes.c_char_p, []),
+    "drt_scene_plan": (_c_i32, [ctypes.POINTER(drt_scene_desc), ctypes.POINTER(_c_u64)]),
+    "drt_scene_upload": (_c_i32, [ctypes.POINTER(drt_scene_desc), _vp, _c_u64, _vp,
+                                  ctypes.POINTER(_vp)]),
+    "drt_scene_pack": (_c_i32, [ctypes.POINTER(drt_scene_desc), _vp, _c_u64, ctypes.POINTER(_vp)]),
+    "drt_scene_info_get": (_c_i32, [_vp, ctypes.POINTER(drt_scene_info)]),
+    "drt_scene_destroy": (_c_i32, [_vp]),
+    "drt_render_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                    _c_i32, ctypes.POINTER(drt_render_opts), _vp, _vp]),
+    "drt_render_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                    _c_i32, ctypes.POINTER(drt_render_opts), _vp,
+                                    ctypes.POINTER(drt_grads), _vp]),
+    "drt_trace": (_c_i32, [_vp, _vp, _c_i64, _c_i32, _vp, _vp]),
+    "drt_philox": (_c_i32, [_vp, _vp, _c_i64, _vp, _vp]),
+    "drt_loss_workspace_floats": (_c_i64, [_c_i64]),
+    "drt_loss_l2": (_c_i32, [_vp, _vp, _c_i64, _vp, _vp, _vp, _vp]),
+    "drt_adam_step": (_c_i32, [_vp, _vp, _vp, _vp, _c_i64, ctypes.POINTER(drt_adam_opts), _vp]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built: run paper_2202_01284_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class DrtError(RuntimeError):
+    pass
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib.drt_last_error().decode()
+        raise DrtError(f"{what} failed ({status}): {msg}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# scene
+# ---------------------------------------------------------------------------
+
+def make_desc(sc):
+    """drt_scene_desc over the arrays of a ``scenes.Scene`` (kept alive on the
+    returned object)."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    mats = (drt_material * sc.n_materials)()
+    for i in range(sc.n_materials):
+        m = mats[i]
+        m.type = int(sc.mat_type[i])
+        m.texture = int(sc.mat_texture[i])
+        m.rough_slot = int(sc.mat_rough_slot[i])
+        m.albedo[:] = [float(x) for x in sc.mat_albedo[i]]
+        m.alpha = float(sc.mat_alpha[i])
+        m.f0[:] = [float(x) for x in sc.mat_f0[i]]
+        m.eta = float(sc.mat_eta[i])
+        m.opacity = float(sc.mat_opacity[i])
+    ems = (drt_emitter * max(1, sc.n_emitters))()
+    for i in range(sc.n_emitters):
+        e = ems[i]
+        e.type = int(sc.em_type[i])
+        e.p0[:] = [float(x) for x in sc.em_p0[i]]
+        e.e1[:] = [float(x) for x in sc.em_e1[i]]
+        e.e2[:] = [float(x) for x in sc.em_e2[i]]
+        e.radiance[:] = [float(x) for x in sc.em_radiance[i]]
+    texs = (drt_texture_desc * max(1, len(sc.tex_shapes)))()
+    for i, (h, w) in enumerate(sc.tex_shapes):
+        texs[i].width = int(w)
+        texs[i].height = int(h)
+    keep += [mats, ems, texs]
+    d = drt_scene_desc()
+    d.n_vertices = int(sc.positions.shape[0])
+    d.n_triangles = int(sc.n_triangles)
+    d.positions = arr(sc.positions, np.float32)
+    d.uvs = arr(sc.uvs, np.float32)
+    d.indices = arr(sc.indices, np.int32)
+    d.tri_material = arr(sc.tri_material, np.int32)
+    d.tri_emitter = arr(sc.tri_emitter, np.int32)
+    d.n_materials = int(sc.n_materials)
+    d.materials = ctypes.addressof(mats)
+    d.n_emitters = int(sc.n_emitters)
+    d.emitters = ctypes.addressof(ems)
+    d.n_textures = len(sc.tex_shapes)
+    d.textures = ctypes.addressof(texs)
+    d.n_roughness = int(len(sc.roughness))
+    if sc.envmap is not None:
+        d.envmap = arr(sc.envmap, np.float32)
+        d.env_width = int(sc.envmap.shape[1])
+        d.env_height = int(sc.envmap.shape[0])
+    d._keep = keep
+    return d
+
+
+def scene_plan(sc) -> int:
+    d = make_desc(sc)
+    n = _c_u64()
+    _check(lib.drt_scene_plan(ctypes.byref(d), ctypes.byref(n)), "drt_scene_plan")
+    return int(n.value)
+
+
+def _info(h) -> dict:
+    inf = drt_scene_info()
+    _check(lib.drt_scene_info_get(h, ctypes.byref(inf)), "drt_scene_info_get")
+    out = {}
+    for name, _ in drt_scene_info._fields_:
+        v = getattr(inf, name)
+        out[name] = list(v) if not isinstance(v, (int, float)) else v
+    return out
+
+
+def scene_pack(sc):
+    """Host-side build of the scene's device layout: (bytes, info)."""
+    d = make_desc(sc)
+    n = scene_plan(sc)
+    buf = np.zeros(n, np.uint8)
+    h = _vp()
+    _check(lib.drt_scene_pack(ctypes.byref(d), buf.ctypes.data, n, ctypes.byref(h)), "drt_scene_pack")
+    info = _info(h)
+    lib.drt_scene_destroy(h)
+    return buf[:info["device_bytes"]], info
+
+
+class Scene:
+    """A scene uploaded into a torch-owned device buffer."""
+
+    def __init__(self, sc, device: str = "cuda"):
+        torch = _torch()
+        self.sc = sc
+        d = make_desc(sc)
+        n = _c_u64()
+        _check(lib.drt_scene_plan(ctypes.byref(d), ctypes.byref(n)), "drt_scene_plan")
+        self.buffer = torch.empty(int(n.value) + 256, dtype=torch.uint8, device=device)
+        base = self.buffer.data_ptr()
+        aligned = (base + 255) & ~255
+        h = _vp()
+        _check(lib.drt_scene_upload(ctypes.byref(d), aligned, int(n.value), _stream(),
+                                    ctypes.byref(h)), "drt_scene_upload")
+        self.handle = h
+        self.info = _info(h)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.drt_scene_destroy(h)
+            self.handle = None
+
+    @property
+    def n_textures(self) -> int:
+        return self.info["n_textures"]
+
+    @property
+    def n_roughness(self) -> int:
+        return self.info["n_roughness"]
+
+
+def scene_upload(sc, device="cuda") -> Scene:
+    return Scene(sc, device)
+
+
+# ---------------------------------------------------------------------------
+# rendering
+# ---------------------------------------------------------------------------
+
+def _cams(cams) -> "ctypes.Array":
+    arr = (drt_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].origin[:] = [float(x) for x in c.origin]
+        arr[i].target[:] = [float(x) for x in c.target]
+        arr[i].up[:] = [float(x) for x in c.up]
+        arr[i].fov_y_deg = float(c.fov_y_deg)
+        arr[i].width = int(c.width)
+        arr[i].height = int(c.height)
+    return arr
+
+
+def _params(scene: Scene, textures, roughness):
+    p = drt_params()
+    for i, t in enumerate(textures):
+        _expect(t, f"texture {i}")
+        p.textures[i] = t.data_ptr()
+    if roughness is not None and roughness.numel() > 0:
+        _expect(roughness, "roughness")
+        p.roughness = roughness.data_ptr()
+    return p
+
+
+def _expect(t, what):
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous float32 device tensor")
+
+
+def _opts(spp, max_depth, rr_depth, seed, flags, stats):
+    o = drt_render_opts()
+    o.spp = int(spp)
+    o.max_depth = int(max_depth)
+    o.rr_depth = int(rr_depth)
+    o.flags = int(flags)
+    o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.stats = None if stats is None else stats.data_ptr()
+    return o
+
+
+NO_RR = 1 << 30
+
+
+def render_forward(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,
+                   rr_depth: int = NO_RR, seed: int = 1, flags: int = 0, stats=None, out=None,
+                   stream=None):
+    """Image [n_cams, H, W, 3] (float32, device)."""
+    torch = _torch()
+    W, H = cams[0].width, cams[0].height
+    if out is None:
+        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=scene.buffer.device)
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
+    _check(lib.drt_render_forward(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                  out.data_ptr(), _stream(stream)), "drt_render_forward")
+    return out
+
+
+def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image, spp: int,
+                   max_depth: int, rr_depth: int = NO_RR, seed: int = 2, flags: int = 0,
+                   grad_textures=None, grad_roughness=None, stats=None, stream=None):
+    """Adds d<adj, I>/d params into grad_textures / grad_roughness (allocated
+    as zeros when not given) and returns them."""
+    torch = _torch()
+    _expect(adj_image, "adj_image")
+    if grad_textures is None:
+        grad_textures = [torch.zeros_like(t) for t in textures]
+    if grad_roughness is None and roughness is not None and roughness.numel() > 0:
+        grad_roughness = torch.zeros_like(roughness)
+    g = drt_grads()
+    for i, t in enumerate(grad_textures):
+        if t is not None:
+            _expect(t, f"grad texture {i}")
+            g.textures[i] = t.data_ptr()
+    if grad_roughness is not None:
+        _expect(grad_roughness, "grad roughness")
+        g.roughness = grad_roughness.data_ptr()
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
+    _check(lib.drt_render_adjoint(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                  adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
+           "drt_render_adjoint")
+    return grad_textures, grad_roughness
+
+
+def trace(scene: Scene, rays, mode: int = 0, stream=None):
+    """rays: float32 device [n, 8] = (o, tmin, d, tmax) -> hits int32/float32
+    view as a float32 tensor [n, 4] (t, b1, b2, prim bits)."""
+    torch = _torch()
+    _expect(rays, "rays")
+    n = rays.shape[0]
+    out = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    _check(lib.drt_trace(scene.handle, rays.data_ptr(), n, mode, out.data_ptr(), _stream(stream)),
+           "drt_trace")
+    return out
+
+
+def philox(counters, keys, stream=None):
+    """counters uint32-as-int32 [n,4], keys [n,2] (device) -> [n,4]."""
+    torch = _torch()
+    n = counters.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device=counters.device)
+    _check(lib.drt_philox(counters.data_ptr(), keys.data_ptr(), n, out.data_ptr(), _stream(stream)),
+           "drt_philox")
+    return out
+
+
+def loss_l2(img, target, adj=None, stream=None):
+    """(loss [1], adj) with adj = 2 (img - target) / n."""
+    torch = _torch()
+    _expect(img, "img")
+    _expect(target, "target")
+    n = img.numel()
+    if adj is None:
+        adj = torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float32, device=img.device)
+    ws = torch.empty(int(lib.drt_loss_workspace_floats(n)), dtype=torch.float32, device=img.device)
+    _check(lib.drt_loss_l2(img.data_ptr(), target.data_ptr(), n, adj.data_ptr(), loss.data_ptr(),
+                           ws.data_ptr(), _stream(stream)), "drt_loss_l2")
+    return loss, adj
+
+
+def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9,
+              beta2: float = 0.99, eps: float = 1e-8, lo: float = -np.inf, hi: float = np.inf,
+              zero_grad: bool = False, stream=None):
+    for t, w in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _expect(t, w)
+    o = drt_adam_opts()
+    o.lr, o.beta1, o.beta2, o.eps = lr, beta1, beta2, eps
+    o.step = int(step)
+    o.lo = float(max(lo, -3.0e38))
+    o.hi = float(min(hi, 3.0e38))
+    o.zero_grad = 1 if zero_grad else 0
+    _check(lib.drt_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                             param.numel(), ctypes.byref(o), _stream(stream)), "drt_adam_step")
+
+
+def new_stats():
+    torch = _torch()
+    return torch.zeros(8, dtype=torch.int64, device="cuda")
+
+
+def read_stats(stats) -> dict:
+    v = stats.cpu().numpy().astype(np.int64)
+    out = {k: int(v[i]) for i, k in enumerate(STAT_NAMES)}
+    out["lrem_max"] = float(np.array([v[6]], np.int64).astype(np.uint32).view(np.float32)[0])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+def _make_render_fn():
+    torch = _torch()
+
+    class RenderFn(torch.autograd.Function):
+        """image = render(params); backward runs the replayed adjoint with its
+        own seed (a decorrelated second integration, Sec. "Physically Based
+        Differentiable Rendering")."""
+
+        @staticmethod
+        def forward(ctx, scene, cams, spp, max_depth, rr_depth, seed_fwd, seed_adj, roughness,
+                    *textures):
+            rough = roughness.contiguous() if roughness is not None else None
+            texs = [t.contiguous() for t in textures]
+            img = render_forward(scene, texs, rough, cams, spp, max_depth, rr_depth, seed_fwd)
+            ctx.scene, ctx.cams = scene, cams
+            ctx.cfg = (spp, max_depth, rr_depth, seed_adj)
+            ctx.save_for_backward(*( [rough] if rough is not None else [] ), *texs)
+            ctx.has_rough = rough is not None
+            return img
+
+        @staticmethod
+        def backward(ctx, grad_img):
+            saved = ctx.saved_tensors
+            rough = saved[0] if ctx.has_rough else None
+            texs = list(saved[1:] if ctx.has_rough else saved)
+            spp, max_depth, rr_depth, seed_adj = ctx.cfg
+            gt, gr = render_adjoint(ctx.scene, texs, rough, ctx.cams, grad_img.contiguous(), spp,
+                                    max_depth, rr_depth, seed_adj)
+            return (None, None, None, None, None, None, None, gr, *gt)
+
+    return RenderFn
+
+
+_RenderFn = None
+
+
+def render(scene: Scene, cams, textures, roughness=None, spp=4, max_depth=3, rr_depth=NO_RR,
+           seed_fwd=1, seed_adj=2):
+    """Differentiable render: gradients flow to ``textures`` and ``roughness``."""
+    global _RenderFn
+    if _RenderFn is None:
+        _RenderFn = _make_render_fn()
+    return _RenderFn.apply(scene, cams, spp, max_depth, rr_depth, seed_fwd, seed_adj, roughness,
+                           *textures)

@@ -1,0 +1,133 @@
+// Internal layout shared by the host runtime (drt_host.cpp) and the gfx950
+// kernels (drt_kernels.hip).  Everything here is plain data: the scene lives
+// in one caller-owned device buffer, addressed through the pointers of
+// DScene, which is passed to every kernel by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/drt.h"
+
+namespace drt {
+
+// BVH traversal stack depth (entries per lane, held in LDS).  The builder
+// guarantees that no path from the root crosses more than
+// kMaxInteriorDepth interior nodes, so the stack never holds more than
+// kMaxInteriorDepth + 1 <= kStackDepth entries.
+constexpr int kStackDepth = 32;
+constexpr int kMaxInteriorDepth = 30;
+constexpr int kBlock = 256;            // threads per workgroup of the megakernels
+constexpr int kTile = 16;              // workgroup = 16 x 16 pixel tile
+constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
+
+// Two-child BVH node, 64 bytes: the boxes of both children and, per child,
+// either an interior node index (n == 0) or a leaf's triangle range.
+struct alignas(16) DNode {
+  float lo0x, lo0y, lo0z, hi0x;
+  float hi0y, hi0z, lo1x, lo1y;
+  float lo1z, hi1x, hi1y, hi1z;
+  int32_t c0, c1, n0, n1;
+};
+static_assert(sizeof(DNode) == 64, "DNode");
+
+// Triangle in BVH leaf order, 48 bytes: vertices, original id, flags.
+struct alignas(16) DTri {
+  float p0x, p0y, p0z, p1x;
+  float p1y, p1z, p2x, p2y;
+  float p2z;
+  int32_t prim;    // original triangle id
+  int32_t flags;   // bit 0: pass-through (null) surface, skipped by shadow rays
+  int32_t pad;
+};
+static_assert(sizeof(DTri) == 48, "DTri");
+
+// Shading attributes by original triangle id, 32 bytes.
+struct alignas(16) DShade {
+  float u0, v0, u1, v1;
+  float u2, v2;
+  int32_t material, emitter;
+};
+static_assert(sizeof(DShade) == 32, "DShade");
+
+struct alignas(16) DMaterial {
+  int32_t type, texture, rough_slot, pad;
+  float albedo[3], alpha;
+  float f0[3], eta;
+  float opacity, pad2[3];
+};
+static_assert(sizeof(DMaterial) == 64, "DMaterial");
+
+struct alignas(16) DEmitter {
+  int32_t type, pad0, pad1, pad2;
+  float p0[3], area;
+  float e1[3], pad3;
+  float e2[3], pad4;
+  float n[3], pad5;
+  float radiance[3], pad6;
+};
+static_assert(sizeof(DEmitter) == 96, "DEmitter");
+
+struct DScene {
+  const DNode* nodes;
+  const DTri* tris;
+  const DShade* shade;
+  const DMaterial* mats;
+  const DEmitter* ems;
+  const float* env;          // [h][w][3]
+  const float* env_puv;      // [h][w]: density in (u, v) of the sampling distribution
+  const float* env_cdf_row;  // [h+1]
+  const float* env_cdf_col;  // [h][w+1]
+  int32_t n_ems, env_w, env_h, env_emitter;
+  int32_t n_mats, n_rough, n_tex, pad;
+  float eps;
+  int32_t tex_w[DRT_MAX_TEXTURES], tex_h[DRT_MAX_TEXTURES];
+};
+
+struct DParams {
+  const float* tex[DRT_MAX_TEXTURES];
+  const float* rough;
+};
+
+struct DGrads {
+  float* tex[DRT_MAX_TEXTURES];
+  float* rough;
+};
+
+struct DCam {
+  float ox, oy, oz;
+  float fx, fy, fz;   // forward
+  float rx, ry, rz;   // right
+  float ux, uy, uz;   // up
+  float tan_half, aspect;
+};
+
+struct DCams {
+  int32_t n, width, height, pad;
+  DCam cam[DRT_MAX_CAMERAS];
+};
+
+struct DRender {
+  int32_t spp, max_depth, rr_depth;
+  uint32_t flags;
+  uint32_t key0, key1;
+  uint64_t* stats;
+};
+
+// Launchers (drt_kernels.hip).
+hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
+                                 const DRender& r, float* image, hipStream_t st);
+hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
+                                 const DRender& r, const float* adj, const DGrads& g,
+                                 hipStream_t st);
+hipError_t launch_trace(const DScene& s, const float* rays, int64_t n, int mode, drt_hit* hits,
+                        hipStream_t st);
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
+                         hipStream_t st);
+int64_t loss_workspace_floats(int64_t n);
+hipError_t launch_loss_l2(const float* img, const float* tgt, int64_t n, float* adj, float* loss,
+                          float* ws, hipStream_t st);
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n,
+                       const drt_adam_opts& o, hipStream_t st);
+
+}  // namespace drt

@@ -1,0 +1,306 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Tolerances (written here, applied element by element):
+  images   -- a pixel passes if every channel has |g - o| <= 1e-3 |o| + 1e-6;
+              at least 99.9% of pixels pass and the mean absolute error is
+              <= 1e-4 (relative to max(1, mean |o|) for scenes brighter than 1).
+  gradients -- ||g - o|| <= 1e-3 ||o|| and, per entry with |o| >= 1e-2 max|o|,
+              |g - o| <= 1e-3 |o| on at least 99.9% of those entries.
+  vs central differences -- |g - fd| <= 2e-2 max(|fd|, 1e-3 max|fd|).
+Integer work (Philox words, hit triangle ids) is compared bit-exactly; hit
+ids on rays whose answer lies within FP32 reach (the oracle's ambiguity flag)
+are excluded and counted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2202_01284_amd  # noqa: F401  (fails loudly without libdrt.so)
+
+
+def _drt():
+    import paper_2202_01284_amd as drt
+    return drt
+
+
+def _params(sc):
+    tex = [torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in sc.textures]
+    rough = torch.from_numpy(np.ascontiguousarray(sc.roughness)).cuda() if len(sc.roughness) else None
+    return tex, rough
+
+
+def check_image(g, o, what=""):
+    g = np.asarray(g, np.float64).reshape(-1, 3)
+    o = np.asarray(o, np.float64).reshape(-1, 3)
+    err = np.abs(g - o)
+    ok = (err <= 1e-3 * np.abs(o) + 1e-6).all(axis=1)
+    frac = ok.mean()
+    mae = err.mean()
+    scale = max(1.0, float(np.abs(o).mean()))
+    print(f"{what}: pass {frac:.5f} ({(~ok).sum()} px fail), mae {mae:.3g}, max err {err.max():.3g}",
+          flush=True)
+    assert frac >= 0.999, (what, frac)
+    assert mae <= 1e-4 * scale, (what, mae)
+
+
+def check_grad(g, o, what=""):
+    g = np.asarray(g, np.float64).reshape(-1)
+    o = np.asarray(o, np.float64).reshape(-1)
+    no = np.linalg.norm(o)
+    assert no > 0, what
+    rel = np.linalg.norm(g - o) / no
+    big = np.abs(o) >= 1e-2 * np.abs(o).max()
+    ok = np.abs(g - o)[big] <= 1e-3 * np.abs(o)[big]
+    print(f"{what}: rel l2 {rel:.3g}, big entries {big.sum()}, pass {ok.mean():.5f}", flush=True)
+    assert rel <= 1e-3, (what, rel)
+    assert ok.mean() >= 0.999, (what, ok.mean())
+
+
+# ---------------------------------------------------------------------------
+# Philox
+# ---------------------------------------------------------------------------
+
+def test_philox_bit_exact():
+    drt = _drt()
+    rng = np.random.default_rng(1)
+    n = 1 << 16
+    ctr = rng.integers(0, 2 ** 32, (n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, (n, 2), dtype=np.uint64).astype(np.uint32)
+    out = drt.philox(torch.from_numpy(ctr.view(np.int32)).cuda(),
+                     torch.from_numpy(key.view(np.int32)).cuda())
+    got = out.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got, oracle.philox(ctr, key))
+
+
+# ---------------------------------------------------------------------------
+# traversal: hit ids bit-exact vs brute force
+# ---------------------------------------------------------------------------
+
+def _rays_for(sc, n, seed):
+    if sc.cameras:
+        cam = sc.cameras[0]
+        rng = np.random.default_rng(seed)
+        px, py = rng.uniform(0, cam.width, n), rng.uniform(0, cam.height, n)
+        d = oracle.camera_dirs(cam, px, py).astype(np.float32)
+        o = np.tile(np.array(cam.origin, np.float32), (n, 1))
+        # secondary rays from points on the first hits, random directions
+        return o, d
+    return scenes.random_rays(n, seed=seed)
+
+
+@pytest.mark.parametrize("name", ["soup", "cornell", "zoo", "grid"])
+def test_trace_closest_and_any_vs_brute_force(name):
+    drt = _drt()
+    sc = {"soup": lambda: scenes.triangle_soup(2000, seed=3),
+          "cornell": scenes.cornell,
+          "zoo": scenes.bsdf_zoo,
+          "grid": lambda: scenes.procedural(n_grid=64, n_spheres=20, sphere_res=(16, 8),
+                                            env_size=(32, 16), n_lights=2, tex_size=16,
+                                            width=32, height=32)}[name]()
+    o, d = _rays_for(sc, 4096, seed=5)
+    rng = np.random.default_rng(9)
+    # add random interior rays
+    lo, hi = sc.positions.min(0), sc.positions.max(0)
+    o2 = rng.uniform(lo, hi, (4096, 3)).astype(np.float32)
+    d2 = rng.normal(size=(4096, 3))
+    d2 = (d2 / np.linalg.norm(d2, axis=1, keepdims=True)).astype(np.float32)
+    o = np.concatenate([o, o2])
+    d = np.concatenate([d, d2])
+    d = (d / np.linalg.norm(d.astype(np.float64), axis=1, keepdims=True)).astype(np.float32)
+    n = o.shape[0]
+    tmax = np.where(np.arange(n) % 3 == 0, 0.7, np.inf).astype(np.float32)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3], rays[:, 4:7], rays[:, 7] = o, d, tmax
+    gs = drt.Scene(sc)
+    print(name, gs.info, flush=True)
+    hits = drt.trace(gs, torch.from_numpy(rays).cuda(), 0).cpu().numpy()
+    prim_g = hits[:, 3].copy().view(np.int32)
+    orc = oracle.OracleScene(sc)
+    prim_o, t_o, _, amb = orc.trace(o.astype(np.float64), d.astype(np.float64), tmax=tmax.astype(np.float64))
+    ok = ~amb
+    print(f"{name}: ambiguous {amb.sum()} of {n}", flush=True)
+    assert ok.mean() > 0.97
+    np.testing.assert_array_equal(prim_g[ok], prim_o[ok])
+    hit = ok & (prim_o >= 0)
+    np.testing.assert_allclose(hits[hit, 0], t_o[hit], rtol=2e-5, atol=1e-6)
+    anyh = drt.trace(gs, torch.from_numpy(rays).cuda(), 1).cpu().numpy()[:, 3].copy().view(np.int32)
+    prim_a, _, _, amb_a = orc.trace(o.astype(np.float64), d.astype(np.float64),
+                                    tmax=tmax.astype(np.float64), any_hit=True)
+    ok = ~amb_a
+    np.testing.assert_array_equal(anyh[ok], prim_a[ok])
+
+
+# ---------------------------------------------------------------------------
+# primal images
+# ---------------------------------------------------------------------------
+
+FWD_CASES = {
+    "cornell_c1": (lambda: scenes.cornell(), dict(spp=4, max_depth=3)),
+    "cornell_tex_conductor": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64)),
+                              dict(spp=4, max_depth=4)),
+    "furnace_sphere": (lambda: scenes.furnace_sphere(), dict(spp=4, max_depth=3)),
+    "furnace_cube_nonee": (lambda: scenes.furnace_cube(), dict(spp=2, max_depth=5, flags=1)),
+    "lit_plane": (lambda: scenes.lit_plane(), dict(spp=2, max_depth=3)),
+    "zoo_rr": (lambda: scenes.bsdf_zoo(width=64, height=64), dict(spp=4, max_depth=6, rr_depth=3)),
+}
+
+
+@pytest.mark.parametrize("case", list(FWD_CASES))
+def test_forward_image_parity(case):
+    drt = _drt()
+    make, kw = FWD_CASES[case]
+    sc = make()
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    rr = kw.get("rr_depth", drt.NO_RR)
+    img = drt.render_forward(gs, tex, rough, sc.cameras, kw["spp"], kw["max_depth"], rr, seed=1,
+                             flags=kw.get("flags", 0)).cpu().numpy()
+    ref = oracle.OracleScene(sc).render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
+                                        flags=kw.get("flags", 0), seed=1)
+    check_image(img, ref, case)
+
+
+def test_forward_multi_camera_parity():
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64),
+                        cameras=scenes.ring_cameras(3, 40, 24))
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    img = drt.render_forward(gs, tex, rough, sc.cameras, 3, 3, seed=7).cpu().numpy()
+    ref = oracle.OracleScene(sc).render(spp=3, max_depth=3, seed=7)
+    check_image(img, ref, "ring3")
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+ADJ_CASES = {
+    "cornell_c1": (lambda: scenes.cornell(texture=scenes.random_texture(64)), dict(spp=4, max_depth=3)),
+    "cornell_conductor": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64)),
+                          dict(spp=4, max_depth=3)),
+    "zoo": (lambda: scenes.bsdf_zoo(width=48, height=48), dict(spp=4, max_depth=6, rr_depth=3)),
+}
+
+
+@pytest.mark.parametrize("case", list(ADJ_CASES))
+def test_adjoint_parity(case):
+    drt = _drt()
+    make, kw = ADJ_CASES[case]
+    sc = make()
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    c = sc.cameras[0]
+    adj = np.random.default_rng(5).normal(size=(1, c.height, c.width, 3)).astype(np.float32)
+    rr = kw.get("rr_depth", drt.NO_RR)
+    stats = drt.new_stats()
+    gt, gr = drt.render_adjoint(gs, tex, rough, sc.cameras, torch.from_numpy(adj).cuda(), kw["spp"],
+                                kw["max_depth"], rr, seed=2, stats=stats)
+    st = drt.read_stats(stats)
+    print(case, st, flush=True)
+    ot, orr = oracle.OracleScene(sc).adjoint(adj.astype(np.float64), spp=kw["spp"],
+                                             max_depth=kw["max_depth"], rr_depth=rr, seed=2)
+    for i, (g, o) in enumerate(zip(gt, ot)):
+        check_grad(g.cpu().numpy(), o, f"{case} texture {i}")
+    if len(sc.roughness):
+        check_grad(gr.cpu().numpy(), orr, f"{case} roughness")
+    # replay residual: the subtraction recovers the full path radiance
+    assert st["lrem_max"] <= 1e-4 * max(1.0, float(np.abs(adj).max()) * 100), st
+
+
+def test_adjoint_matches_central_differences_on_gpu():
+    """Texel gradients of <adj, I> vs central differences of the GPU primal
+    with common random numbers (the adjoint's seed), h = 1e-2."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64))
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    c = sc.cameras[0]
+    adj = np.random.default_rng(6).normal(size=(1, c.height, c.width, 3))
+    gt, _ = drt.render_adjoint(gs, tex, rough, sc.cameras,
+                               torch.from_numpy(adj.astype(np.float32)).cuda(), 4, 3, seed=2)
+    g = gt[0].cpu().numpy().reshape(-1).astype(np.float64)
+    rng = np.random.default_rng(10)
+    cand = np.flatnonzero(np.abs(g) > 1e-2 * np.abs(g).max())
+    pick = rng.choice(cand, 32, replace=False)
+    h = 1e-2
+    fds = []
+    for k in pick:
+        tp = tex[0].clone().reshape(-1)
+        tm = tex[0].clone().reshape(-1)
+        tp[k] += h
+        tm[k] -= h
+        step = (tp[k].item() - tm[k].item()) / 2
+        Ip = drt.render_forward(gs, [tp.reshape(tex[0].shape)], rough, sc.cameras, 4, 3, seed=2)
+        Im = drt.render_forward(gs, [tm.reshape(tex[0].shape)], rough, sc.cameras, 4, 3, seed=2)
+        dI = Ip.cpu().numpy().astype(np.float64) - Im.cpu().numpy().astype(np.float64)
+        fds.append((adj * dI).sum() / (2 * step))
+    fds = np.array(fds)
+    scale = np.abs(fds).max()
+    err = np.abs(g[pick] - fds)
+    print("fd max rel err", (err / np.maximum(np.abs(fds), 1e-3 * scale)).max(), flush=True)
+    assert np.all(err <= 2e-2 * np.maximum(np.abs(fds), 1e-3 * scale))
+
+
+# ---------------------------------------------------------------------------
+# loss and Adam
+# ---------------------------------------------------------------------------
+
+def test_loss_and_adam_vs_oracle():
+    drt = _drt()
+    rng = np.random.default_rng(2)
+    n = 3 * 1000 * 37 + 5    # several blocks and a ragged tail
+    img = rng.random(n).astype(np.float32)
+    tgt = rng.random(n).astype(np.float32)
+    loss, adj = drt.loss_l2(torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda())
+    lo, ao = oracle.loss_l2(img.astype(np.float64), tgt.astype(np.float64))
+    assert abs(loss.item() - lo) <= 1e-6 * lo
+    np.testing.assert_allclose(adj.cpu().numpy(), ao, rtol=1e-6, atol=1e-12)
+    p = rng.random(n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    pt, gt = torch.from_numpy(p).cuda(), torch.from_numpy(g).cuda()
+    m, v = torch.zeros_like(pt), torch.zeros_like(pt)
+    po, mo, vo = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in (1, 2, 3):
+        drt.adam_step(pt, gt, m, v, t, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8, lo=0.0, hi=1.0)
+        oracle.adam(po, g.astype(np.float64), mo, vo, 1e-2, 0.9, 0.99, 1e-8, t, 0.0, 1.0)
+    np.testing.assert_allclose(pt.cpu().numpy(), po, rtol=0, atol=2e-6)
+
+
+def test_empty_and_degenerate_inputs():
+    drt = _drt()
+    sc = scenes.triangle_soup(1, seed=1)
+    gs = drt.Scene(sc)
+    # zero rays is a no-op; a one-triangle scene is traversable
+    drt.trace(gs, torch.zeros((0, 8), dtype=torch.float32, device="cuda"), 0)
+    o, d = scenes.random_rays(64, seed=2)
+    rays = np.zeros((64, 8), np.float32)
+    rays[:, 0:3], rays[:, 4:7], rays[:, 7] = o, d, np.inf
+    hits = drt.trace(gs, torch.from_numpy(rays).cuda(), 0).cpu().numpy()
+    prim_o, _, _, amb = oracle.OracleScene(sc).trace(o.astype(np.float64), d.astype(np.float64))
+    np.testing.assert_array_equal(hits[~amb, 3].copy().view(np.int32), prim_o[~amb])
+    # a 1x1 image, 1 spp, depth 1 (camera ray only)
+    sc2 = scenes.cornell(width=1, height=1)
+    gs2 = drt.Scene(sc2)
+    tex, _ = _params(sc2)
+    img = drt.render_forward(gs2, tex, None, sc2.cameras, 1, 1, seed=3).cpu().numpy()
+    ref = oracle.OracleScene(sc2).render(spp=1, max_depth=1, seed=3)
+    check_image(img, ref, "1x1")
+    # zero adjoint: no gradient, nothing traced
+    z = torch.zeros((1, 1, 1, 3), dtype=torch.float32, device="cuda")
+    gt, _ = drt.render_adjoint(gs2, tex, None, sc2.cameras, z, 1, 3)
+    assert float(gt[0].abs().sum()) == 0.0
+    # invalid arguments are rejected before any launch
+    with pytest.raises(drt.DrtError):
+        drt.render_forward(gs2, tex, None, sc2.cameras, 0, 3)
