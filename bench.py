@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-aux", action="store_true", help="skip the 1M-triangle primal figure")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -56,6 +58,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.calib_copy:
+        # a plain copy of known size: 256 MiB read + 256 MiB written
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     R, SPP, D = args.res, args.spp, 3
     sc = scenes.cornell(tex_size=args.tex, width=R, height=R, conductor=True)
     gs = drt.Scene(sc)

@@ -134,9 +134,10 @@ class OracleScene:
     # -- queries -------------------------------------------------------------
     def render(self, cams=None, spp=4, max_depth=3, rr_depth=1 << 30, flags=0, seed=1,
                pixel_ids: Optional[np.ndarray] = None, textures=None, roughness=None,
-               threads: Optional[int] = None) -> np.ndarray:
+               threads: Optional[int] = None, ambiguity: bool = False):
         """Pixel estimates.  Full image [n_cams,H,W,3] if pixel_ids is None,
-        else [len(pixel_ids),3]."""
+        else [len(pixel_ids),3].  With ambiguity=True also returns, per pixel,
+        the number of samples with a discrete decision within FP32 reach."""
         cams = self.sc.cameras if cams is None else cams
         ca = cam_array(cams)
         W, H = cams[0].width, cams[0].height
@@ -145,14 +146,17 @@ class OracleScene:
             pixel_ids = np.arange(len(cams) * W * H, dtype=np.int64)
         pixel_ids = np.ascontiguousarray(pixel_ids, np.int64)
         out = np.zeros((pixel_ids.size, 3), np.float64)
+        amb = np.zeros(pixel_ids.size, np.int32) if ambiguity else None
         texs, tptr, rough = self._params(textures, roughness)
         lib().oracle_render(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)), _c_int(spp),
                             _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
                             _c_i64(pixel_ids.size), _p(pixel_ids),
-                            _c_int(threads or n_threads_default()), _p(out))
+                            _c_int(threads or n_threads_default()), _p(out), _p(amb))
         if full:
-            return out.reshape(len(cams), H, W, 3)
-        return out
+            out = out.reshape(len(cams), H, W, 3)
+            if ambiguity:
+                amb = amb.reshape(len(cams), H, W)
+        return (out, amb) if ambiguity else out
 
     def radiance(self, o, d, spp=16, max_depth=3, rr_depth=1 << 30, flags=0, seed=1,
                  textures=None, roughness=None, threads=None) -> np.ndarray:

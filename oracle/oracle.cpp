@@ -165,6 +165,30 @@ struct Params {
 };
 
 // ---------------------------------------------------------------------------
+// Decisions within FP32 reach.  A float32 implementation of the same
+// estimator follows the same path as this double-precision one except where
+// a discrete decision (texel index, environment cell, CDF bin, Russian
+// roulette, lobe choice, which triangle a ray hits or grazes) is taken within
+// float32 rounding of its threshold.  When a caller asks, such samples are
+// flagged so comparisons can set them aside (and count them).
+// ---------------------------------------------------------------------------
+static thread_local bool* t_amb = nullptr;
+static const double kTolUV = 3e-7;     // texture coordinate (uv units) to a texel edge
+static const double kTolU = 2e-6;      // uniform vs a computed threshold
+static const double kTolAngle = 2e-6;  // direction angle (radians) to an environment cell edge
+static const double kTolBary = 2e-5;   // ray to a triangle edge (normalised barycentric)
+static const double kTolT = 1e-6;      // relative distance between two hits
+static inline void flag_if(bool c) {
+  if (c && t_amb) *t_amb = true;
+}
+// distance of x to the nearest integer in [1, n-1] (the interior cell edges)
+static inline double edge_dist(double x, int n) {
+  double k = std::floor(x + 0.5);
+  if (k < 1 || k > n - 1) return 1e300;
+  return std::fabs(x - k);
+}
+
+// ---------------------------------------------------------------------------
 // Intersection: watertight ray/triangle test of Woop, Benthin and Wald (JCGT
 // 2013) evaluated in double precision, no culling, t in (tmin, tmax).  The
 // closest hit is the minimum over ALL triangles (brute force); ties go to the
@@ -220,6 +244,30 @@ struct Hit {
   double b[3] = {0, 0, 0};
 };
 
+// Flag the ray if any triangle's edge passes within kTolBary of it in front
+// of t_lim, or another triangle is hit within kTolT of t_hit.
+static void scan_edges(const Scene& s, V3 o, V3 d, double tmin, double t_lim, int hit_prim,
+                       bool skip_null) {
+  for (int j = 0; j < s.n_tris(); ++j) {
+    if (skip_null && s.mats[s.tri_mat[j]].type == 0) continue;
+    V3 p0 = s.pos[s.idx[3 * j]], p1 = s.pos[s.idx[3 * j + 1]], p2 = s.pos[s.idx[3 * j + 2]];
+    V3 e1 = p1 - p0, e2 = p2 - p0, pv = cross(d, e2);
+    double det = dot(e1, pv);
+    if (std::fabs(det) <= 1e-14 * length(e1) * length(e2)) continue;
+    V3 tv = o - p0;
+    double bu = dot(tv, pv) / det;
+    V3 qv = cross(tv, e1);
+    double bv = dot(d, qv) / det;
+    double tt = dot(e2, qv) / det;
+    double tol_t = kTolT * std::max(1.0, std::fabs(tt));
+    if (!(tt > tmin - tol_t && tt < t_lim + tol_t)) continue;
+    double bmin = std::min(std::min(bu, bv), 1.0 - bu - bv);
+    if (std::fabs(bmin) < kTolBary) { flag_if(true); return; }
+    if (bmin > 0 && j != hit_prim && std::fabs(tt - t_lim) <= tol_t) { flag_if(true); return; }
+    if (bmin > 0 && std::fabs(tt - tmin) <= tol_t) { flag_if(true); return; }
+  }
+}
+
 static Hit closest_hit(const Scene& s, V3 o, V3 d, double tmin, double tmax) {
   RayPre rp = ray_pre(d);
   Hit h;
@@ -232,11 +280,13 @@ static Hit closest_hit(const Scene& s, V3 o, V3 d, double tmin, double tmax) {
     }
   }
   // ties: the strict "t < best" above keeps the first (lowest id) of equal t
+  if (t_amb) scan_edges(s, o, d, tmin, h.prim >= 0 ? h.t : tmax, h.prim, false);
   return h;
 }
 
 // Any hit on a triangle whose material is not the pass-through (null) BSDF.
 static bool occluded(const Scene& s, V3 o, V3 d, double tmax) {
+  if (t_amb) scan_edges(s, o, d, 0.0, tmax, -1, true);
   RayPre rp = ray_pre(d);
   for (int i = 0; i < s.n_tris(); ++i) {
     if (s.mats[s.tri_mat[i]].type == BSDF_NULL) continue;
@@ -488,6 +538,7 @@ static Sample bsdf_sample(const Shading& sh, V3 wi, double u1, double u2, double
     case BSDF_PLASTIC: {
       if (wi.z <= 0) return s;
       double ps = std::min(std::max(fresnel_dielectric(wi.z, m.eta), 0.1), 0.9);
+      flag_if(std::fabs(ulobe - ps) < kTolU);
       if (ulobe < ps) {
         V3 mm = ggx_sample_m(a, u1, u2);
         if (dot(wi, mm) <= 0) return s;
@@ -506,6 +557,7 @@ static Sample bsdf_sample(const Shading& sh, V3 wi, double u1, double u2, double
       double c = dot(wi, mm);
       if (c <= 0) return s;
       double F = fresnel_dielectric(c, eta);
+      flag_if(std::fabs(ulobe - F) < kTolU);
       if (ulobe < F) {
         s.wo = reflect_about(wi, mm);
         if (s.wo.z * sg <= 0) return s;
@@ -539,6 +591,13 @@ static void env_dir_to_cell(const Scene& s, V3 d, int* row, int* col, double* si
   if (ph < 0) ph += 2.0 * kPi;
   int c = (int)std::floor(ph / (2.0 * kPi) * s.env_w);
   int r = (int)std::floor(th / kPi * s.env_h);
+  if (t_amb) {
+    double st = std::sin(th);
+    flag_if(edge_dist(th / kPi * s.env_h, s.env_h) * kPi / s.env_h < kTolAngle);
+    double dph = std::min(std::fabs(ph - c * 2.0 * kPi / s.env_w),
+                          std::fabs(ph - (c + 1) * 2.0 * kPi / s.env_w));
+    flag_if(dph * std::max(st, 1e-12) < kTolAngle);
+  }
   *col = std::min(std::max(c, 0), s.env_w - 1);
   *row = std::min(std::max(r, 0), s.env_h - 1);
   *sin_t = std::sin(th);
@@ -576,9 +635,11 @@ static bool env_sample(const Scene& s, double u1, double u2, V3* d) {
   if (s.env_total <= 0) return false;
   int r = cdf_find(s.env_cdf_row.data(), s.env_h, u1);
   double r0 = s.env_cdf_row[r], r1 = s.env_cdf_row[r + 1];
+  flag_if(std::fabs(u1 - r0) < kTolU || std::fabs(u1 - r1) < kTolU);
   double v = (r + (u1 - r0) / (r1 - r0)) / s.env_h;
   const double* cc = &s.env_cdf_col[(size_t)r * (s.env_w + 1)];
   int c = cdf_find(cc, s.env_w, u2);
+  flag_if(std::fabs(u2 - cc[c]) < kTolU || std::fabs(u2 - cc[c + 1]) < kTolU);
   double u = (c + (u2 - cc[c]) / (cc[c + 1] - cc[c])) / s.env_w;
   double th = v * kPi, ph = u * 2.0 * kPi;
   *d = V3(std::sin(th) * std::cos(ph), std::cos(th), std::sin(th) * std::sin(ph));
@@ -683,6 +744,10 @@ static ShadeCtx fetch_shading(const Scene& s, const Params& P, int mat, double u
     int x = (int)std::min(fu, (double)(W - 1));
     int y = (int)std::min(fv, (double)(H - 1));
     int64_t texel = (int64_t)y * W + x;
+    if (t_amb) {
+      flag_if(edge_dist(std::max(u, 0.0) * W, W) / W < kTolUV);
+      flag_if(edge_dist(std::max(v, 0.0) * H, H) / H < kTolUV);
+    }
     const float* t = P.tex[m.texture] + 3 * texel;
     c.sh.albedo = RGB(t[0], t[1], t[2]);
     c.k_tex = texel_key(m.texture, texel);
@@ -881,6 +946,7 @@ static RGB trace_sample(const Scene& s, const Params& P, const Opts& opt, const 
     d = wo;
     if (k >= opt.rr_depth) {
       double q = std::min(std::max(beta[0], std::max(beta[1], beta[2])), 0.95);
+      flag_if(std::fabs(u01(r1[2]) - q) < kTolU);
       if (u01(r1[2]) >= q) break;
       beta = beta * (1.0 / q);
       for (auto& pp : tbeta.e) pp.second = pp.second * (1.0 / q);
@@ -1101,7 +1167,7 @@ void oracle_trace(void* h, int64_t n, const double* o, const double* d, const do
 void oracle_render(void* h, const float* const* textures, const float* roughness,
                    const double* cams, int n_cams, int spp, int max_depth, int rr_depth,
                    uint32_t flags, uint64_t seed, int64_t n_pix, const int64_t* pixel_ids,
-                   int n_threads, double* out) {
+                   int n_threads, double* out, int* ambiguous) {
   const Scene& s = *(Scene*)h;
   Params P{textures, roughness};
   Opts opt{spp, max_depth, rr_depth, flags, seed};
@@ -1113,14 +1179,20 @@ void oracle_render(void* h, const float* const* textures, const float* roughness
     int cam = (int)(pid / ((int64_t)W * H));
     int y = (int)((pid / W) % H), x = (int)(pid % W);
     RGB acc;
+    int n_amb = 0;
     for (int sidx = 0; sidx < spp; ++sidx) {
       uint64_t g = (uint64_t)pid * spp + sidx;
       Stream st = make_stream(seed, g);
       V3 o, d;
+      bool amb = false;
+      t_amb = ambiguous ? &amb : nullptr;
       camera_ray(cs[cam], st, x, y, &o, &d);
       acc = acc + trace_sample(s, P, opt, st, o, d, nullptr, nullptr);
+      t_amb = nullptr;
+      n_amb += amb ? 1 : 0;
     }
     for (int c = 0; c < 3; ++c) out[3 * i + c] = acc[c] / spp;
+    if (ambiguous) ambiguous[i] = n_amb;
   });
 }
 

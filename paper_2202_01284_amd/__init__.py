@@ -20,7 +20,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdrt.so")
+# DRT_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("DRT_LIBRARY") or os.path.join(_HERE, "libdrt.so")
 
 MAX_TEXTURES = 8
 MAX_CAMERAS = 32

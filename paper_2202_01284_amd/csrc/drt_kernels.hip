@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "drt_internal.h"
 
 namespace drt {
@@ -43,7 +45,12 @@ DEV float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 DEV f3 cross(f3 a, f3 b) {
   return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
-DEV f3 normalize(f3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+DEV f3 normalize(f3 a) { return a * __builtin_amdgcn_rsqf(dot(a, a)); }
+// sin and cos of 2 pi u for u in [0, 1): the hardware takes revolutions
+DEV void sincos_2pi(float u, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(u);
+  *c = __builtin_amdgcn_cosf(u);
+}
 DEV bool nonzero(f3 a) { return a.x != 0.f || a.y != 0.f || a.z != 0.f; }
 DEV float maxc(f3 a) { return fmaxf(a.x, fmaxf(a.y, a.z)); }
 DEV float comp(f3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
@@ -55,8 +62,10 @@ DEV float comp(f3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32 -> 64-bit product gives both halves
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     uint32_t n0 = hi1 ^ c1 ^ k0;
     uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -188,14 +197,16 @@ DEV DTri load_tri(const DScene& s, int i) {
   return t;
 }
 
-// ANY = false: closest hit in (tmin, tmax), ties to the lowest original id.
-// ANY = true: true iff a non-null triangle is hit in (tmin, tmax).
-template <bool ANY>
-DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, Hit& h, int* stk,
-                  Counters& cnt) {
+// One traversal loop for both ray kinds, so the lanes of a wave traverse
+// together whatever ray each carries.
+// any = false: closest hit in (tmin, tmax), ties to the lowest original id.
+// any = true: true iff a non-null triangle is hit in (tmin, tmax).
+DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool any, Hit& h,
+                  int* stk, Counters& cnt) {
   float tbest = tmax;
   h.tri = -1;
   h.prim = 0x7fffffff;
+  bool found = false;
   int node = 0, sp = 0;
   for (;;) {
     const float4* np = reinterpret_cast<const float4*>(s.nodes + node);
@@ -205,35 +216,36 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, Hit&
     float tn0, tn1;
     bool h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, tn0);
     bool h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, tn1);
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      bool hs = side == 0 ? h0 : h1;
-      int first = side == 0 ? q.x : q.y;
-      int count = side == 0 ? q.z : q.w;
-      if (hs && count > 0) {
-        for (int i = first; i < first + count; ++i) {
-          DTri T = load_tri(s, i);
-          cnt.tris++;
-          if (ANY && (T.flags & 1)) continue;
-          float t, b1, b2;
-          if (!tri_test(r, T, tmin, tbest, t, b1, b2)) continue;
-          if (ANY) {
-            if (t < tmax) return true;
-            continue;
-          }
-          // closest: strictly nearer, or an exact tie with a lower original id
-          if (t < tbest || (h.tri >= 0 && T.prim < h.prim)) {
-            tbest = t;
-            h.t = t;
-            h.b1 = b1;
-            h.b2 = b2;
-            h.tri = i;
-            h.prim = T.prim;
-          }
+    // leaf children: test their triangles now (one loop over both ranges)
+    int l0 = (h0 && q.z > 0) ? q.z : 0;
+    int l1 = (h1 && q.w > 0) ? q.w : 0;
+    for (int j = 0; j < l0 + l1; ++j) {
+      int i = j < l0 ? q.x + j : q.y + (j - l0);
+      DTri T = load_tri(s, i);
+      cnt.tris++;
+      if (any && (T.flags & 1)) continue;
+      float t, b1, b2;
+      if (!tri_test(r, T, tmin, tbest, t, b1, b2)) continue;
+      if (any) {
+        if (t < tmax) {
+          found = true;
+          break;
         }
-        if (side == 0) h0 = false; else h1 = false;
+        continue;
+      }
+      // closest: strictly nearer, or an exact tie with a lower original id
+      if (t < tbest || (h.tri >= 0 && T.prim < h.prim)) {
+        tbest = t;
+        h.t = t;
+        h.b1 = b1;
+        h.b2 = b2;
+        h.tri = i;
+        h.prim = T.prim;
       }
     }
+    if (found) break;
+    h0 = h0 && q.z == 0;
+    h1 = h1 && q.w == 0;
     if (h0 && h1) {
       bool near0 = tn0 <= tn1;
       stk[sp * kBlock] = near0 ? q.y : q.x;
@@ -249,7 +261,7 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, Hit&
       node = stk[sp * kBlock];
     }
   }
-  return ANY ? false : h.tri >= 0;
+  return any ? found : h.tri >= 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -280,7 +292,7 @@ DEV f3 spawn(const DScene& s, f3 p, f3 n_g, f3 d) {
 // cosine-weighted hemisphere: phi = 2 pi u_a, sin^2(theta) = u_b
 DEV f3 cosine_hemisphere(float ua, float ub) {
   float sp, cp;
-  sincospif(2.0f * ua, &sp, &cp);
+  sincos_2pi(ua, &sp, &cp);
   float r = sqrtf(ub);
   return mk(cp * r, sp * r, sqrtf(1.0f - ub));
 }
@@ -316,7 +328,7 @@ DEV f3 ggx_sample_m(float a, float u1, float u2) {
   float ct = sqrtf(cos2);
   float st = sqrtf(fmaxf(0.f, 1.0f - cos2));
   float sp, cp;
-  sincospif(2.0f * u2, &sp, &cp);
+  sincos_2pi(u2, &sp, &cp);
   return mk(st * cp, st * sp, ct);
 }
 // exact unpolarised dielectric Fresnel; cos_i >= 0 on the incident side,
@@ -557,8 +569,8 @@ DEV bool env_sample(const DScene& s, float u1, float u2, f3& d) {
   int c = cdf_find(cc, s.env_w, u2);
   float u = ((float)c + (u2 - cc[c]) / (cc[c + 1] - cc[c])) / (float)s.env_w;
   float st, ct, sp, cp;
-  sincospif(v, &st, &ct);
-  sincospif(2.0f * u, &sp, &cp);
+  sincos_2pi(0.5f * v, &st, &ct);
+  sincos_2pi(u, &sp, &cp);
   d = mk(st * cp, ct, st * sp);
   return true;
 }
@@ -598,195 +610,6 @@ DEV void scatter_rough(const Sink& k, int slot, float g, Counters& cnt) {
   else if (k.rough_global) { atomicAdd(k.rough_global + slot, g); cnt.scatter++; }
 }
 
-// ---------------------------------------------------------------------------
-// The path: one sample.  REPLAY = false returns the sample radiance L.
-// REPLAY = true re-traces the same sample with the same random numbers,
-// subtracts each collected term from `Lrem` (initialised to L) and scatters
-// dL . (d NEE_k + Lrem (d f_k)/f_k) at every scattering vertex; it returns
-// the final Lrem, which is zero up to rounding.
-// ---------------------------------------------------------------------------
-template <bool REPLAY>
-DEV f3 trace_path(const DScene& s, const DParams& P, const DRender& R, const LdsTables& tab,
-                  uint32_t g_lo, uint32_t g_hi, f3 o, f3 d, int* stk, Counters& cnt, f3 Lrem,
-                  f3 dL, const Sink& sink) {
-  f3 L = mk(0, 0, 0), beta = mk(1, 1, 1);
-  float prev_pdf = 0.f;  // 0: the next emitter hit takes no MIS weight
-  f3 prev_p = o;
-  const int n_em = s.n_ems;
-  const float p_sel = n_em > 0 ? 1.0f / (float)n_em : 0.f;
-  const bool no_nee = (R.flags & DRT_FLAG_NO_NEE) != 0;
-  cnt.samples++;
-  for (int k = 1; k <= R.max_depth; ++k) {
-    RayPre rp = ray_pre(o, d);
-    Hit h;
-    cnt.rays++;
-    bool hit = traverse<false>(s, rp, 0.f, INFINITY, h, stk, cnt);
-    if (!hit) {
-      if (s.env_emitter >= 0) {
-        int row, col;
-        float st;
-        env_cell(s, d, row, col, st);
-        float w = 1.0f;
-        if (!(prev_pdf == 0.f || no_nee)) w = power_heuristic(prev_pdf, p_sel * env_pdf(s, row, col, st));
-        f3 c = beta * env_lookup(s, row, col) * w;
-        L = L + c;
-        if (REPLAY) Lrem = Lrem - c;
-      }
-      break;
-    }
-    DTri T = load_tri(s, h.tri);
-    f3 p0 = mk(T.p0x, T.p0y, T.p0z), p1 = mk(T.p1x, T.p1y, T.p1z), p2 = mk(T.p2x, T.p2y, T.p2z);
-    float b0 = 1.0f - h.b1 - h.b2;
-    f3 p = p0 * b0 + p1 * h.b1 + p2 * h.b2;
-    f3 n_g = normalize(cross(p1 - p0, p2 - p0));
-    const float4* shp = reinterpret_cast<const float4*>(s.shade + T.prim);
-    float4 sa = shp[0], sb = shp[1];
-    int mat_id = __float_as_int(sb.z), em_id = __float_as_int(sb.w);
-    float cos_y = -dot(d, n_g);
-    if (em_id >= 0 && cos_y > 0.f) {
-      const DEmitter& E = s.ems[em_id];
-      float w = 1.0f;
-      if (!(prev_pdf == 0.f || no_nee)) {
-        f3 dv = p - prev_p;
-        w = power_heuristic(prev_pdf, p_sel * dot(dv, dv) / (E.area * cos_y));
-      }
-      f3 c = beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
-      L = L + c;
-      if (REPLAY) Lrem = Lrem - c;
-    }
-    if (k == R.max_depth) break;
-    uint4 r0 = philox(g_lo, g_hi, (uint32_t)(k - 1), 0u, R.key0, R.key1);
-    uint4 r1 = philox(g_lo, g_hi, (uint32_t)(k - 1), 1u, R.key0, R.key1);
-    const DMaterial& M = s.mats[mat_id];
-    int type = M.type;
-    if (type == DRT_BSDF_NULL || (type == DRT_BSDF_MASK && u01(r1.w) >= M.opacity)) {
-      if (type == DRT_BSDF_MASK) prev_pdf = 0.f;
-      o = spawn(s, p, n_g, d);
-      continue;
-    }
-    cnt.verts++;
-    // hoisted out of the switch: frame, albedo (texture or constant), roughness
-    Frame fr = make_frame(n_g);
-    f3 wi = to_local(fr, -d);
-    Shade sh;
-    sh.type = type;
-    sh.albedo = mk(M.albedo[0], M.albedo[1], M.albedo[2]);
-    sh.f0 = mk(M.f0[0], M.f0[1], M.f0[2]);
-    sh.alpha = M.alpha;
-    sh.eta = M.eta;
-    sh.opacity = M.opacity;
-    int tex = M.texture, texel = 0;
-    if (tex >= 0) {
-      float u = sa.x * b0 + sa.z * h.b1 + sb.x * h.b2;
-      float v = sa.y * b0 + sa.w * h.b1 + sb.y * h.b2;
-      int W = tab.tw[tex], H = tab.th[tex];
-      int x = (int)fminf(floorf(fmaxf(u, 0.f) * (float)W), (float)(W - 1));
-      int y = (int)fminf(floorf(fmaxf(v, 0.f) * (float)H), (float)(H - 1));
-      texel = y * W + x;
-      const float* tp = tab.tex[tex] + 3 * (size_t)texel;
-      sh.albedo = mk(tp[0], tp[1], tp[2]);
-    }
-    int rslot = M.rough_slot;
-    if (rslot >= 0) sh.alpha = P.rough[rslot];
-    // next-event estimation
-    if (!no_nee && n_em > 0) {
-      const DEmitter& E = s.ems[pick(r0.x, (uint32_t)n_em)];
-      float lu = u01(r0.y), lv = u01(r0.z);
-      bool valid = false, delta = false, finite = false;
-      f3 wl = mk(0, 0, 1), y = mk(0, 0, 0), Le = mk(0, 0, 0);
-      float pdf_l = 0.f;
-      if (E.type == DRT_EMITTER_AREA) {
-        y = mk(E.p0[0], E.p0[1], E.p0[2]) + mk(E.e1[0], E.e1[1], E.e1[2]) * lu +
-            mk(E.e2[0], E.e2[1], E.e2[2]) * lv;
-        f3 dv = y - p;
-        float dist2 = dot(dv, dv), dist = sqrtf(dist2);
-        wl = dv * (1.0f / dist);
-        float cy = -dot(wl, mk(E.n[0], E.n[1], E.n[2]));
-        if (cy > 0.f) {
-          pdf_l = dist2 / (E.area * cy);
-          Le = mk(E.radiance[0], E.radiance[1], E.radiance[2]);
-          finite = true;
-          valid = true;
-        }
-      } else if (E.type == DRT_EMITTER_ENV) {
-        if (env_sample(s, lu, lv, wl)) {
-          int row, col;
-          float st;
-          env_cell(s, wl, row, col, st);
-          pdf_l = env_pdf(s, row, col, st);
-          if (pdf_l > 0.f) {
-            Le = env_lookup(s, row, col);
-            valid = true;
-          }
-        }
-      } else {
-        wl = mk(E.p0[0], E.p0[1], E.p0[2]);
-        Le = mk(E.radiance[0], E.radiance[1], E.radiance[2]);
-        pdf_l = 1.0f;
-        delta = true;
-        valid = true;
-      }
-      if (valid) {
-        BEval fe = bsdf_eval<REPLAY>(sh, wi, to_local(fr, wl));
-        if (nonzero(fe.f)) {
-          f3 so = spawn(s, p, n_g, wl), sd = wl;
-          float tmax = INFINITY;
-          if (finite) {
-            f3 dv = y - so;
-            float dl = sqrtf(dot(dv, dv));
-            sd = dv * (1.0f / dl);
-            tmax = (1.0f - 1e-4f) * dl;
-          }
-          RayPre sr = ray_pre(so, sd);
-          Hit sh_hit;
-          cnt.shadow++;
-          if (!traverse<true>(s, sr, 0.f, tmax, sh_hit, stk, cnt)) {
-            float w = delta ? 1.0f : power_heuristic(p_sel * pdf_l, fe.pdf);
-            f3 coef = beta * Le * (w / (p_sel * pdf_l));
-            f3 c = coef * fe.f;
-            L = L + c;
-            if (REPLAY) {
-              Lrem = Lrem - c;
-              if (tex >= 0) scatter_tex(sink, tex, texel, dL * coef * fe.dalb, cnt);
-              if (rslot >= 0) {
-                f3 g = dL * coef * fe.dalpha;
-                scatter_rough(sink, rslot, g.x + g.y + g.z, cnt);
-              }
-            }
-          }
-        }
-      }
-    }
-    // BSDF sampling
-    f3 wo;
-    BEval be;
-    if (!bsdf_sample<REPLAY>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be)) break;
-    if (REPLAY) {
-      // radiance arriving over wo = everything not yet subtracted
-      f3 q = mk(be.f.x != 0.f ? dL.x * Lrem.x / be.f.x : 0.f,
-                be.f.y != 0.f ? dL.y * Lrem.y / be.f.y : 0.f,
-                be.f.z != 0.f ? dL.z * Lrem.z / be.f.z : 0.f);
-      if (tex >= 0) scatter_tex(sink, tex, texel, q * be.dalb, cnt);
-      if (rslot >= 0) {
-        f3 g = q * be.dalpha;
-        scatter_rough(sink, rslot, g.x + g.y + g.z, cnt);
-      }
-    }
-    beta = beta * be.f * (1.0f / be.pdf);
-    prev_pdf = be.pdf;
-    prev_p = p;
-    f3 wow = to_world(fr, wo);
-    o = spawn(s, p, n_g, wow);
-    d = wow;
-    if (k >= R.rr_depth) {
-      float q = fminf(maxc(beta), 0.95f);
-      if (u01(r1.z) >= q) break;
-      beta = beta * (1.0f / q);
-    }
-  }
-  return REPLAY ? Lrem : L;
-}
-
 DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, uint32_t g_hi,
                     const DRender& R, f3& o, f3& d) {
   uint4 r = philox(g_lo, g_hi, 0xFFFFFFFFu, 0u, R.key0, R.key1);
@@ -796,6 +619,295 @@ DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, ui
   float sy = (1.0f - 2.0f * py) * c.tan_half;
   o = mk(c.ox, c.oy, c.oz);
   d = normalize(mk(c.fx, c.fy, c.fz) + mk(c.rx, c.ry, c.rz) * sx + mk(c.ux, c.uy, c.uz) * sy);
+}
+
+// ---------------------------------------------------------------------------
+// The megakernel body.  A lane owns one pixel and loops over its samples.
+// Each iteration of the loop is one vertex for every lane of the wave, in
+// two phases that all lanes take together: (A) trace the closest-hit ray and
+// do the emission, next-event and BSDF-sampling work of the vertex it finds;
+// (B) trace the vertex's shadow ray and resolve the next-event term.  A lane
+// whose path has ended starts the pixel's next sample (in the adjoint: the
+// replay of the same sample) at the end of the iteration, so lanes stay in
+// phase and busy until their own pixel is done.
+//
+// Path conventions.  D = max_depth counts segments including the camera ray;
+// emission found at vertex k counts if k <= D; next-event estimation and
+// BSDF sampling happen at vertex k < D; Russian roulette after sampling at
+// k >= rr_depth.  Null surfaces, and mask surfaces whose opacity test fails,
+// are passed through and count as vertices.  Random numbers of vertex k come
+// from Philox blocks (g, b = k-1, dim 0/1): dim 0 = (light choice, light u,
+// light v, lobe choice), dim 1 = (bsdf u, bsdf v, roulette, mask).
+//
+// ADJ = false: primal; `out` receives the sum of the sample radiances.
+// ADJ = true: per sample, pass A traces the path for its radiance L; pass B
+// replays it from Lrem = L, subtracts each collected term as it is met, and
+// scatters dL . (d NEE_k + Lrem (d f_k)/f_k) at each scattering vertex.
+// ---------------------------------------------------------------------------
+template <bool ADJ>
+DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
+                      const LdsTables& tab, int cam, int x, int y, f3 dL, int* stk, Counters& cnt,
+                      const Sink& sink, f3& out) {
+  const int W = C.width, H = C.height;
+  const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
+  const int n_em = s.n_ems;
+  const float p_sel = n_em > 0 ? 1.0f / (float)n_em : 0.f;
+  const bool no_nee = (R.flags & DRT_FLAG_NO_NEE) != 0;
+
+  f3 acc = mk(0, 0, 0);
+  int sidx = 0;
+  uint32_t glo = 0, ghi = 0;
+  f3 beta, L, Lrem = mk(0, 0, 0), o, d, prev_p;
+  float prev_pdf;
+  int k;
+
+  auto start = [&]() {
+    uint64_t g = pix * (uint64_t)R.spp + (uint64_t)sidx;
+    glo = (uint32_t)g;
+    ghi = (uint32_t)(g >> 32);
+    camera_ray(C.cam[cam], W, H, x, y, glo, ghi, R, o, d);
+    beta = mk(1, 1, 1);
+    L = mk(0, 0, 0);
+    prev_pdf = 0.f;  // 0: the next emitter hit takes no MIS weight
+    prev_p = o;
+    k = 1;
+    cnt.samples++;
+  };
+
+  // one vertex for this lane: returns true when the path has ended.  The
+  // replay variant (pass B) carries the subtraction and the scatter; the
+  // other passes compile without them.
+  auto step = [&](auto replay) -> bool {
+    constexpr bool RB = ADJ && decltype(replay)::value;
+    bool done = false, nee = false;
+    f3 nee_c = mk(0, 0, 0), nee_gt = mk(0, 0, 0), so = o, sd = d;
+    float nee_gr = 0.f, stmax = 0.f;
+    bool bsdf_pend = false;
+    f3 rat_alb = mk(0, 0, 0), rat_alpha = mk(0, 0, 0);
+    int vtex = -1, vtexel = 0, vrslot = -1;
+    // ---------------- phase A: closest hit and the vertex's work
+    {
+      RayPre rp = ray_pre(o, d);
+      Hit h;
+      cnt.rays++;
+      const bool hit = traverse(s, rp, 0.f, INFINITY, false, h, stk, cnt);
+      if (!hit) {
+        if (s.env_emitter >= 0) {
+          int row, col;
+          float st;
+          env_cell(s, d, row, col, st);
+          float w = 1.0f;
+          if (!(prev_pdf == 0.f || no_nee)) w = power_heuristic(prev_pdf, p_sel * env_pdf(s, row, col, st));
+          f3 c = beta * env_lookup(s, row, col) * w;
+          L = L + c;
+          if (RB) Lrem = Lrem - c;
+        }
+        done = true;
+      } else {
+        DTri T = load_tri(s, h.tri);
+        f3 p0 = mk(T.p0x, T.p0y, T.p0z), p1 = mk(T.p1x, T.p1y, T.p1z), p2 = mk(T.p2x, T.p2y, T.p2z);
+        float b0 = 1.0f - h.b1 - h.b2;
+        f3 p = p0 * b0 + p1 * h.b1 + p2 * h.b2;
+        f3 n_g = normalize(cross(p1 - p0, p2 - p0));
+        const float4* shp = reinterpret_cast<const float4*>(s.shade + T.prim);
+        float4 sb = shp[1];
+        int mat_id = __float_as_int(sb.z), em_id = __float_as_int(sb.w);
+        float cos_y = -dot(d, n_g);
+        if (em_id >= 0 && cos_y > 0.f) {
+          const DEmitter& E = s.ems[em_id];
+          float w = 1.0f;
+          if (!(prev_pdf == 0.f || no_nee)) {
+            f3 dv = p - prev_p;
+            w = power_heuristic(prev_pdf, p_sel * dot(dv, dv) / (E.area * cos_y));
+          }
+          f3 c = beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
+          L = L + c;
+          if (RB) Lrem = Lrem - c;
+        }
+        if (k == R.max_depth) {
+          done = true;
+        } else {
+          uint4 r0 = philox(glo, ghi, (uint32_t)(k - 1), 0u, R.key0, R.key1);
+          uint4 r1 = philox(glo, ghi, (uint32_t)(k - 1), 1u, R.key0, R.key1);
+          const DMaterial& M = s.mats[mat_id];
+          const int type = M.type;
+          if (type == DRT_BSDF_NULL || (type == DRT_BSDF_MASK && u01(r1.w) >= M.opacity)) {
+            // pass-through: same direction, counts as a vertex
+            if (type == DRT_BSDF_MASK) prev_pdf = 0.f;
+            o = spawn(s, p, n_g, d);
+            ++k;
+          } else {
+            cnt.verts++;
+            // hoisted out of the switch: frame, albedo (texture or constant), roughness
+            Frame fr = make_frame(n_g);
+            f3 wi = to_local(fr, -d);
+            Shade sh;
+            sh.type = type;
+            sh.albedo = mk(M.albedo[0], M.albedo[1], M.albedo[2]);
+            sh.f0 = mk(M.f0[0], M.f0[1], M.f0[2]);
+            sh.alpha = M.alpha;
+            sh.eta = M.eta;
+            sh.opacity = M.opacity;
+            vtex = M.texture;
+            if (vtex >= 0) {
+              float4 sa = shp[0];
+              float u = sa.x * b0 + sa.z * h.b1 + sb.x * h.b2;
+              float v = sa.y * b0 + sa.w * h.b1 + sb.y * h.b2;
+              int TW = tab.tw[vtex], TH = tab.th[vtex];
+              int tx = (int)fminf(floorf(fmaxf(u, 0.f) * (float)TW), (float)(TW - 1));
+              int ty = (int)fminf(floorf(fmaxf(v, 0.f) * (float)TH), (float)(TH - 1));
+              vtexel = ty * TW + tx;
+              const float* tp = tab.tex[vtex] + 3 * (size_t)vtexel;
+              sh.albedo = mk(tp[0], tp[1], tp[2]);
+            }
+            vrslot = M.rough_slot;
+            if (vrslot >= 0) sh.alpha = P.rough[vrslot];
+            // next-event candidate; its shadow ray is traced in phase B
+            if (!no_nee && n_em > 0) {
+              const DEmitter& E = s.ems[pick(r0.x, (uint32_t)n_em)];
+              float lu = u01(r0.y), lv = u01(r0.z);
+              bool valid = false, delta = false, finite = false;
+              f3 wl = mk(0, 0, 1), y = mk(0, 0, 0), Le = mk(0, 0, 0);
+              float pdf_l = 0.f;
+              if (E.type == DRT_EMITTER_AREA) {
+                y = mk(E.p0[0], E.p0[1], E.p0[2]) + mk(E.e1[0], E.e1[1], E.e1[2]) * lu +
+                    mk(E.e2[0], E.e2[1], E.e2[2]) * lv;
+                f3 dv = y - p;
+                float dist2 = dot(dv, dv), dist = sqrtf(dist2);
+                wl = dv * (1.0f / dist);
+                float cy = -dot(wl, mk(E.n[0], E.n[1], E.n[2]));
+                if (cy > 0.f) {
+                  pdf_l = dist2 / (E.area * cy);
+                  Le = mk(E.radiance[0], E.radiance[1], E.radiance[2]);
+                  finite = true;
+                  valid = true;
+                }
+              } else if (E.type == DRT_EMITTER_ENV) {
+                if (env_sample(s, lu, lv, wl)) {
+                  int row, col;
+                  float st;
+                  env_cell(s, wl, row, col, st);
+                  pdf_l = env_pdf(s, row, col, st);
+                  if (pdf_l > 0.f) {
+                    Le = env_lookup(s, row, col);
+                    valid = true;
+                  }
+                }
+              } else {
+                wl = mk(E.p0[0], E.p0[1], E.p0[2]);
+                Le = mk(E.radiance[0], E.radiance[1], E.radiance[2]);
+                pdf_l = 1.0f;
+                delta = true;
+                valid = true;
+              }
+              if (valid) {
+                BEval fe = bsdf_eval<RB>(sh, wi, to_local(fr, wl));
+                if (nonzero(fe.f)) {
+                  float w = delta ? 1.0f : power_heuristic(p_sel * pdf_l, fe.pdf);
+                  f3 coef = beta * Le * (w / (p_sel * pdf_l));
+                  nee_c = coef * fe.f;
+                  if (RB) {
+                    nee_gt = dL * coef * fe.dalb;
+                    f3 g = dL * coef * fe.dalpha;
+                    nee_gr = g.x + g.y + g.z;
+                  }
+                  // shadow ray from the offset origin; towards an area light it
+                  // stops short of the sampled point by 1e-4 of its length
+                  so = spawn(s, p, n_g, wl);
+                  sd = wl;
+                  stmax = INFINITY;
+                  if (finite) {
+                    f3 dv = y - so;
+                    float dl = sqrtf(dot(dv, dv));
+                    sd = dv * (1.0f / dl);
+                    stmax = (1.0f - 1e-4f) * dl;
+                  }
+                  nee = true;
+                }
+              }
+            }
+            // BSDF sampling
+            f3 wo;
+            BEval be;
+            const bool ok = bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
+            if (RB) {
+              bsdf_pend = ok;
+              if (bsdf_pend) {
+                rat_alb = mk(be.f.x != 0.f ? be.dalb.x / be.f.x : 0.f,
+                             be.f.y != 0.f ? be.dalb.y / be.f.y : 0.f,
+                             be.f.z != 0.f ? be.dalb.z / be.f.z : 0.f);
+                rat_alpha = mk(be.f.x != 0.f ? be.dalpha.x / be.f.x : 0.f,
+                               be.f.y != 0.f ? be.dalpha.y / be.f.y : 0.f,
+                               be.f.z != 0.f ? be.dalpha.z / be.f.z : 0.f);
+              }
+            }
+            if (ok) {
+              beta = beta * be.f * (1.0f / be.pdf);
+              prev_pdf = be.pdf;
+              prev_p = p;
+              f3 wow = to_world(fr, wo);
+              o = spawn(s, p, n_g, wow);
+              d = wow;
+              if (k >= R.rr_depth) {
+                float q = fminf(maxc(beta), 0.95f);
+                if (u01(r1.z) >= q) done = true;
+                else beta = beta * (1.0f / q);
+              }
+            } else {
+              done = true;
+            }
+            ++k;
+          }
+        }
+      }
+    }
+    // ---------------- phase B: the shadow ray of this vertex
+    f3 gtex = mk(0, 0, 0);
+    float grough = 0.f;
+    if (nee) {
+      RayPre rp = ray_pre(so, sd);
+      Hit h;
+      cnt.shadow++;
+      if (!traverse(s, rp, 0.f, stmax, true, h, stk, cnt)) {
+        L = L + nee_c;
+        if (RB) {
+          Lrem = Lrem - nee_c;
+          gtex = nee_gt;
+          grough = nee_gr;
+        }
+      }
+    }
+    if (RB && bsdf_pend) {
+      // radiance arriving over the sampled direction = what is left of L
+      gtex = gtex + dL * Lrem * rat_alb;
+      f3 g = dL * Lrem * rat_alpha;
+      grough += g.x + g.y + g.z;
+    }
+    if (RB) {
+      // one scatter per vertex for its next-event and continuation terms
+      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
+      if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
+    }
+    return done;
+  };
+  // lanes start each path together (coherent primary rays); a lane whose
+  // path ends early waits for the wave
+  for (;;) {
+    start();
+    while (!step(std::false_type{})) {
+    }
+    if (ADJ) {
+      Lrem = L;  // pass B replays this sample from its full radiance
+      start();
+      while (!step(std::true_type{})) {
+      }
+      cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z))));
+    } else {
+      acc = acc + L;
+    }
+    if (++sidx == R.spp) break;
+  }
+  out = acc;
 }
 
 DEV void load_tables(LdsTables& tab, const DScene& s, const DParams& P, const DGrads* G) {
@@ -822,8 +934,10 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 }
 
 // ---------------------------------------------------------------------------
-// megakernels
+// megakernels: one 16x16 pixel tile per workgroup
 // ---------------------------------------------------------------------------
+// STATS = false compiles the counters out (they are never read).
+template <bool STATS>
 __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, DCams C, DRender R,
                                                            float* __restrict__ image) {
   __shared__ int stack[kStackDepth * kBlock];
@@ -836,26 +950,22 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
   const int cam = blockIdx.z;
   Counters cnt = {};
   if (x < W && y < H) {
-    const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
-    f3 acc = mk(0, 0, 0);
     Sink none{&tab, nullptr, nullptr};
-    for (int sidx = 0; sidx < R.spp; ++sidx) {
-      uint64_t g = pix * (uint64_t)R.spp + sidx;
-      f3 o, d;
-      camera_ray(C.cam[cam], W, H, x, y, (uint32_t)g, (uint32_t)(g >> 32), R, o, d);
-      acc = acc + trace_path<false>(s, P, R, tab, (uint32_t)g, (uint32_t)(g >> 32), o, d,
-                                    stack + threadIdx.x, cnt, mk(0, 0, 0), mk(0, 0, 0), none);
-    }
-    float inv = 1.0f / (float)R.spp;
-    float* out = image + 3 * pix;
+    f3 acc;
+    render_pixel<false>(s, P, C, R, tab, cam, x, y, mk(0, 0, 0), stack + threadIdx.x, cnt, none,
+                        acc);
+    const float inv = 1.0f / (float)R.spp;
+    float* out = image + 3 * (((size_t)cam * H + y) * W + x);
     out[0] = acc.x * inv;
     out[1] = acc.y * inv;
     out[2] = acc.z * inv;
   }
-  flush_counters(R, cnt);
+  if constexpr (STATS) flush_counters(R, cnt);
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
+// Held to 128 VGPRs (4 waves per SIMD): measured faster than 3 waves at 131.
+template <bool STATS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
                                                            const float* __restrict__ adj,
                                                            DGrads G) {
   __shared__ int stack[kStackDepth * kBlock];
@@ -871,25 +981,13 @@ __global__ __launch_bounds__(kBlock) void k_render_adjoint(DScene s, DParams P, 
   const int cam = blockIdx.z;
   Counters cnt = {};
   if (x < W && y < H) {
-    const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
+    const size_t pix = ((size_t)cam * H + y) * W + x;
     const float inv = 1.0f / (float)R.spp;
     f3 dL = mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
     if (nonzero(dL)) {
-      Sink none{&tab, nullptr, nullptr};
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
-      for (int sidx = 0; sidx < R.spp; ++sidx) {
-        uint64_t g = pix * (uint64_t)R.spp + sidx;
-        uint32_t glo = (uint32_t)g, ghi = (uint32_t)(g >> 32);
-        f3 o, d;
-        camera_ray(C.cam[cam], W, H, x, y, glo, ghi, R, o, d);
-        // pass A: the sample's radiance (kept in registers, nothing stored)
-        f3 L = trace_path<false>(s, P, R, tab, glo, ghi, o, d, stack + threadIdx.x, cnt,
-                                 mk(0, 0, 0), mk(0, 0, 0), none);
-        // pass B: replay with subtraction and scatter
-        f3 rem = trace_path<true>(s, P, R, tab, glo, ghi, o, d, stack + threadIdx.x, cnt, L, dL,
-                                  sink);
-        cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(rem.x), fmaxf(fabsf(rem.y), fabsf(rem.z))));
-      }
+      f3 unused;
+      render_pixel<true>(s, P, C, R, tab, cam, x, y, dL, stack + threadIdx.x, cnt, sink, unused);
     }
   }
   __syncthreads();
@@ -900,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void k_render_adjoint(DScene s, DParams P, 
       cnt.scatter++;
     }
   }
-  flush_counters(R, cnt);
+  if constexpr (STATS) flush_counters(R, cnt);
 }
 
 // Ray queries (closest / any) for tests and traversal measurements.
@@ -916,13 +1014,13 @@ __global__ __launch_bounds__(kBlock) void k_trace(DScene s, const float* __restr
   Hit h;
   drt_hit o;
   if (mode == 0) {
-    bool hit = traverse<false>(s, r, a.w, b.w, h, stack + threadIdx.x, cnt);
+    bool hit = traverse(s, r, a.w, b.w, false, h, stack + threadIdx.x, cnt);
     o.t = hit ? h.t : INFINITY;
     o.b1 = hit ? h.b1 : 0.f;
     o.b2 = hit ? h.b2 : 0.f;
     o.prim = hit ? h.prim : -1;
   } else {
-    bool hit = traverse<true>(s, r, a.w, b.w, h, stack + threadIdx.x, cnt);
+    bool hit = traverse(s, r, a.w, b.w, true, h, stack + threadIdx.x, cnt);
     o.t = 0.f;
     o.b1 = 0.f;
     o.b2 = 0.f;
@@ -1003,11 +1101,17 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
 
 // ---------------------------------------------------------------------------
 // launchers
+
 // ---------------------------------------------------------------------------
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, float* image, hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
-  hipLaunchKernelGGL(k_render_forward, grid, dim3(kBlock), 0, st, s, p, c, r, image);
+  if (r.stats)
+    hipLaunchKernelGGL((k_render_forward<true>), grid, dim3(kBlock), 0, st, s, p, c, r,
+                       image);
+  else
+    hipLaunchKernelGGL((k_render_forward<false>), grid, dim3(kBlock), 0, st, s, p, c,
+                       r, image);
   return hipGetLastError();
 }
 
@@ -1015,7 +1119,12 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
-  hipLaunchKernelGGL(k_render_adjoint, grid, dim3(kBlock), 0, st, s, p, c, r, adj, g);
+  if (r.stats)
+    hipLaunchKernelGGL((k_render_adjoint<true>), grid, dim3(kBlock), 0, st, s, p, c,
+                       r, adj, g);
+  else
+    hipLaunchKernelGGL((k_render_adjoint<false>), grid, dim3(kBlock), 0, st, s, p, c,
+                       r, adj, g);
   return hipGetLastError();
 }
 

@@ -40,18 +40,32 @@ def _params(sc):
     return tex, rough
 
 
-def check_image(g, o, what=""):
+def check_image(g, o, what="", amb=None, max_amb_frac=0.25):
+    """Image tolerance; pixels with a sample whose discrete decisions lie
+    within FP32 reach (amb > 0, from the oracle) are set aside and counted."""
     g = np.asarray(g, np.float64).reshape(-1, 3)
     o = np.asarray(o, np.float64).reshape(-1, 3)
+    keep = np.ones(g.shape[0], bool) if amb is None else (np.asarray(amb).reshape(-1) == 0)
+    n_amb = int((~keep).sum())
+    assert n_amb <= max_amb_frac * keep.size, (what, n_amb)
+    g, o = g[keep], o[keep]
     err = np.abs(g - o)
     ok = (err <= 1e-3 * np.abs(o) + 1e-6).all(axis=1)
     frac = ok.mean()
     mae = err.mean()
     scale = max(1.0, float(np.abs(o).mean()))
-    print(f"{what}: pass {frac:.5f} ({(~ok).sum()} px fail), mae {mae:.3g}, max err {err.max():.3g}",
-          flush=True)
+    print(f"{what}: pass {frac:.5f} ({(~ok).sum()} px fail of {ok.size}, {n_amb} set aside), "
+          f"mae {mae:.3g}, max err {err.max():.3g}", flush=True)
     assert frac >= 0.999, (what, frac)
     assert mae <= 1e-4 * scale, (what, mae)
+
+
+def unambiguous_adjoint(orc, adj, amb):
+    """Zero the image-space adjoint on pixels the oracle flags (a sample of
+    theirs takes a decision within FP32 reach), for both implementations."""
+    adj = adj.copy()
+    adj.reshape(-1, 3)[np.asarray(amb).reshape(-1) > 0] = 0
+    return adj
 
 
 def check_grad(g, o, what=""):
@@ -166,9 +180,9 @@ def test_forward_image_parity(case):
     rr = kw.get("rr_depth", drt.NO_RR)
     img = drt.render_forward(gs, tex, rough, sc.cameras, kw["spp"], kw["max_depth"], rr, seed=1,
                              flags=kw.get("flags", 0)).cpu().numpy()
-    ref = oracle.OracleScene(sc).render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
-                                        flags=kw.get("flags", 0), seed=1)
-    check_image(img, ref, case)
+    ref, amb = oracle.OracleScene(sc).render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
+                                             flags=kw.get("flags", 0), seed=1, ambiguity=True)
+    check_image(img, ref, case, amb)
 
 
 def test_forward_multi_camera_parity():
@@ -178,8 +192,8 @@ def test_forward_multi_camera_parity():
     gs = drt.Scene(sc)
     tex, rough = _params(sc)
     img = drt.render_forward(gs, tex, rough, sc.cameras, 3, 3, seed=7).cpu().numpy()
-    ref = oracle.OracleScene(sc).render(spp=3, max_depth=3, seed=7)
-    check_image(img, ref, "ring3")
+    ref, amb = oracle.OracleScene(sc).render(spp=3, max_depth=3, seed=7, ambiguity=True)
+    check_image(img, ref, "ring3", amb)
 
 
 # ---------------------------------------------------------------------------
@@ -204,13 +218,18 @@ def test_adjoint_parity(case):
     c = sc.cameras[0]
     adj = np.random.default_rng(5).normal(size=(1, c.height, c.width, 3)).astype(np.float32)
     rr = kw.get("rr_depth", drt.NO_RR)
+    orc = oracle.OracleScene(sc)
+    _, amb = orc.render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr, seed=2,
+                        ambiguity=True)
+    print(case, "pixels set aside:", int((amb > 0).sum()), flush=True)
+    adj = unambiguous_adjoint(orc, adj, amb)
     stats = drt.new_stats()
     gt, gr = drt.render_adjoint(gs, tex, rough, sc.cameras, torch.from_numpy(adj).cuda(), kw["spp"],
                                 kw["max_depth"], rr, seed=2, stats=stats)
     st = drt.read_stats(stats)
     print(case, st, flush=True)
-    ot, orr = oracle.OracleScene(sc).adjoint(adj.astype(np.float64), spp=kw["spp"],
-                                             max_depth=kw["max_depth"], rr_depth=rr, seed=2)
+    ot, orr = orc.adjoint(adj.astype(np.float64), spp=kw["spp"], max_depth=kw["max_depth"],
+                          rr_depth=rr, seed=2)
     for i, (g, o) in enumerate(zip(gt, ot)):
         check_grad(g.cpu().numpy(), o, f"{case} texture {i}")
     if len(sc.roughness):
