@@ -124,7 +124,7 @@ def main():
     achieved = flops / (adj_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_render_adjoint", "bound": "alu", "achieved": round(achieved, 4),
                 "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
-                "traffic": None, "launch_ms": round(adj_ms, 3),
+                "traffic": measured_traffic(), "launch_ms": round(adj_ms, 3),
                 "units_per_launch": {k: st[k] for k in ("rays", "shadow_rays", "nodes", "tris",
                                                          "vertices", "scatter", "samples")}}
 
@@ -159,6 +159,21 @@ def main():
         "aux": aux,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per adjoint launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "adjoint_traffic.json")))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return int(rec["hbm_bytes"])
 
 
 def aux_primal_1m(drt, scenes, torch):
