@@ -316,3 +316,133 @@ def adam(p, g, m, v, lr, b1, b2, eps, t, lo=-np.inf, hi=np.inf):
     lib().oracle_adam(_c_i64(p.size), _p(p), _p(np.ascontiguousarray(g, np.float64)), _p(m), _p(v),
                       _c_dbl(lr), _c_dbl(b1), _c_dbl(b2), _c_dbl(eps), _c_int(t), _c_dbl(lo),
                       _c_dbl(hi))
+
+
+# -- radiance cache ------------------------------------------------------------
+
+def nrc_cfg_array(cfg) -> np.ndarray:
+    return np.array([cfg["levels"], cfg["features"], cfg["log2_table"], cfg["base_res"],
+                     cfg["max_res"], *cfg["bbox_lo"], *cfg["bbox_hi"]], np.float64)
+
+
+def sh16(d):
+    out = np.zeros(16)
+    lib().oracle_sh16(_p(np.ascontiguousarray(d, np.float64)), _p(out))
+    return out
+
+
+def level_res(cfg, l):
+    return lib().oracle_level_res(_p(nrc_cfg_array(cfg)), _c_int(l))
+
+
+def grid_corners(cfg, l, xn):
+    idx = np.zeros(8, np.uint32)
+    w = np.zeros(8)
+    lib().oracle_grid_corners(_p(nrc_cfg_array(cfg)), _c_int(l), _p(np.ascontiguousarray(xn, np.float64)),
+                              _p(idx), _p(w))
+    return idx, w
+
+
+def nrc_encode(feat, cfg, grid):
+    """feat [n,13] raw records -> [n,80] network inputs (FP64)."""
+    feat = np.ascontiguousarray(feat, np.float64).reshape(-1, 13)
+    g = np.ascontiguousarray(grid, np.float32).reshape(-1)
+    out = np.zeros((feat.shape[0], 80))
+    lib().oracle_nrc_encode(_c_i64(feat.shape[0]), _p(feat), _p(nrc_cfg_array(cfg)), _p(g), _p(out))
+    return out
+
+
+def nrc_grid_backward(feat, cfg, dfeat, grad=None):
+    feat = np.ascontiguousarray(feat, np.float64).reshape(-1, 13)
+    dfeat = np.ascontiguousarray(dfeat, np.float64).reshape(-1, 80)
+    if grad is None:
+        grad = np.zeros(cfg["levels"] * (1 << cfg["log2_table"]) * cfg["features"])
+    lib().oracle_nrc_grid_backward(_c_i64(feat.shape[0]), _p(feat), _p(nrc_cfg_array(cfg)), _p(dfeat),
+                                   _p(grad))
+    return grad
+
+
+def mlp_num_weights() -> int:
+    return lib().oracle_mlp_num_weights()
+
+
+def mlp_forward(x, W, emu=False, threads=None):
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 80)
+    W = np.ascontiguousarray(W, np.float64)
+    y = np.zeros((x.shape[0], 3))
+    lib().oracle_mlp_forward(_c_i64(x.shape[0]), _p(x), _p(W), _c_int(1 if emu else 0),
+                             _c_int(threads or n_threads_default()), _p(y))
+    return y
+
+
+def mlp_backward(x, W, dy, emu=False):
+    """(dW, dx) of sum_i <dy_i, y_i>."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 80)
+    W = np.ascontiguousarray(W, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64).reshape(-1, 3)
+    dW = np.zeros_like(W)
+    dx = np.zeros_like(x)
+    lib().oracle_mlp_backward(_c_i64(x.shape[0]), _p(x), _p(W), _p(dy), _c_int(1 if emu else 0),
+                              _p(dW), _p(dx))
+    return dW, dx
+
+
+def rel_l2(y, t):
+    y = np.ascontiguousarray(y, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    dy = np.zeros_like(y)
+    lib().oracle_rel_l2.restype = _c_dbl
+    loss = lib().oracle_rel_l2(_c_i64(y.size // 3), _p(y), _p(t), _p(dy))
+    return loss, dy
+
+
+def _render_cached(self, cfg, grid, W, K=3, cams=None, spp=4, max_depth=6, rr_depth=3, flags=0,
+                   seed=1, pixel_ids=None, emu=True, textures=None, roughness=None, threads=None,
+                   ambiguity=False):
+    cams = self.sc.cameras if cams is None else cams
+    ca = cam_array(cams)
+    Wd, H = cams[0].width, cams[0].height
+    full = pixel_ids is None
+    if full:
+        pixel_ids = np.arange(len(cams) * Wd * H, dtype=np.int64)
+    pixel_ids = np.ascontiguousarray(pixel_ids, np.int64)
+    out = np.zeros((pixel_ids.size, 3))
+    amb = np.zeros(pixel_ids.size, np.int32) if ambiguity else None
+    texs, tptr, rough = self._params(textures, roughness)
+    g = np.ascontiguousarray(grid, np.float32).reshape(-1)
+    Wv = np.ascontiguousarray(W, np.float64)
+    lib().oracle_render_cached(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)), _c_int(spp),
+                               _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
+                               _c_int(K), _p(nrc_cfg_array(cfg)), _p(g), _p(Wv),
+                               _c_int(1 if emu else 0), _c_i64(pixel_ids.size), _p(pixel_ids),
+                               _c_int(threads or n_threads_default()), _p(out), _p(amb))
+    if full:
+        out = out.reshape(len(cams), H, Wd, 3)
+        if ambiguity:
+            amb = amb.reshape(len(cams), H, Wd)
+    return (out, amb) if ambiguity else out
+
+
+def _train_records(self, n_paths, K=3, cams=None, max_depth=6, rr_depth=3, flags=0, seed=7,
+                   textures=None, roughness=None, threads=None, extra=False):
+    """(features [n,13], targets [n,3], valid [n] bool, ambiguous [n] bool);
+    with extra=True also (beta, L_before, L_total) [n,3]."""
+    cams = self.sc.cameras if cams is None else cams
+    ca = cam_array(cams)
+    feat = np.zeros((n_paths, 13))
+    tgt = np.zeros((n_paths, 3))
+    valid = np.zeros(n_paths, np.int32)
+    amb = np.zeros(n_paths, np.int32)
+    beta, lat, ltot = np.zeros((n_paths, 3)), np.zeros((n_paths, 3)), np.zeros((n_paths, 3))
+    texs, tptr, rough = self._params(textures, roughness)
+    lib().oracle_train_records(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)),
+                               _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
+                               _c_int(K), _c_i64(n_paths), _c_int(threads or n_threads_default()),
+                               _p(feat), _p(tgt), _p(valid), _p(amb), _p(beta), _p(lat), _p(ltot))
+    if extra:
+        return feat, tgt, valid.astype(bool), amb.astype(bool), beta, lat, ltot
+    return feat, tgt, valid.astype(bool), amb.astype(bool)
+
+
+OracleScene.render_cached = _render_cached
+OracleScene.train_records = _train_records

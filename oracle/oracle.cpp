@@ -789,6 +789,26 @@ static V3 cam_dir(const Cam& k, int x, int y, double jx, double jy) {
 }
 
 // ---------------------------------------------------------------------------
+// Radiance-cache hook.  At the first scattering vertex with index k >= K
+// (and k < D), after that vertex's emission has been collected, the raw
+// features of the vertex are recorded: position, the direction back along
+// the incoming ray, the geometric normal turned towards that direction,
+// roughness (1 for non-microfacet types) and albedo (rho, f0 for a
+// conductor, 1 for a dielectric).  mode 0 (cached estimator): the path stops
+// there and the caller adds beta * max(C(features), 0).  mode 1 (training
+// record): the plain path continues; the target is the radiance collected
+// after the record point divided by beta at it.
+// ---------------------------------------------------------------------------
+struct CacheHook {
+  int K = 3;
+  int mode = 0;
+  bool has = false;
+  double feat[13];   // p[3], w[3], n[3], alpha, albedo[3]
+  RGB beta;          // throughput at the record vertex
+  RGB L_at;          // radiance collected up to and including its emission
+};
+
+// ---------------------------------------------------------------------------
 // One path-traced sample (the estimator of the primal megakernel).
 //
 // Depth: D counts path segments including the camera ray; emission found at
@@ -802,7 +822,8 @@ static V3 cam_dir(const Cam& k, int x, int y, double jx, double jy) {
 // propagated (sparse dual numbers).
 // ---------------------------------------------------------------------------
 static RGB trace_sample(const Scene& s, const Params& P, const Opts& opt, const Stream& rs, V3 o,
-                        V3 d, std::vector<VertexRec>* recs, Tangent* tanL) {
+                        V3 d, std::vector<VertexRec>* recs, Tangent* tanL,
+                        CacheHook* ch = nullptr) {
   RGB L, beta(1, 1, 1);
   Tangent tbeta;  // d beta
   double prev_pdf = 0;  // 0: no MIS for the next emitter hit (camera / delta event)
@@ -862,6 +883,21 @@ static RGB trace_sample(const Scene& s, const Params& P, const Opts& opt, const 
     Frame fr = make_frame(n_g);
     V3 wi = fr.to_local(-d);
     ShadeCtx sc = fetch_shading(s, P, s.tri_mat[h.prim], u, v);
+    if (ch && !ch->has && k >= ch->K) {
+      V3 w = -d;
+      V3 nn = dot(n_g, w) >= 0 ? n_g : -n_g;
+      double f[13] = {p.x, p.y, p.z, w.x, w.y, w.z, nn.x, nn.y, nn.z, 1.0, 0, 0, 0};
+      int t = mat.type;
+      bool ggx = t == BSDF_CONDUCTOR || t == BSDF_DIELECTRIC || t == BSDF_PLASTIC;
+      if (ggx) f[9] = sc.sh.alpha;
+      RGB alb = t == BSDF_CONDUCTOR ? mat.f0 : (t == BSDF_DIELECTRIC ? RGB(1, 1, 1) : sc.sh.albedo);
+      f[10] = alb[0]; f[11] = alb[1]; f[12] = alb[2];
+      std::memcpy(ch->feat, f, sizeof(f));
+      ch->has = true;
+      ch->beta = beta;
+      ch->L_at = L;
+      if (ch->mode == 0) break;
+    }
     VertexRec* rec = recs ? &recs->back() : nullptr;
     if (rec) {
       rec->k_tex = sc.k_tex; rec->has_tex = sc.has_tex;
@@ -1028,6 +1064,228 @@ static void parallel_for(int64_t n, int n_threads, F fn) {
     });
   }
   for (auto& x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// Neural radiance cache: input encoding and network.
+//
+// Encoding of a record (80 inputs): a multiresolution hash grid over the
+// position normalised to the scene box -- 16 levels of 2 features, 2^19
+// entries per level, resolutions from 16 to 2048 in a geometric series,
+// trilinear interpolation of the 8 corners, dense indexing while a level's
+// (N+1)^3 corners fit the table and otherwise the spatial hash of Mueller et
+// al. (Instant-NGP, 2022): xor of the corner coordinates times 1,
+// 2654435761, 805459861, modulo the table size; then 16 real spherical
+// harmonics (bands 0-3) of the direction, 16 of the normal, the roughness
+// and the albedo (68 values), zero-padded to 80.
+//
+// Network: 80 -> 64 -> 64 -> 64 -> 64 -> 3, ReLU on the hidden layers, no
+// biases; weights row-major [out][in], layers in order.  In the BF16 mode the
+// values a BF16 implementation stores in BF16 are rounded to it (round to
+// nearest even): the inputs, the weights, the hidden activations, and in the
+// backward pass the output gradient and the hidden-layer gradients.
+// ---------------------------------------------------------------------------
+struct GridCfg {
+  int L, F, log2T;
+  double Nmin, Nmax;
+  double lo[3], hi[3];
+};
+static const int kIn = 80, kHid = 64, kOut = 3;
+static const int kNumWeights = kHid * kIn + 3 * kHid * kHid + kOut * kHid;
+
+static int level_res(const GridCfg& g, int l) {
+  double r = g.Nmin * std::exp(l * (std::log(g.Nmax) - std::log(g.Nmin)) / (g.L - 1));
+  return (int)std::floor(r + 1e-6);
+}
+
+// the 8 corner indices and trilinear weights of one level
+static void grid_corners(const GridCfg& g, int l, const double xn[3], uint32_t idx[8], double w[8]) {
+  int N = level_res(g, l);
+  uint64_t T = 1ull << g.log2T;
+  int c0[3];
+  double fr[3];
+  for (int a = 0; a < 3; ++a) {
+    double pos = xn[a] * N;
+    int c = (int)std::floor(pos);
+    c = std::min(std::max(c, 0), N - 1);
+    c0[a] = c;
+    fr[a] = pos - c;
+  }
+  bool dense = (uint64_t)(N + 1) * (N + 1) * (N + 1) <= T;
+  for (int k = 0; k < 8; ++k) {
+    uint32_t c[3];
+    double wk = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      int bit = (k >> a) & 1;
+      c[a] = (uint32_t)(c0[a] + bit);
+      wk *= bit ? fr[a] : 1.0 - fr[a];
+    }
+    uint32_t id;
+    if (dense) {
+      id = c[0] + c[1] * (uint32_t)(N + 1) + c[2] * (uint32_t)(N + 1) * (uint32_t)(N + 1);
+    } else {
+      id = (c[0] * 1u) ^ (c[1] * 2654435761u) ^ (c[2] * 805459861u);
+      id &= (uint32_t)(T - 1);
+    }
+    idx[k] = id;
+    w[k] = wk;
+  }
+}
+
+static void normalise_pos(const GridCfg& g, const double p[3], double xn[3]) {
+  for (int a = 0; a < 3; ++a) {
+    double e = g.hi[a] - g.lo[a];
+    double v = e > 0 ? (p[a] - g.lo[a]) / e : 0.0;
+    xn[a] = std::min(std::max(v, 0.0), 1.0);
+  }
+}
+
+// Real spherical harmonics, bands 0..3, orthonormal on the sphere.
+static void sh16(const double d[3], double o[16]) {
+  double x = d[0], y = d[1], z = d[2];
+  const double c0 = 0.5 * std::sqrt(1.0 / kPi);
+  const double c1 = std::sqrt(3.0 / (4.0 * kPi));
+  const double c2a = 0.5 * std::sqrt(15.0 / kPi), c2b = 0.25 * std::sqrt(5.0 / kPi);
+  const double c2c = 0.25 * std::sqrt(15.0 / kPi);
+  const double c3a = 0.25 * std::sqrt(35.0 / (2.0 * kPi)), c3b = 0.5 * std::sqrt(105.0 / kPi);
+  const double c3c = 0.25 * std::sqrt(21.0 / (2.0 * kPi)), c3d = 0.25 * std::sqrt(7.0 / kPi);
+  const double c3e = 0.25 * std::sqrt(105.0 / kPi);
+  o[0] = c0;
+  o[1] = c1 * y;
+  o[2] = c1 * z;
+  o[3] = c1 * x;
+  o[4] = c2a * x * y;
+  o[5] = c2a * y * z;
+  o[6] = c2b * (3.0 * z * z - 1.0);
+  o[7] = c2a * x * z;
+  o[8] = c2c * (x * x - y * y);
+  o[9] = c3a * y * (3.0 * x * x - y * y);
+  o[10] = c3b * x * y * z;
+  o[11] = c3c * y * (5.0 * z * z - 1.0);
+  o[12] = c3d * z * (5.0 * z * z - 3.0);
+  o[13] = c3c * x * (5.0 * z * z - 1.0);
+  o[14] = c3e * z * (x * x - y * y);
+  o[15] = c3a * x * (x * x - 3.0 * y * y);
+}
+
+static void encode(const GridCfg& g, const float* grid, const double f[13], double out[80]) {
+  for (int i = 0; i < 80; ++i) out[i] = 0.0;
+  double xn[3];
+  normalise_pos(g, f, xn);
+  uint64_t T = 1ull << g.log2T;
+  for (int l = 0; l < g.L; ++l) {
+    uint32_t idx[8];
+    double w[8];
+    grid_corners(g, l, xn, idx, w);
+    for (int ft = 0; ft < g.F; ++ft) {
+      double acc = 0;
+      for (int k = 0; k < 8; ++k) acc += w[k] * grid[((uint64_t)l * T + idx[k]) * g.F + ft];
+      out[l * g.F + ft] = acc;
+    }
+  }
+  sh16(f + 3, out + 32);
+  sh16(f + 6, out + 48);
+  out[64] = f[9];
+  out[65] = f[10];
+  out[66] = f[11];
+  out[67] = f[12];
+}
+
+static double bf16_round(double v) {
+  float fv = (float)v;
+  uint32_t b;
+  std::memcpy(&b, &fv, 4);
+  if ((b & 0x7F800000u) != 0x7F800000u) b += 0x7FFFu + ((b >> 16) & 1u);
+  b &= 0xFFFF0000u;
+  float r;
+  std::memcpy(&r, &b, 4);
+  return r;
+}
+
+struct Mlp {
+  // layer l: out x in, offset
+  static int rows(int l) { return l == 4 ? kOut : kHid; }
+  static int cols(int l) { return l == 0 ? kIn : kHid; }
+  static int off(int l) { return l == 0 ? 0 : kHid * kIn + (l - 1) * kHid * kHid; }
+};
+
+// acts[l] holds the input of layer l (acts[0] = x), as the BF16 path would
+// store it; y = output (not rounded).
+static void mlp_forward(const double* W, const double* x, bool emu, std::vector<double>* acts,
+                        double y[3]) {
+  std::vector<double> a(x, x + kIn);
+  if (emu) for (auto& v : a) v = bf16_round(v);
+  if (acts) { acts->clear(); acts->insert(acts->end(), a.begin(), a.end()); }
+  for (int l = 0; l < 5; ++l) {
+    int R = Mlp::rows(l), C = Mlp::cols(l);
+    const double* w = W + Mlp::off(l);
+    std::vector<double> o(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+      double acc = 0;
+      for (int c = 0; c < C; ++c) {
+        double wv = emu ? bf16_round(w[r * C + c]) : w[r * C + c];
+        acc += wv * a[c];
+      }
+      o[r] = acc;
+    }
+    if (l < 4) {
+      for (auto& v : o) {
+        v = v > 0 ? v : 0.0;
+        if (emu) v = bf16_round(v);
+      }
+      if (acts) acts->insert(acts->end(), o.begin(), o.end());
+      a = o;
+    } else {
+      for (int r = 0; r < kOut; ++r) y[r] = o[r];
+    }
+  }
+}
+
+// dW += d(loss)/dW, dx = d(loss)/dx for one sample with output gradient dy.
+static void mlp_backward(const double* W, const double* x, const double dy[3], bool emu,
+                         double* dW, double* dx) {
+  std::vector<double> acts;
+  double y[3];
+  mlp_forward(W, x, emu, &acts, y);
+  auto act = [&](int l) { return acts.data() + (l == 0 ? 0 : kIn + (l - 1) * kHid); };
+  std::vector<double> g(dy, dy + kOut);
+  if (emu) for (auto& v : g) v = bf16_round(v);
+  for (int l = 4; l >= 0; --l) {
+    int R = Mlp::rows(l), C = Mlp::cols(l);
+    const double* w = W + Mlp::off(l);
+    const double* in = act(l);
+    for (int r = 0; r < R; ++r)
+      for (int c = 0; c < C; ++c) dW[Mlp::off(l) + r * C + c] += g[r] * in[c];
+    std::vector<double> gi(C, 0.0);
+    for (int c = 0; c < C; ++c) {
+      double acc = 0;
+      for (int r = 0; r < R; ++r) acc += (emu ? bf16_round(w[r * C + c]) : w[r * C + c]) * g[r];
+      gi[c] = acc;
+    }
+    if (l > 0) {
+      for (int c = 0; c < C; ++c) {
+        gi[c] = in[c] > 0 ? gi[c] : 0.0;  // ReLU of layer l-1's output
+        if (emu) gi[c] = bf16_round(gi[c]);
+      }
+      g = gi;
+    } else {
+      for (int c = 0; c < C; ++c) dx[c] = gi[c];
+    }
+  }
+}
+
+// Relative L2 (Mueller et al., neural radiance caching, 2021): mean over
+// samples and channels of (y - t)^2 / (sg(y)^2 + 0.01).
+static double rel_l2(int64_t n, const double* y, const double* t, double* dy) {
+  double acc = 0;
+  double inv = 1.0 / (3.0 * n);
+  for (int64_t i = 0; i < 3 * n; ++i) {
+    double den = y[i] * y[i] + 0.01;
+    double r = y[i] - t[i];
+    acc += r * r / den;
+    if (dy) dy[i] = 2.0 * r / den * inv;
+  }
+  return acc * inv;
 }
 
 }  // namespace orc
@@ -1415,6 +1673,162 @@ void oracle_adam(int64_t n, double* p, const double* g, double* m, double* v, do
     double x = p[i] - lr * mh / (std::sqrt(vh) + eps);
     p[i] = std::min(std::max(x, lo), hi);
   }
+}
+
+// ---------------------------------------------------------------------------
+// radiance cache
+// cfg: [L, F, log2T, Nmin, Nmax, lo0, lo1, lo2, hi0, hi1, hi2] (doubles)
+// ---------------------------------------------------------------------------
+static GridCfg grid_cfg(const double* c) {
+  GridCfg g;
+  g.L = (int)c[0]; g.F = (int)c[1]; g.log2T = (int)c[2]; g.Nmin = c[3]; g.Nmax = c[4];
+  for (int a = 0; a < 3; ++a) { g.lo[a] = c[5 + a]; g.hi[a] = c[8 + a]; }
+  return g;
+}
+
+void oracle_sh16(const double* d, double* out) { sh16(d, out); }
+
+int oracle_level_res(const double* cfg, int l) { return level_res(grid_cfg(cfg), l); }
+
+void oracle_grid_corners(const double* cfg, int l, const double* xn, uint32_t* idx, double* w) {
+  grid_corners(grid_cfg(cfg), l, xn, idx, w);
+}
+
+// feat [n][13] raw features -> out [n][80]; grid: float [L][T][F]
+void oracle_nrc_encode(int64_t n, const double* feat, const double* cfg, const float* grid,
+                       double* out) {
+  GridCfg g = grid_cfg(cfg);
+  for (int64_t i = 0; i < n; ++i) encode(g, grid, feat + 13 * i, out + 80 * i);
+}
+
+// grad [L][T][F] += sum_i trilinear-weight * dfeat[i][l*F + f]
+void oracle_nrc_grid_backward(int64_t n, const double* feat, const double* cfg,
+                              const double* dfeat, double* grad) {
+  GridCfg g = grid_cfg(cfg);
+  uint64_t T = 1ull << g.log2T;
+  for (int64_t i = 0; i < n; ++i) {
+    double xn[3];
+    normalise_pos(g, feat + 13 * i, xn);
+    for (int l = 0; l < g.L; ++l) {
+      uint32_t idx[8];
+      double w[8];
+      grid_corners(g, l, xn, idx, w);
+      for (int ft = 0; ft < g.F; ++ft)
+        for (int k = 0; k < 8; ++k)
+          grad[((uint64_t)l * T + idx[k]) * g.F + ft] += w[k] * dfeat[80 * i + l * g.F + ft];
+    }
+  }
+}
+
+int oracle_mlp_num_weights(void) { return kNumWeights; }
+
+void oracle_mlp_forward(int64_t n, const double* x, const double* W, int emu, int n_threads,
+                        double* y) {
+  parallel_for(n, n_threads, [&](int, int64_t i) { mlp_forward(W, x + kIn * i, emu != 0, nullptr, y + 3 * i); });
+}
+
+// dW (accumulated) and dx [n][80] for output gradients dy [n][3]
+void oracle_mlp_backward(int64_t n, const double* x, const double* W, const double* dy, int emu,
+                         double* dW, double* dx) {
+  for (int64_t i = 0; i < n; ++i) mlp_backward(W, x + kIn * i, dy + 3 * i, emu != 0, dW, dx + kIn * i);
+}
+
+double oracle_rel_l2(int64_t n, const double* y, const double* t, double* dy) {
+  return rel_l2(n, y, t, dy);
+}
+
+// Cached estimator: each sample's path stops at its record vertex (first
+// scattering vertex with index >= K) and adds beta * max(C, 0) with C the
+// network's output on the encoded record.  Same pixel ids/layout as
+// oracle_render.  W: network weights (double); grid: float [L][T][F].
+void oracle_render_cached(void* h, const float* const* textures, const float* roughness,
+                          const double* cams, int n_cams, int spp, int max_depth, int rr_depth,
+                          uint32_t flags, uint64_t seed, int K, const double* cfg,
+                          const float* grid, const double* W, int emu, int64_t n_pix,
+                          const int64_t* pixel_ids, int n_threads, double* out, int* ambiguous) {
+  const Scene& s = *(Scene*)h;
+  Params P{textures, roughness};
+  Opts opt{spp, max_depth, rr_depth, flags, seed};
+  GridCfg g = grid_cfg(cfg);
+  std::vector<Cam> cs;
+  for (int c = 0; c < n_cams; ++c) cs.push_back(make_cam(cams + 12 * c));
+  const int Wd = cs[0].W, Ht = cs[0].H;
+  parallel_for(n_pix, n_threads, [&](int, int64_t i) {
+    int64_t pid = pixel_ids[i];
+    int cam = (int)(pid / ((int64_t)Wd * Ht));
+    int y = (int)((pid / Wd) % Ht), x = (int)(pid % Wd);
+    RGB acc;
+    int n_amb = 0;
+    for (int sidx = 0; sidx < spp; ++sidx) {
+      uint64_t gi = (uint64_t)pid * spp + sidx;
+      Stream st = make_stream(seed, gi);
+      V3 o, d;
+      bool amb = false;
+      t_amb = ambiguous ? &amb : nullptr;
+      camera_ray(cs[cam], st, x, y, &o, &d);
+      CacheHook ch;
+      ch.K = K;
+      ch.mode = 0;
+      RGB L = trace_sample(s, P, opt, st, o, d, nullptr, nullptr, &ch);
+      t_amb = nullptr;
+      if (ch.has) {
+        double enc[80], yv[3];
+        encode(g, grid, ch.feat, enc);
+        mlp_forward(W, enc, emu != 0, nullptr, yv);
+        for (int c = 0; c < 3; ++c) L[c] += ch.beta[c] * std::max(yv[c], 0.0);
+      }
+      acc = acc + L;
+      n_amb += amb ? 1 : 0;
+    }
+    for (int c = 0; c < 3; ++c) out[3 * i + c] = acc[c] / spp;
+    if (ambiguous) ambiguous[i] = n_amb;
+  });
+}
+
+// Training records: path j (key = seed, g = j) starts at pixel
+// floor(r n_pix / 2^32) with r the first word of block (camera, dim 2), runs a
+// plain path, and, if it reaches a record vertex, returns its features and
+// target = (radiance collected after the record point) / beta there
+// (channels with beta = 0 get target 0).  valid[j] = 1 if recorded.
+void oracle_train_records(void* h, const float* const* textures, const float* roughness,
+                          const double* cams, int n_cams, int max_depth, int rr_depth,
+                          uint32_t flags, uint64_t seed, int K, int64_t n_paths, int n_threads,
+                          double* feat, double* target, int* valid, int* ambiguous,
+                          double* beta_out, double* lat_out, double* ltot_out) {
+  const Scene& s = *(Scene*)h;
+  Params P{textures, roughness};
+  Opts opt{1, max_depth, rr_depth, flags, seed};
+  std::vector<Cam> cs;
+  for (int c = 0; c < n_cams; ++c) cs.push_back(make_cam(cams + 12 * c));
+  const int Wd = cs[0].W, Ht = cs[0].H;
+  const uint32_t n_pix = (uint32_t)((int64_t)n_cams * Wd * Ht);
+  parallel_for(n_paths, n_threads, [&](int, int64_t j) {
+    Stream st = make_stream(seed, (uint64_t)j);
+    uint32_t r[4];
+    st.block(kCameraBlock, 2, r);
+    uint32_t pid = pick(r[0], n_pix);
+    int cam = (int)(pid / ((uint32_t)Wd * Ht));
+    int y = (int)((pid / Wd) % Ht), x = (int)(pid % Wd);
+    V3 o, d;
+    bool amb = false;
+    t_amb = ambiguous ? &amb : nullptr;
+    camera_ray(cs[cam], st, x, y, &o, &d);
+    CacheHook ch;
+    ch.K = K;
+    ch.mode = 1;
+    RGB L = trace_sample(s, P, opt, st, o, d, nullptr, nullptr, &ch);
+    t_amb = nullptr;
+    valid[j] = ch.has ? 1 : 0;
+    if (ambiguous) ambiguous[j] = amb ? 1 : 0;
+    for (int c = 0; c < 13; ++c) feat[13 * j + c] = ch.has ? ch.feat[c] : 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double b = ch.beta[c];
+      target[3 * j + c] = (ch.has && b != 0) ? (L[c] - ch.L_at[c]) / b : 0.0;
+      if (beta_out) beta_out[3 * j + c] = ch.has ? b : 0.0;
+      if (lat_out) lat_out[3 * j + c] = ch.has ? ch.L_at[c] : L[c];
+      if (ltot_out) ltot_out[3 * j + c] = L[c];
+    }
+  });
 }
 
 }  // extern "C"

@@ -623,3 +623,42 @@ def bsdf_zoo(width=64, height=64, seed=SEED_GEOMETRY, sun_intensity=200.0) -> Sc
     cam = Camera((0.0, 2.2, 4.0), (0.0, 0.3, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
     return b.build(tex_shapes=[(64, 64)], textures=[tex], roughness=rough,
                    envmap=env, cameras=[cam], name="bsdf_zoo")
+
+
+# ----------------------------------------------------------------------------
+# radiance-cache configuration and initial state (seeded inputs)
+# ----------------------------------------------------------------------------
+
+NRC_IN, NRC_HIDDEN, NRC_OUT = 80, 64, 3
+NRC_LAYERS = [(NRC_HIDDEN, NRC_IN), (NRC_HIDDEN, NRC_HIDDEN), (NRC_HIDDEN, NRC_HIDDEN),
+              (NRC_HIDDEN, NRC_HIDDEN), (NRC_OUT, NRC_HIDDEN)]
+NRC_NUM_WEIGHTS = sum(r * c for r, c in NRC_LAYERS)
+
+
+def nrc_config(sc: Scene, levels=16, features=2, log2_table=19, base_res=16, max_res=2048,
+               trunc_vertex=3) -> dict:
+    """Hash-grid configuration over the scene's vertex bounding box."""
+    lo = sc.positions.min(0).astype(np.float64)
+    hi = sc.positions.max(0).astype(np.float64)
+    return dict(levels=levels, features=features, log2_table=log2_table, base_res=base_res,
+                max_res=max_res, bbox_lo=[float(x) for x in np.float32(lo)],
+                bbox_hi=[float(x) for x in np.float32(hi)], trunc_vertex=trunc_vertex)
+
+
+def nrc_init(cfg: dict, seed: int = 16):
+    """Initial network weights (He-uniform, float32 [NRC_NUM_WEIGHTS], layers
+    row-major [out][in], input columns 68..79 zero) and hash-grid features
+    (float16 [levels, 2^log2_table, features], U(-1e-4, 1e-4))."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for li, (r, c) in enumerate(NRC_LAYERS):
+        fan_in = 68 if li == 0 else c
+        a = np.sqrt(6.0 / fan_in)
+        w = rng.uniform(-a, a, (r, c))
+        if li == 0:
+            w[:, 68:] = 0.0
+        ws.append(w.reshape(-1))
+    W = np.concatenate(ws).astype(np.float32)
+    T = 1 << cfg["log2_table"]
+    grid = rng.uniform(-1e-4, 1e-4, (cfg["levels"], T, cfg["features"])).astype(np.float16)
+    return W, grid
