@@ -249,9 +249,92 @@ typedef struct {
   int32_t step;
   float lo, hi;
   int32_t zero_grad;
+  uint16_t* half_out; /* device FP16 copy of the updated parameters, or NULL */
 } drt_adam_opts;
 drt_status drt_adam_step(float* param, float* grad, float* m, float* v, int64_t n,
                          const drt_adam_opts* opts, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Neural radiance cache.  The paper does not cover it; this build adds it as
+ * a learned replacement of path tails: paths stop at their record vertex --
+ * the first scattering vertex with index >= K, after that vertex's emission
+ * -- and add beta * max(C, 0), where C is a small network evaluated on an
+ * encoding of the vertex.  The network is trained online on records of plain
+ * paths whose target is the radiance they collected after the record point,
+ * divided by the throughput there.
+ *
+ * Record (float[16]): position[3], direction back along the ray[3], normal
+ * facing that direction[3], roughness (1 unless microfacet), albedo[3]
+ * (f0 for a conductor, 1 for a dielectric), then target[3] (training) or
+ * throughput[3] (queries).
+ * Encoding (80 inputs): 16-level hash grid of the position normalised to
+ * bbox (2 FP16 features per entry, 2^log2_table entries per level,
+ * resolutions base_res..max_res geometrically, trilinear; dense indexing while
+ * (N+1)^3 entries fit, else the spatial hash of Mueller et al. 2022), 16 real
+ * spherical harmonics (bands 0-3) of the direction and of the normal,
+ * roughness, albedo, zero padding.
+ * Network: 80 -> 64 -> 64 -> 64 -> 64 -> 3, ReLU, no biases; weights are one
+ * float array [DRT_NRC_WEIGHTS] of row-major [out][in] matrices, rounded to
+ * BF16 inside the kernels; BF16 MFMA with FP32 accumulation.
+ * ------------------------------------------------------------------------ */
+enum { DRT_NRC_INPUTS = 80, DRT_NRC_WEIGHTS = 17600, DRT_NRC_RECORD = 16, DRT_NRC_LEVELS = 16 };
+
+typedef struct {
+  int32_t levels;        /* 16 in this build */
+  int32_t features;      /* 2 in this build */
+  int32_t log2_table;    /* entries per level = 2^log2_table, 10..24 */
+  int32_t base_res, max_res;
+  int32_t trunc_vertex;  /* K >= 2 */
+  float bbox_lo[3], bbox_hi[3];
+} drt_nrc_config;
+
+/* Encoding only (test hook): records [n][16] -> x [n][80] float. */
+drt_status drt_nrc_encode(const drt_nrc_config* cfg, const uint16_t* grid, const float* records,
+                          int64_t n, float* x, void* hip_stream);
+
+/* Network only (test hooks): y [n][3] = net(x); inputs rounded to BF16.
+ * backward: dW [DRT_NRC_WEIGHTS] += d<dy, y>/dW; dx [n][80] = d<dy, y>/dx for
+ * inputs 0..31 (the hash features), 0 for the others; dx may be NULL. */
+drt_status drt_nrc_forward(const float* weights, const float* x, int64_t n, float* y,
+                           void* hip_stream);
+drt_status drt_nrc_backward(const float* weights, const float* x, const float* dy, int64_t n,
+                            float* dW, float* dx, void* hip_stream);
+
+/* Hash-grid gradient only (test hook): dgrid [levels][2^log2_table][2] +=
+ * the trilinear scatter of dx [n][80] (inputs 0..31) at the records'
+ * positions. */
+drt_status drt_nrc_grid_backward(const drt_nrc_config* cfg, const float* records, const float* dx,
+                                 int64_t n, float* dgrid, void* hip_stream);
+
+/* Training paths: path j (Philox counter g = j, key opts->seed) starts at the
+ * pixel floor(r n_pix / 2^32), r = first word of block (camera, dim 2), runs a
+ * plain path (opts->max_depth, rr_depth, flags; spp is ignored) and writes
+ * records[j] and valid[j]; *count = number of valid records (set, not added).
+ * records: device float [n_paths][16]; valid: device int32 [n_paths]. */
+drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
+                           const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                           const drt_nrc_config* cfg, int64_t n_paths, float* records,
+                           int32_t* valid, int32_t* count, void* hip_stream);
+
+/* One training pass: relative-L2 loss (Mueller et al. 2021: mean over valid
+ * records and channels of (y - t)^2 / (y^2 + 0.01), y held fixed in the
+ * denominator) -> network and grid gradients ADDED to dW [17600] and dgrid
+ * [levels][2^log2_table][2] (float); *loss is set to the loss. */
+drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,
+                         const float* records, const int32_t* valid, const int32_t* count,
+                         int64_t n, float* dW, float* dgrid, float* loss, void* hip_stream);
+
+/* Primal render with the cache: image = (1/spp) sum over samples of the
+ * path radiance up to the record vertex plus beta * max(C, 0) there.
+ * queries: device float [capacity][16], query_pixels: int32 [capacity],
+ * query_count: int32 [1] (scratch, set by the call); capacity >= n_cams*W*H*spp.
+ * The cache terms are added with float atomics (order not deterministic). */
+drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
+                                     const drt_camera* cams, int32_t n_cams,
+                                     const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                     const float* weights, const uint16_t* grid, float* queries,
+                                     int32_t* query_pixels, int32_t* query_count,
+                                     int64_t capacity, float* image, void* hip_stream);
 
 #ifdef __cplusplus
 }

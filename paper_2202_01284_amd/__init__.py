@@ -92,7 +92,13 @@ class drt_hit(ctypes.Structure):
 
 class drt_adam_opts(ctypes.Structure):
     _fields_ = [("lr", _c_f), ("beta1", _c_f), ("beta2", _c_f), ("eps", _c_f), ("step", _c_i32),
-                ("lo", _c_f), ("hi", _c_f), ("zero_grad", _c_i32)]
+                ("lo", _c_f), ("hi", _c_f), ("zero_grad", _c_i32), ("half_out", _vp)]
+
+
+class drt_nrc_config(ctypes.Structure):
+    _fields_ = [("levels", _c_i32), ("features", _c_i32), ("log2_table", _c_i32),
+                ("base_res", _c_i32), ("max_res", _c_i32), ("trunc_vertex", _c_i32),
+                ("bbox_lo", _c_f * 3), ("bbox_hi", _c_f * 3)]
 
 
 # Every entry point of include/drt.h with its ctypes signature.
@@ -115,6 +121,20 @@ _SIGS = {
     "drt_loss_workspace_floats": (_c_i64, [_c_i64]),
     "drt_loss_l2": (_c_i32, [_vp, _vp, _c_i64, _vp, _vp, _vp, _vp]),
     "drt_adam_step": (_c_i32, [_vp, _vp, _vp, _vp, _c_i64, ctypes.POINTER(drt_adam_opts), _vp]),
+    "drt_nrc_encode": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _c_i64, _vp, _vp]),
+    "drt_nrc_forward": (_c_i32, [_vp, _vp, _c_i64, _vp, _vp]),
+    "drt_nrc_grid_backward": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _c_i64, _vp, _vp]),
+    "drt_nrc_backward": (_c_i32, [_vp, _vp, _vp, _c_i64, _vp, _vp, _vp]),
+    "drt_nrc_collect": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
+                                 ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_nrc_config),
+                                 _c_i64, _vp, _vp, _vp, _vp]),
+    "drt_nrc_train": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp, _c_i64, _vp,
+                               _vp, _vp, _vp]),
+    "drt_render_forward_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params),
+                                           ctypes.POINTER(drt_camera), _c_i32,
+                                           ctypes.POINTER(drt_render_opts),
+                                           ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp,
+                                           _vp, _c_i64, _vp, _vp]),
 }
 
 
@@ -414,7 +434,7 @@ def loss_l2(img, target, adj=None, stream=None):
 
 def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9,
               beta2: float = 0.99, eps: float = 1e-8, lo: float = -np.inf, hi: float = np.inf,
-              zero_grad: bool = False, stream=None):
+              zero_grad: bool = False, half_out=None, stream=None):
     for t, w in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
         _expect(t, w)
     o = drt_adam_opts()
@@ -423,6 +443,7 @@ def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9
     o.lo = float(max(lo, -3.0e38))
     o.hi = float(min(hi, 3.0e38))
     o.zero_grad = 1 if zero_grad else 0
+    o.half_out = None if half_out is None else half_out.data_ptr()
     _check(lib.drt_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
                              param.numel(), ctypes.byref(o), _stream(stream)), "drt_adam_step")
 
@@ -487,3 +508,168 @@ def render(scene: Scene, cams, textures, roughness=None, spp=4, max_depth=3, rr_
         _RenderFn = _make_render_fn()
     return _RenderFn.apply(scene, cams, spp, max_depth, rr_depth, seed_fwd, seed_adj, roughness,
                            *textures)
+
+
+# ---------------------------------------------------------------------------
+# neural radiance cache
+# ---------------------------------------------------------------------------
+NRC_INPUTS, NRC_WEIGHTS, NRC_RECORD = 80, 17600, 16
+
+
+def nrc_config(cfg: dict) -> drt_nrc_config:
+    c = drt_nrc_config()
+    c.levels = int(cfg["levels"])
+    c.features = int(cfg["features"])
+    c.log2_table = int(cfg["log2_table"])
+    c.base_res = int(cfg["base_res"])
+    c.max_res = int(cfg["max_res"])
+    c.trunc_vertex = int(cfg["trunc_vertex"])
+    c.bbox_lo[:] = [float(x) for x in cfg["bbox_lo"]]
+    c.bbox_hi[:] = [float(x) for x in cfg["bbox_hi"]]
+    return c
+
+
+def nrc_encode(cfg: dict, grid, records, stream=None):
+    """records float [n,16] -> network inputs float [n,80] (before BF16)."""
+    torch = _torch()
+    n = records.shape[0]
+    x = torch.empty((n, NRC_INPUTS), dtype=torch.float32, device=records.device)
+    c = nrc_config(cfg)
+    _check(lib.drt_nrc_encode(ctypes.byref(c), grid.data_ptr(), records.data_ptr(), n,
+                              x.data_ptr(), _stream(stream)), "drt_nrc_encode")
+    return x
+
+
+def nrc_grid_backward(cfg: dict, records, dx, dgrid, stream=None):
+    c = nrc_config(cfg)
+    _check(lib.drt_nrc_grid_backward(ctypes.byref(c), records.data_ptr(), dx.data_ptr(),
+                                     records.shape[0], dgrid.data_ptr(), _stream(stream)),
+           "drt_nrc_grid_backward")
+    return dgrid
+
+
+def nrc_forward(weights, x, stream=None):
+    torch = _torch()
+    n = x.shape[0]
+    y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
+    _check(lib.drt_nrc_forward(weights.data_ptr(), x.data_ptr(), n, y.data_ptr(), _stream(stream)),
+           "drt_nrc_forward")
+    return y
+
+
+def nrc_backward(weights, x, dy, dW=None, stream=None):
+    torch = _torch()
+    n = x.shape[0]
+    if dW is None:
+        dW = torch.zeros(NRC_WEIGHTS, dtype=torch.float32, device=x.device)
+    dx = torch.empty((n, NRC_INPUTS), dtype=torch.float32, device=x.device)
+    _check(lib.drt_nrc_backward(weights.data_ptr(), x.data_ptr(), dy.data_ptr(), n, dW.data_ptr(),
+                                dx.data_ptr(), _stream(stream)), "drt_nrc_backward")
+    return dW, dx
+
+
+def nrc_collect(scene: Scene, textures, roughness, cams, cfg: dict, n_paths: int, seed: int,
+                max_depth: int = 6, rr_depth: int = 3, flags: int = 0, out=None, stream=None):
+    """Training records of n_paths plain paths: (records [n,16], valid [n] int32, count [1])."""
+    torch = _torch()
+    dev = scene.buffer.device
+    if out is None:
+        out = (torch.empty((n_paths, NRC_RECORD), dtype=torch.float32, device=dev),
+               torch.empty(n_paths, dtype=torch.int32, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    rec, valid, count = out
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(1, max_depth, rr_depth, seed, flags, None)
+    c = nrc_config(cfg)
+    _check(lib.drt_nrc_collect(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                               ctypes.byref(c), n_paths, rec.data_ptr(), valid.data_ptr(),
+                               count.data_ptr(), _stream(stream)), "drt_nrc_collect")
+    return rec, valid, count
+
+
+def nrc_train(cfg: dict, weights, grid, records, valid, count, dW, dgrid, loss=None, stream=None):
+    torch = _torch()
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=weights.device)
+    c = nrc_config(cfg)
+    _check(lib.drt_nrc_train(ctypes.byref(c), weights.data_ptr(), grid.data_ptr(),
+                             records.data_ptr(), valid.data_ptr(), count.data_ptr(),
+                             records.shape[0], dW.data_ptr(), dgrid.data_ptr(), loss.data_ptr(),
+                             _stream(stream)), "drt_nrc_train")
+    return loss
+
+
+def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, weights, grid,
+                          spp: int, max_depth: int = 6, rr_depth: int = 3, seed: int = 1,
+                          flags: int = 0, out=None, work=None, stream=None):
+    """Primal image with path tails replaced by the cache at the record vertex."""
+    torch = _torch()
+    dev = scene.buffer.device
+    W, H = cams[0].width, cams[0].height
+    if out is None:
+        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=dev)
+    cap = len(cams) * W * H * spp
+    if work is None:
+        work = (torch.empty((cap, NRC_RECORD), dtype=torch.float32, device=dev),
+                torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty(1, dtype=torch.int32, device=dev))
+    q, qpix, qcount = work
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    c = nrc_config(cfg)
+    _check(lib.drt_render_forward_cached(scene.handle, ctypes.byref(p), ca, len(cams),
+                                         ctypes.byref(o), ctypes.byref(c), weights.data_ptr(),
+                                         grid.data_ptr(), q.data_ptr(), qpix.data_ptr(),
+                                         qcount.data_ptr(), q.shape[0], out.data_ptr(),
+                                         _stream(stream)), "drt_render_forward_cached")
+    return out
+
+
+class NrcCache:
+    """Radiance-cache state on the device: FP32 master weights and hash-grid
+    features (with an FP16 copy of the grid for the kernels), Adam moments,
+    gradient buffers, and the per-frame training loop
+    (collect -> train -> Adam on the network -> Adam on the grid)."""
+
+    def __init__(self, cfg: dict, weights0, grid0, n_paths: int = 65536, lr: float = 1e-2,
+                 device: str = "cuda"):
+        torch = _torch()
+        self.cfg = dict(cfg)
+        self.W = torch.as_tensor(np.asarray(weights0, np.float32)).to(device).contiguous()
+        g16 = torch.as_tensor(np.asarray(grid0, np.float16).reshape(-1)).to(device).contiguous()
+        self.grid16 = g16
+        self.grid = g16.float().contiguous()
+        self.mW, self.vW = torch.zeros_like(self.W), torch.zeros_like(self.W)
+        self.mG, self.vG = torch.zeros_like(self.grid), torch.zeros_like(self.grid)
+        self.dW, self.dG = torch.zeros_like(self.W), torch.zeros_like(self.grid)
+        self.n_paths = n_paths
+        self.lr = lr
+        self.step = 0
+        self.buf = None
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def train_frame(self, scene: Scene, textures, roughness, cams, seed: int, max_depth: int = 6,
+                    rr_depth: int = 3):
+        torch = _torch()
+        if self.buf is None:
+            dev = self.W.device
+            self.buf = (torch.empty((self.n_paths, NRC_RECORD), dtype=torch.float32, device=dev),
+                        torch.empty(self.n_paths, dtype=torch.int32, device=dev),
+                        torch.empty(1, dtype=torch.int32, device=dev))
+        rec, valid, count = nrc_collect(scene, textures, roughness, cams, self.cfg, self.n_paths,
+                                        seed, max_depth, rr_depth, out=self.buf)
+        nrc_train(self.cfg, self.W, self.grid16, rec, valid, count, self.dW, self.dG, self.loss)
+        self.step += 1
+        adam_step(self.W, self.dW, self.mW, self.vW, self.step, lr=self.lr, beta1=0.9, beta2=0.99,
+                  eps=1e-8, zero_grad=True)
+        adam_step(self.grid, self.dG, self.mG, self.vG, self.step, lr=self.lr, beta1=0.9,
+                  beta2=0.99, eps=1e-8, zero_grad=True, half_out=self.grid16)
+        return self.loss
+
+    def render(self, scene: Scene, textures, roughness, cams, spp: int, seed: int, max_depth=6,
+               rr_depth=3, out=None, work=None):
+        return render_forward_cached(scene, textures, roughness, cams, self.cfg, self.W,
+                                     self.grid16, spp, max_depth, rr_depth, seed, out=out,
+                                     work=work)

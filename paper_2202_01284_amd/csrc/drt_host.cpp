@@ -569,6 +569,32 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   return DRT_OK;
 }
 
+drt_status nrc_net(const drt_nrc_config* c, const uint16_t* grid, DNrcNet* net) {
+  if (!c) return fail(DRT_EINVAL, "cache config is NULL");
+  if (c->levels != DRT_NRC_LEVELS || c->features != 2)
+    return fail(DRT_EUNSUPPORTED, "this build has 16 levels of 2 features");
+  if (c->log2_table < 10 || c->log2_table > 24) return fail(DRT_EINVAL, "log2_table must be in [10, 24]");
+  if (c->base_res < 1 || c->max_res < c->base_res) return fail(DRT_EINVAL, "bad grid resolutions");
+  if (c->trunc_vertex < 2) return fail(DRT_EINVAL, "trunc_vertex must be >= 2");
+  std::memset(net, 0, sizeof(*net));
+  net->grid = reinterpret_cast<const uint32_t*>(grid);
+  net->log2_table = c->log2_table;
+  const double T = std::ldexp(1.0, c->log2_table);
+  for (int l = 0; l < DRT_NRC_LEVELS; ++l) {
+    double r = c->base_res * std::exp(l * (std::log((double)c->max_res) - std::log((double)c->base_res)) /
+                                      (DRT_NRC_LEVELS - 1));
+    int N = (int)std::floor(r + 1e-6);
+    net->res[l] = N;
+    net->dense[l] = (double)(N + 1) * (N + 1) * (N + 1) <= T ? 1 : 0;
+  }
+  for (int a = 0; a < 3; ++a) {
+    double e = (double)c->bbox_hi[a] - c->bbox_lo[a];
+    net->lo[a] = c->bbox_lo[a];
+    net->inv_ext[a] = e > 0 ? (float)(1.0 / e) : 0.f;
+  }
+  return DRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -720,6 +746,134 @@ drt_status drt_adam_step(float* param, float* grad, float* m, float* v, int64_t 
   if (n == 0) return ok();
   hipError_t e = launch_adam(param, grad, m, v, n, *opts, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return ok();
+}
+
+drt_status drt_nrc_encode(const drt_nrc_config* cfg, const uint16_t* grid, const float* records,
+                          int64_t n, float* x, void* hip_stream) {
+  DNrcNet net;
+  drt_status st = nrc_net(cfg, grid, &net);
+  if (st != DRT_OK) return st;
+  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+  if (n == 0) return ok();
+  if (!grid || !records || !x) return fail(DRT_EINVAL, "null pointer argument");
+  hipError_t e = launch_nrc_encode(net, records, n, x, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_encode launch");
+  return ok();
+}
+
+drt_status drt_nrc_grid_backward(const drt_nrc_config* cfg, const float* records, const float* dx,
+                                 int64_t n, float* dgrid, void* hip_stream) {
+  DNrcNet net;
+  drt_status st = nrc_net(cfg, nullptr, &net);
+  if (st != DRT_OK) return st;
+  if (n < 0 || n > ((int64_t)1 << 32)) return fail(DRT_EINVAL, "n out of range");
+  if (n == 0) return ok();
+  if (!records || !dx || !dgrid) return fail(DRT_EINVAL, "null pointer argument");
+  hipError_t e = launch_nrc_grid_backward(net, records, dx, n, dgrid, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_grid_backward launch");
+  return ok();
+}
+
+drt_status drt_nrc_forward(const float* weights, const float* x, int64_t n, float* y,
+                           void* hip_stream) {
+  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+  if (n == 0) return ok();
+  if (!weights || !x || !y) return fail(DRT_EINVAL, "null pointer argument");
+  hipError_t e = launch_nrc_forward(weights, x, n, y, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_forward launch");
+  return ok();
+}
+
+drt_status drt_nrc_backward(const float* weights, const float* x, const float* dy, int64_t n,
+                            float* dW, float* dx, void* hip_stream) {
+  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+  if (n == 0) return ok();
+  if (!weights || !x || !dy || !dW) return fail(DRT_EINVAL, "null pointer argument");
+  hipError_t e = launch_nrc_backward(weights, x, dy, n, dW, dx, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_backward launch");
+  return ok();
+}
+
+drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
+                           const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                           const drt_nrc_config* cfg, int64_t n_paths, float* records,
+                           int32_t* valid, int32_t* count, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!cfg || cfg->trunc_vertex < 2) return fail(DRT_EINVAL, "cache config with trunc_vertex >= 2 required");
+  if (n_paths < 0 || n_paths > ((int64_t)1 << 32)) return fail(DRT_EINVAL, "n_paths out of range");
+  if (!count) return fail(DRT_EINVAL, "count is NULL");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e = launch_zero(count, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  if (n_paths == 0) return ok();
+  if (!records || !valid) return fail(DRT_EINVAL, "records and valid are required");
+  DNrcIO io = {};
+  io.rec = records;
+  io.valid = valid;
+  io.count = count;
+  io.K = cfg->trunc_vertex;
+  e = launch_nrc_records(scene->dev, dp, dc, dr, n_paths, io, stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_collect launch");
+  return ok();
+}
+
+drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,
+                         const float* records, const int32_t* valid, const int32_t* count,
+                         int64_t n, float* dW, float* dgrid, float* loss, void* hip_stream) {
+  DNrcNet net;
+  drt_status st = nrc_net(cfg, grid, &net);
+  if (st != DRT_OK) return st;
+  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+  if (!weights || !grid || !count || !dW || !dgrid || !loss)
+    return fail(DRT_EINVAL, "null pointer argument");
+  if (n > 0 && (!records || !valid)) return fail(DRT_EINVAL, "records and valid are required");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e = launch_zero(loss, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  if (n == 0) return ok();
+  e = launch_nrc_train(net, weights, records, valid, count, n, dW, dgrid, loss, stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_train launch");
+  return ok();
+}
+
+drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
+                                     const drt_camera* cams, int32_t n_cams,
+                                     const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                     const float* weights, const uint16_t* grid, float* queries,
+                                     int32_t* query_pixels, int32_t* query_count,
+                                     int64_t capacity, float* image, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  DNrcNet net;
+  st = nrc_net(cfg, grid, &net);
+  if (st != DRT_OK) return st;
+  if (!weights || !grid || !queries || !query_pixels || !query_count || !image)
+    return fail(DRT_EINVAL, "null pointer argument");
+  int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
+  if (capacity < need || need > INT32_MAX)
+    return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e = launch_zero(query_count, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  DNrcIO io = {};
+  io.rec = queries;
+  io.qpix = query_pixels;
+  io.count = query_count;
+  io.capacity = capacity;
+  io.K = cfg->trunc_vertex;
+  e = launch_render_cached(scene->dev, dp, dc, dr, image, io, stream);
+  if (e != hipSuccess) return hip_fail(e, "render_cached launch");
+  e = launch_nrc_infer(net, weights, queries, query_pixels, query_count, need,
+                       1.0f / (float)opts->spp, image, stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_infer launch");
   return ok();
 }
 

@@ -114,9 +114,37 @@ struct DRender {
   uint64_t* stats;
 };
 
+// Radiance-cache record: 16 floats = position[3], direction[3], normal[3],
+// roughness, albedo[3], then throughput[3] (queries) or target[3] (training).
+constexpr int NRC_REC = 16;
+
+// Radiance-cache network view for the kernels.
+struct DNrcNet {
+  const uint32_t* grid;  // [16 levels][2^log2_table] entries of 2 FP16 features
+  int log2_table;
+  int res[16];           // level resolutions
+  int dense[16];         // 1 if the level is indexed densely
+  float lo[3], inv_ext[3];
+};
+
+// Outputs of the cached primal (queries) and of the training paths.
+struct DNrcIO {
+  float* rec;       // [capacity or n_paths][NRC_REC]
+  int* qpix;        // queries: image index of each query
+  int* valid;       // training: 1 if path j has a record
+  int* count;       // appended queries / valid records
+  int64_t capacity; // queries the buffer holds
+  int K;            // record vertex index
+};
+
 // Launchers (drt_kernels.hip).
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, float* image, hipStream_t st);
+hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& c,
+                                const DRender& r, float* image, const DNrcIO& io,
+                                hipStream_t st);
+hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
+                              int64_t n_paths, const DNrcIO& io, hipStream_t st);
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st);
@@ -129,5 +157,20 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, int64_t n, float* 
                           float* ws, hipStream_t st);
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n,
                        const drt_adam_opts& o, hipStream_t st);
+hipError_t launch_zero(void* p, int64_t n_words, hipStream_t st);
+// Launchers (drt_nrc.hip).
+hipError_t launch_nrc_forward(const float* W, const float* x, int64_t n, float* y, hipStream_t st);
+hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n,
+                               float* dW, float* dx, hipStream_t st);
+hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
+                             hipStream_t st);
+hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
+                            const int* count, int64_t capacity, float inv_spp, float* image,
+                            hipStream_t st);
+hipError_t launch_nrc_grid_backward(const DNrcNet& net, const float* rec, const float* dx,
+                                    int64_t n, float* dgrid, hipStream_t st);
+hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+                            const int* count, int64_t n, float* dW, float* dgrid, float* loss,
+                            hipStream_t st);
 
 }  // namespace drt

@@ -15,6 +15,7 @@
 // call as a switch on the material id with the albedo/roughness fetch hoisted
 // out of it, roughness gradients pre-reduced in LDS per workgroup, texel
 // gradients as hardware float atomics (no return value).
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -639,15 +640,25 @@ DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, ui
 // from Philox blocks (g, b = k-1, dim 0/1): dim 0 = (light choice, light u,
 // light v, lobe choice), dim 1 = (bsdf u, bsdf v, roulette, mask).
 //
-// ADJ = false: primal; `out` receives the sum of the sample radiances.
-// ADJ = true: per sample, pass A traces the path for its radiance L; pass B
+// MODE_PRIMAL: `out` receives the sum of the sample radiances.
+// MODE_ADJOINT: per sample, pass A traces the path for its radiance L; pass B
 // replays it from Lrem = L, subtracts each collected term as it is met, and
 // scatters dL . (d NEE_k + Lrem (d f_k)/f_k) at each scattering vertex.
+// MODE_CACHED: a path stops at its record vertex -- the first scattering
+// vertex with index >= K, after that vertex's emission -- and appends a query
+// (features, throughput, pixel) for the radiance cache to answer.
+// MODE_TRAIN: a path records the features of its record vertex, goes on as a
+// plain path, and writes target = (radiance after the record point) / beta.
+// Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
 // ---------------------------------------------------------------------------
-template <bool ADJ>
+enum { MODE_PRIMAL = 0, MODE_ADJOINT = 1, MODE_CACHED = 2, MODE_TRAIN = 3 };
+
+template <int MODE>
 DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
-                      const LdsTables& tab, int cam, int x, int y, f3 dL, int* stk, Counters& cnt,
-                      const Sink& sink, f3& out) {
+                      const LdsTables& tab, int cam, int x, int y, uint64_t g_base, int n_samples,
+                      f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
+                      f3& out) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
   const int W = C.width, H = C.height;
   const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
   const int n_em = s.n_ems;
@@ -660,9 +671,12 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   f3 beta, L, Lrem = mk(0, 0, 0), o, d, prev_p;
   float prev_pdf;
   int k;
+  // record vertex (MODE_TRAIN)
+  bool recorded = false;
+  f3 beta_at = mk(0, 0, 0), L_at = mk(0, 0, 0);
 
   auto start = [&]() {
-    uint64_t g = pix * (uint64_t)R.spp + (uint64_t)sidx;
+    uint64_t g = g_base + (uint64_t)sidx;
     glo = (uint32_t)g;
     ghi = (uint32_t)(g >> 32);
     camera_ray(C.cam[cam], W, H, x, y, glo, ghi, R, o, d);
@@ -671,6 +685,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     prev_pdf = 0.f;  // 0: the next emitter hit takes no MIS weight
     prev_p = o;
     k = 1;
+    recorded = false;
     cnt.samples++;
   };
 
@@ -762,8 +777,45 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
             }
             vrslot = M.rough_slot;
             if (vrslot >= 0) sh.alpha = P.rough[vrslot];
+            bool stop_here = false;
+            if (MODE >= MODE_CACHED && !recorded && k >= io.K) {
+              // features of the record vertex: position, direction back along
+              // the ray, normal facing it, roughness (1 unless microfacet),
+              // albedo (f0 for a conductor, 1 for a dielectric)
+              f3 w = -d;
+              f3 nn = dot(n_g, w) >= 0.f ? n_g : -n_g;
+              bool ggx = type == DRT_BSDF_CONDUCTOR || type == DRT_BSDF_DIELECTRIC ||
+                         type == DRT_BSDF_PLASTIC;
+              f3 alb = type == DRT_BSDF_CONDUCTOR ? sh.f0
+                       : (type == DRT_BSDF_DIELECTRIC ? mk(1, 1, 1) : sh.albedo);
+              float* rec = nullptr;
+              if (MODE == MODE_CACHED) {
+                int slot = atomicAdd(io.count, 1);
+                if (slot < io.capacity) {
+                  rec = io.rec + (size_t)NRC_REC * slot;
+                  io.qpix[slot] = (int)pix;
+                  rec[13] = beta.x;
+                  rec[14] = beta.y;
+                  rec[15] = beta.z;
+                }
+                stop_here = true;
+                done = true;
+              } else {
+                rec = io.rec + (size_t)NRC_REC * g_base;
+                recorded = true;
+                beta_at = beta;
+                L_at = L;
+              }
+              if (rec) {
+                rec[0] = p.x; rec[1] = p.y; rec[2] = p.z;
+                rec[3] = w.x; rec[4] = w.y; rec[5] = w.z;
+                rec[6] = nn.x; rec[7] = nn.y; rec[8] = nn.z;
+                rec[9] = ggx ? sh.alpha : 1.0f;
+                rec[10] = alb.x; rec[11] = alb.y; rec[12] = alb.z;
+              }
+            }
             // next-event candidate; its shadow ray is traced in phase B
-            if (!no_nee && n_em > 0) {
+            if (!stop_here && !no_nee && n_em > 0) {
               const DEmitter& E = s.ems[pick(r0.x, (uint32_t)n_em)];
               float lu = u01(r0.y), lv = u01(r0.z);
               bool valid = false, delta = false, finite = false;
@@ -829,7 +881,8 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
             // BSDF sampling
             f3 wo;
             BEval be;
-            const bool ok = bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
+            const bool ok = !stop_here &&
+                            bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
             if (RB) {
               bsdf_pend = ok;
               if (bsdf_pend) {
@@ -896,6 +949,18 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     start();
     while (!step(std::false_type{})) {
     }
+    if (MODE == MODE_TRAIN) {
+      float* rec = io.rec + (size_t)NRC_REC * g_base;
+      if (recorded) {
+        rec[13] = beta_at.x != 0.f ? (L.x - L_at.x) / beta_at.x : 0.f;
+        rec[14] = beta_at.y != 0.f ? (L.y - L_at.y) / beta_at.y : 0.f;
+        rec[15] = beta_at.z != 0.f ? (L.z - L_at.z) / beta_at.z : 0.f;
+        atomicAdd(io.count, 1);
+      } else {
+        for (int c = 0; c < NRC_REC; ++c) rec[c] = 0.f;
+      }
+      io.valid[g_base] = recorded ? 1 : 0;
+    }
     if (ADJ) {
       Lrem = L;  // pass B replays this sample from its full radiance
       start();
@@ -905,7 +970,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     } else {
       acc = acc + L;
     }
-    if (++sidx == R.spp) break;
+    if (++sidx == n_samples) break;
   }
   out = acc;
 }
@@ -937,9 +1002,10 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 // megakernels: one 16x16 pixel tile per workgroup
 // ---------------------------------------------------------------------------
 // STATS = false compiles the counters out (they are never read).
-template <bool STATS>
+// CACHED: paths stop at their record vertex and append cache queries.
+template <bool STATS, bool CACHED>
 __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, DCams C, DRender R,
-                                                           float* __restrict__ image) {
+                                                           float* __restrict__ image, DNrcIO io) {
   __shared__ int stack[kStackDepth * kBlock];
   __shared__ LdsTables tab;
   load_tables(tab, s, P, nullptr);
@@ -952,8 +1018,10 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
   if (x < W && y < H) {
     Sink none{&tab, nullptr, nullptr};
     f3 acc;
-    render_pixel<false>(s, P, C, R, tab, cam, x, y, mk(0, 0, 0), stack + threadIdx.x, cnt, none,
-                        acc);
+    const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
+    render_pixel<CACHED ? MODE_CACHED : MODE_PRIMAL>(s, P, C, R, tab, cam, x, y,
+                                                     pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
+                                                     stack + threadIdx.x, cnt, none, io, acc);
     const float inv = 1.0f / (float)R.spp;
     float* out = image + 3 * (((size_t)cam * H + y) * W + x);
     out[0] = acc.x * inv;
@@ -987,7 +1055,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (nonzero(dL)) {
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
       f3 unused;
-      render_pixel<true>(s, P, C, R, tab, cam, x, y, dL, stack + threadIdx.x, cnt, sink, unused);
+      DNrcIO none_io = {};
+      render_pixel<MODE_ADJOINT>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
+                                 stack + threadIdx.x, cnt, sink, none_io, unused);
     }
   }
   __syncthreads();
@@ -999,6 +1069,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
   }
   if constexpr (STATS) flush_counters(R, cnt);
+}
+
+// Training paths of the radiance cache: path j (counter g = j) starts at the
+// pixel chosen by the first word of its camera block dim 2, and writes record
+// j (features, target) and valid[j].
+__global__ __launch_bounds__(kBlock) void k_nrc_records(DScene s, DParams P, DCams C, DRender R,
+                                                        int64_t n_paths, DNrcIO io) {
+  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ LdsTables tab;
+  load_tables(tab, s, P, nullptr);
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_paths) return;
+  const uint32_t n_pix = (uint32_t)((int64_t)C.n * C.width * C.height);
+  uint4 r = philox((uint32_t)j, (uint32_t)((uint64_t)j >> 32), 0xFFFFFFFFu, 2u, R.key0, R.key1);
+  const uint32_t pid = pick(r.x, n_pix);
+  const int cam = (int)(pid / ((uint32_t)C.width * C.height));
+  const int y = (int)((pid / C.width) % C.height), x = (int)(pid % C.width);
+  Counters cnt = {};
+  Sink none{&tab, nullptr, nullptr};
+  f3 unused;
+  render_pixel<MODE_TRAIN>(s, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
+                           stack + threadIdx.x, cnt, none, io, unused);
 }
 
 // Ray queries (closest / any) for tests and traversal measurements.
@@ -1084,7 +1177,8 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
                                               int64_t n, float lr, float b1, float b2, float eps,
-                                              float c1, float c2, float lo, float hi, int zero) {
+                                              float c1, float c2, float lo, float hi, int zero,
+                                              uint16_t* __restrict__ half_out) {
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * 256;
   for (; i < n; i += stride) {
@@ -1095,7 +1189,9 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
     m[i] = mi;
     v[i] = vi;
     float x = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    p[i] = fminf(fmaxf(x, lo), hi);
+    x = fminf(fmaxf(x, lo), hi);
+    p[i] = x;
+    if (half_out) half_out[i] = __half_as_ushort(__float2half_rn(x));
   }
 }
 
@@ -1106,12 +1202,30 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, float* image, hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  DNrcIO none = {};
   if (r.stats)
-    hipLaunchKernelGGL((k_render_forward<true>), grid, dim3(kBlock), 0, st, s, p, c, r,
-                       image);
+    hipLaunchKernelGGL((k_render_forward<true, false>), grid, dim3(kBlock), 0, st, s, p, c, r,
+                       image, none);
   else
-    hipLaunchKernelGGL((k_render_forward<false>), grid, dim3(kBlock), 0, st, s, p, c,
-                       r, image);
+    hipLaunchKernelGGL((k_render_forward<false, false>), grid, dim3(kBlock), 0, st, s, p, c,
+                       r, image, none);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& c,
+                                const DRender& r, float* image, const DNrcIO& io,
+                                hipStream_t st) {
+  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  hipLaunchKernelGGL((k_render_forward<false, true>), grid, dim3(kBlock), 0, st, s, p, c, r,
+                     image, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
+                              int64_t n_paths, const DNrcIO& io, hipStream_t st) {
+  int64_t blocks = (n_paths + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_nrc_records, dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c, r,
+                     n_paths, io);
   return hipGetLastError();
 }
 
@@ -1162,7 +1276,21 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n,
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p, g, m, v, n, o.lr,
-                     o.beta1, o.beta2, o.eps, (float)c1, (float)c2, o.lo, o.hi, o.zero_grad);
+                     o.beta1, o.beta2, o.eps, (float)c1, (float)c2, o.lo, o.hi, o.zero_grad,
+                     o.half_out);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, int64_t n_words, hipStream_t st) {
+  int64_t blocks = (n_words + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, n_words);
   return hipGetLastError();
 }
 

@@ -1,0 +1,637 @@
+// gfx950 kernels of the neural radiance cache: input encoding, the fused
+// BF16 MFMA network (forward, backward, training step) and query resolution.
+//
+// Network: 80 inputs -> 64 -> 64 -> 64 -> 64 -> 3, ReLU, no biases, weights
+// row-major [out][in] in one float array (FP32 master copy; kernels round to
+// BF16 when staging them in LDS).  Activations are BF16, products accumulate
+// in FP32 (v_mfma_f32_16x16x16_bf16).
+//
+// Register layout.  A wave works on tiles of 16 samples.  Weights are the A
+// operand (rows = output neurons, 16 per tile), samples the N dimension: lane
+// i holds A[i%16][4(i/16)+j], B[4(i/16)+j][i%16] and D[4(i/16)+j][i%16].  The
+// D tile of output neurons 16t..16t+15 is therefore exactly the B operand of
+// the next layer's k-step t, so activations never leave registers in the
+// forward pass; the encoding is computed directly into the B chunks of the
+// first layer (lane group g = i/16 computes inputs 16s + 4g .. 16s + 4g + 3).
+//
+// Encoding (80 inputs): a 16-level hash grid over the position normalised to
+// the scene box (2 FP16 features per entry, trilinear, dense indexing while
+// a level fits the table, else the Instant-NGP spatial hash), 16 real
+// spherical harmonics (bands 0-3) of the direction and of the normal, the
+// roughness and the albedo, zero padding.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "drt_internal.h"
+
+namespace drt {
+
+#define DEV __device__ __forceinline__
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kW0 = 0, kW1 = 64 * 80, kW2 = kW1 + 4096, kW3 = kW2 + 4096, kW4 = kW3 + 4096;
+constexpr int kW4Pad = 16 * 64;             // output layer padded to 16 rows in LDS
+constexpr int kLdsW = kW4 + kW4Pad;         // bf16 weights staged in LDS
+constexpr int kBlockN = 256;                // 4 waves per workgroup
+
+DEV uint16_t f2bf(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7F800000u) != 0x7F800000u) b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+DEV bf16x4 pack4(float a, float b, float c, float d) {
+  bf16x4 r;
+  r[0] = (short)f2bf(a);
+  r[1] = (short)f2bf(b);
+  r[2] = (short)f2bf(c);
+  r[3] = (short)f2bf(d);
+  return r;
+}
+DEV bf16x4 relu_pack(f32x4 v) {
+  return pack4(fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f));
+}
+DEV f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+DEV f32x4 zero4() {
+  f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  return z;
+}
+DEV bf16x4 zero_b() {
+  bf16x4 z = {0, 0, 0, 0};
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// weights in LDS
+// ---------------------------------------------------------------------------
+DEV void stage_weights(uint16_t* wl, const float* __restrict__ W) {
+  for (int i = threadIdx.x; i < kLdsW; i += blockDim.x) {
+    float v;
+    if (i < kW4) {
+      v = W[i];
+    } else {
+      int r = (i - kW4) / 64, c = (i - kW4) % 64;
+      v = r < 3 ? W[kW4 + r * 64 + c] : 0.f;
+    }
+    wl[i] = f2bf(v);
+  }
+}
+// A operand of W (rows 16t.., cols 16s..): 4 contiguous bf16 per lane
+DEV bf16x4 ldA(const uint16_t* w, int K, int t, int s, int lane) {
+  return *reinterpret_cast<const bf16x4*>(w + (16 * t + (lane & 15)) * K + 16 * s + 4 * (lane >> 4));
+}
+// A operand of W^T (rows = inputs 16t.., k = outputs 16s..)
+DEV bf16x4 ldAT(const uint16_t* w, int K, int t, int s, int lane) {
+  const uint16_t* p = w + (16 * s + 4 * (lane >> 4)) * K + 16 * t + (lane & 15);
+  bf16x4 r;
+  r[0] = (short)p[0];
+  r[1] = (short)p[K];
+  r[2] = (short)p[2 * K];
+  r[3] = (short)p[3 * K];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// encoding
+// ---------------------------------------------------------------------------
+struct GridLds {
+  int res[16];
+  int dense[16];
+};
+
+DEV void sh16_sel(float x, float y, float z, int g, float o[4]) {
+  const float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f;
+  const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.5462742152960396f;
+  const float c3a = 0.5900435899266435f, c3b = 2.890611442640554f, c3c = 0.4570457994644658f;
+  const float c3d = 0.3731763325901154f, c3e = 1.445305721320277f;
+  float v[16];
+  v[0] = c0;
+  v[1] = c1 * y;
+  v[2] = c1 * z;
+  v[3] = c1 * x;
+  v[4] = c2a * x * y;
+  v[5] = c2a * y * z;
+  v[6] = c2b * (3.f * z * z - 1.f);
+  v[7] = c2a * x * z;
+  v[8] = c2c * (x * x - y * y);
+  v[9] = c3a * y * (3.f * x * x - y * y);
+  v[10] = c3b * x * y * z;
+  v[11] = c3c * y * (5.f * z * z - 1.f);
+  v[12] = c3d * z * (5.f * z * z - 3.f);
+  v[13] = c3c * x * (5.f * z * z - 1.f);
+  v[14] = c3e * z * (x * x - y * y);
+  v[15] = c3a * x * (x * x - 3.f * y * y);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    o[j] = g == 0 ? v[j] : (g == 1 ? v[4 + j] : (g == 2 ? v[8 + j] : v[12 + j]));
+}
+
+// Trilinear corners of one level: index (entry of 2 features) and weight.
+DEV void level_corners(const DNrcNet& net, const GridLds& gl, int l, const float xn[3],
+                       uint32_t idx[8], float w[8]) {
+  const int N = gl.res[l];
+  int c0[3];
+  float fr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float pos = xn[a] * (float)N;
+    int c = (int)floorf(pos);
+    c = min(max(c, 0), N - 1);
+    c0[a] = c;
+    fr[a] = pos - (float)c;
+  }
+  const uint32_t mask = (1u << net.log2_table) - 1u;
+  const uint32_t n1 = (uint32_t)(N + 1);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint32_t cx = c0[0] + (k & 1), cy = c0[1] + ((k >> 1) & 1), cz = c0[2] + ((k >> 2) & 1);
+    w[k] = ((k & 1) ? fr[0] : 1.f - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.f - fr[1]) *
+           (((k >> 2) & 1) ? fr[2] : 1.f - fr[2]);
+    idx[k] = gl.dense[l] ? cx + cy * n1 + cz * n1 * n1
+                         : ((cx * 1u) ^ (cy * 2654435761u) ^ (cz * 805459861u)) & mask;
+  }
+}
+
+DEV void normalise(const DNrcNet& net, const float* rec, float xn[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xn[a] = fminf(fmaxf((rec[a] - net.lo[a]) * net.inv_ext[a], 0.f), 1.f);
+}
+
+DEV void level_features(const DNrcNet& net, const GridLds& gl, int l, const float xn[3],
+                        float& f0, float& f1) {
+  uint32_t idx[8];
+  float w[8];
+  level_corners(net, gl, l, xn, idx, w);
+  const uint32_t* tab = net.grid + ((size_t)l << net.log2_table);
+  f0 = 0.f;
+  f1 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint32_t e = tab[idx[k]];
+    f0 += w[k] * __half2float(__ushort_as_half((unsigned short)(e & 0xFFFFu)));
+    f1 += w[k] * __half2float(__ushort_as_half((unsigned short)(e >> 16)));
+  }
+}
+
+// The 20 inputs of lane group g of a sample (B chunks s = 0..4), FP32.
+DEV void encode_lane(const DNrcNet& net, const GridLds& gl, const float* rec, bool valid, int g,
+                     float in[5][4]) {
+  if (!valid) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) in[s][j] = 0.f;
+    return;
+  }
+  float xn[3];
+  normalise(net, rec, xn);
+  // chunk 0: hash features 4g..4g+3 = levels 2g, 2g+1; chunk 1: levels 8+2g, 9+2g
+  level_features(net, gl, 2 * g, xn, in[0][0], in[0][1]);
+  level_features(net, gl, 2 * g + 1, xn, in[0][2], in[0][3]);
+  level_features(net, gl, 8 + 2 * g, xn, in[1][0], in[1][1]);
+  level_features(net, gl, 9 + 2 * g, xn, in[1][2], in[1][3]);
+  sh16_sel(rec[3], rec[4], rec[5], g, in[2]);
+  sh16_sel(rec[6], rec[7], rec[8], g, in[3]);
+  in[4][0] = g == 0 ? rec[9] : 0.f;
+  in[4][1] = g == 0 ? rec[10] : 0.f;
+  in[4][2] = g == 0 ? rec[11] : 0.f;
+  in[4][3] = g == 0 ? rec[12] : 0.f;
+}
+
+DEV void load_grid_tables(GridLds& gl, const DNrcNet& net) {
+  if (threadIdx.x < 16) {
+    gl.res[threadIdx.x] = net.res[threadIdx.x];
+    gl.dense[threadIdx.x] = net.dense[threadIdx.x];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// network forward for one 16-sample tile
+// ---------------------------------------------------------------------------
+struct Acts {
+  bf16x4 h0[5], h1[4], h2[4], h3[4], h4[4];
+};
+
+DEV void hidden_layer(const uint16_t* w, int K, const bf16x4* in, int ksteps, bf16x4* out, int lane) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < ksteps; ++s) acc = mfma(ldA(w, K, t, s, lane), in[s], acc);
+    out[t] = relu_pack(acc);
+  }
+}
+
+// Y: lane group 0 holds the 3 outputs of its sample in Y[0..2]
+DEV f32x4 forward_tile(const uint16_t* wl, Acts& A, int lane) {
+  hidden_layer(wl + kW0, 80, A.h0, 5, A.h1, lane);
+  hidden_layer(wl + kW1, 64, A.h1, 4, A.h2, lane);
+  hidden_layer(wl + kW2, 64, A.h2, 4, A.h3, lane);
+  hidden_layer(wl + kW3, 64, A.h3, 4, A.h4, lane);
+  f32x4 y = zero4();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) y = mfma(ldA(wl + kW4, 64, 0, s, lane), A.h4[s], y);
+  return y;
+}
+
+// ---------------------------------------------------------------------------
+// backward for one tile: dW accumulated into LDS (FP32), dX of inputs 0..31
+// ---------------------------------------------------------------------------
+DEV bf16x4 mask_pack(f32x4 g, bf16x4 h) {
+  return pack4(h[0] != 0 ? g[0] : 0.f, h[1] != 0 ? g[1] : 0.f, h[2] != 0 ? g[2] : 0.f,
+               h[3] != 0 ? g[3] : 0.f);
+}
+
+// stage a [features][16 samples] block from B-layout chunks (lane holds
+// features 16c + 4g + j of sample lane%16)
+DEV void stage(uint16_t* st, const bf16x4* chunks, int n_chunks, int lane) {
+  const int g = lane >> 4, smp = lane & 15;
+  // the previous reads of this wave's staging block are complete (LDS is in
+  // order per wave); keep the compiler from moving the accesses across
+  __builtin_amdgcn_wave_barrier();
+  for (int c = 0; c < n_chunks; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[(16 * c + 4 * g + j) * 16 + smp] = (uint16_t)chunks[c][j];
+  __builtin_amdgcn_wave_barrier();
+}
+// operand of a staged block: rows 16u.. (lane%16), k = samples 4g..4g+3
+DEV bf16x4 ld_staged(const uint16_t* st, int u, int lane) {
+  return *reinterpret_cast<const bf16x4*>(st + (16 * u + (lane & 15)) * 16 + 4 * (lane >> 4));
+}
+
+// dW[out][in] += sum over the tile's samples of dH[s][out] H[s][in]
+DEV void accumulate_dw(float* dwl, int K, int out_tiles, int out_rows, const uint16_t* st_dh,
+                       const uint16_t* st_h, int lane) {
+  const int g = lane >> 4;
+  for (int t = 0; t < out_tiles; ++t) {
+    bf16x4 a = ld_staged(st_dh, t, lane);
+    for (int u = 0; u < K / 16; ++u) {
+      f32x4 d = mfma(a, ld_staged(st_h, u, lane), zero4());
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int r = 16 * t + 4 * g + j;
+        if (r < out_rows && d[j] != 0.f) atomicAdd(dwl + r * K + 16 * u + (lane & 15), d[j]);
+      }
+    }
+  }
+}
+
+// dY: lane group 0 holds the output gradients (rows 0..2) of its sample.
+// Returns dX chunks 0, 1 (inputs 0..31) in D layout.
+DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts& A, f32x4 dy,
+                       f32x4 dx[2], int lane) {
+  const int g = lane >> 4;
+  bf16x4 dyb = g == 0 ? pack4(dy[0], dy[1], dy[2], 0.f) : zero_b();
+  uint16_t* st_dh = st;             // [64][16]
+  uint16_t* st_h = st + 64 * 16;    // [80][16]
+  // output layer
+  stage(st_dh, &dyb, 1, lane);
+  stage(st_h, A.h4, 4, lane);
+  accumulate_dw(dwl + kW4, 64, 1, 3, st_dh, st_h, lane);
+  bf16x4 g4[4], g3[4], g2[4], g1[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
+  // hidden layers 3, 2, 1
+  stage(st_dh, g4, 4, lane);
+  stage(st_h, A.h3, 4, lane);
+  accumulate_dw(dwl + kW3, 64, 4, 64, st_dh, st_h, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW3, 64, t, s, lane), g4[s], acc);
+    g3[t] = mask_pack(acc, A.h3[t]);
+  }
+  stage(st_dh, g3, 4, lane);
+  stage(st_h, A.h2, 4, lane);
+  accumulate_dw(dwl + kW2, 64, 4, 64, st_dh, st_h, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW2, 64, t, s, lane), g3[s], acc);
+    g2[t] = mask_pack(acc, A.h2[t]);
+  }
+  stage(st_dh, g2, 4, lane);
+  stage(st_h, A.h1, 4, lane);
+  accumulate_dw(dwl + kW1, 64, 4, 64, st_dh, st_h, lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
+    g1[t] = mask_pack(acc, A.h1[t]);
+  }
+  // input layer
+  stage(st_dh, g1, 4, lane);
+  stage(st_h, A.h0, 5, lane);
+  accumulate_dw(dwl + kW0, 80, 4, 64, st_dh, st_h, lane);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
+    dx[t] = acc;
+  }
+  (void)g;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// B chunks of a tile from explicit inputs x [n][80] (rounded to BF16)
+DEV void load_inputs(const float* __restrict__ x, int64_t n, int64_t sample, int lane, bf16x4 h0[5]) {
+  const int g = lane >> 4;
+  for (int s = 0; s < 5; ++s) {
+    if (sample < n) {
+      const float* p = x + sample * 80 + 16 * s + 4 * g;
+      h0[s] = pack4(p[0], p[1], p[2], p[3]);
+    } else {
+      h0[s] = zero_b();
+    }
+  }
+}
+
+// Network only: y = net(x) for explicit inputs.
+__global__ __launch_bounds__(kBlockN) void k_nrc_forward(const float* __restrict__ W,
+                                                        const float* __restrict__ x, int64_t n,
+                                                        float* __restrict__ y) {
+  __shared__ uint16_t wl[kLdsW];
+  stage_weights(wl, W);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    Acts A;
+    load_inputs(x, n, sample, lane, A.h0);
+    f32x4 out = forward_tile(wl, A, lane);
+    if ((lane >> 4) == 0 && sample < n) {
+      y[3 * sample] = out[0];
+      y[3 * sample + 1] = out[1];
+      y[3 * sample + 2] = out[2];
+    }
+  }
+}
+
+// Network only: dW += d<dy, y>/dW, dx = d<dy, y>/dx (inputs 0..31; others 0).
+__global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restrict__ W,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ dy, int64_t n,
+                                                         float* __restrict__ dW,
+                                                         float* __restrict__ dx) {
+  __shared__ uint16_t wl[kLdsW];
+  __shared__ float dwl[kW4 + 3 * 64];
+  __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
+  stage_weights(wl, W);
+  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) dwl[i] = 0.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    Acts A;
+    load_inputs(x, n, sample, lane, A.h0);
+    forward_tile(wl, A, lane);
+    f32x4 d = zero4();
+    if (g == 0 && sample < n) {
+      d[0] = dy[3 * sample];
+      d[1] = dy[3 * sample + 1];
+      d[2] = dy[3 * sample + 2];
+    }
+    f32x4 dxv[2];
+    backward_tile(wl, dwl, st[threadIdx.x >> 6], A, d, dxv, lane);
+    if (dx && sample < n) {
+      for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dx[sample * 80 + 16 * t + 4 * g + j] = t < 2 ? dxv[t][j] : 0.f;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x)
+    if (dwl[i] != 0.f) atomicAdd(dW + i, dwl[i]);
+}
+
+// Encoding only: records [n][16] -> x [n][80] (FP32, before BF16 rounding).
+__global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float* __restrict__ rec,
+                                                       int64_t n, float* __restrict__ x) {
+  __shared__ GridLds gl;
+  load_grid_tables(gl, net);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    bool valid = sample < n;
+    float in[5][4];
+    encode_lane(net, gl, valid ? rec + sample * NRC_REC : rec, valid, g, in);
+    if (valid)
+      for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[sample * 80 + 16 * s + 4 * g + j] = in[s][j];
+  }
+}
+
+// Cache queries: image[pixel] += beta * max(C(record), 0) / spp.
+__global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float* __restrict__ W,
+                                                      const float* __restrict__ q,
+                                                      const int* __restrict__ qpix,
+                                                      const int* __restrict__ count,
+                                                      int64_t capacity, float inv_spp,
+                                                      float* __restrict__ image) {
+  __shared__ uint16_t wl[kLdsW];
+  __shared__ GridLds gl;
+  stage_weights(wl, W);
+  load_grid_tables(gl, net);
+  __syncthreads();
+  const int64_t n = min((int64_t)*count, capacity);
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    bool valid = sample < n;
+    const float* rec = q + (valid ? sample : 0) * NRC_REC;
+    float in[5][4];
+    encode_lane(net, gl, rec, valid, g, in);
+    Acts A;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) A.h0[s] = pack4(in[s][0], in[s][1], in[s][2], in[s][3]);
+    f32x4 y = forward_tile(wl, A, lane);
+    if (g == 0 && valid) {
+      float* px = image + 3 * (size_t)qpix[sample];
+      float c0 = rec[13] * fmaxf(y[0], 0.f) * inv_spp;
+      float c1 = rec[14] * fmaxf(y[1], 0.f) * inv_spp;
+      float c2 = rec[15] * fmaxf(y[2], 0.f) * inv_spp;
+      if (c0 != 0.f) atomicAdd(px, c0);
+      if (c1 != 0.f) atomicAdd(px + 1, c1);
+      if (c2 != 0.f) atomicAdd(px + 2, c2);
+    }
+  }
+}
+
+// One training pass over records [n][16] with valid flags: relative-L2 loss
+// (mean over valid records and channels), dW and hash-grid gradients
+// accumulated (FP32 atomics), loss added to loss[0].
+__global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float* __restrict__ W,
+                                                      const float* __restrict__ rec,
+                                                      const int* __restrict__ valid,
+                                                      const int* __restrict__ count, int64_t n,
+                                                      float* __restrict__ dW,
+                                                      float* __restrict__ dgrid,
+                                                      float* __restrict__ loss) {
+  __shared__ uint16_t wl[kLdsW];
+  __shared__ float dwl[kW4 + 3 * 64];
+  __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
+  __shared__ GridLds gl;
+  __shared__ float loss_acc;
+  stage_weights(wl, W);
+  load_grid_tables(gl, net);
+  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) dwl[i] = 0.f;
+  if (threadIdx.x == 0) loss_acc = 0.f;
+  __syncthreads();
+  const int n_valid = *count;
+  const float inv = n_valid > 0 ? 1.0f / (3.0f * (float)n_valid) : 0.f;
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  float my_loss = 0.f;
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    bool ok = sample < n && valid[sample] != 0;
+    const float* r = rec + (sample < n ? sample : 0) * NRC_REC;
+    float in[5][4];
+    encode_lane(net, gl, r, ok, g, in);
+    Acts A;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) A.h0[s] = pack4(in[s][0], in[s][1], in[s][2], in[s][3]);
+    f32x4 y = forward_tile(wl, A, lane);
+    f32x4 d = zero4();
+    if (g == 0 && ok) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float den = y[c] * y[c] + 0.01f;
+        float e = y[c] - r[13 + c];
+        my_loss += e * e / den;
+        d[c] = 2.0f * e / den * inv;
+      }
+    }
+    f32x4 dx[2];
+    backward_tile(wl, dwl, st[threadIdx.x >> 6], A, d, dx, lane);
+    if (ok) {
+      // this lane holds d/d inputs {4g+j} and {16+4g+j}: levels 2g, 2g+1, 8+2g, 9+2g
+      float xn[3];
+      normalise(net, r, xn);
+      const int lv[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = lv[q];
+        const float d0 = dx[q >> 1][2 * (q & 1)], d1 = dx[q >> 1][2 * (q & 1) + 1];
+        if (d0 == 0.f && d1 == 0.f) continue;
+        uint32_t idx[8];
+        float w[8];
+        level_corners(net, gl, l, xn, idx, w);
+        float* tab = dgrid + ((size_t)l << net.log2_table) * 2;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (w[k] == 0.f) continue;
+          atomicAdd(tab + 2 * (size_t)idx[k], w[k] * d0);
+          atomicAdd(tab + 2 * (size_t)idx[k] + 1, w[k] * d1);
+        }
+      }
+    }
+  }
+  if (my_loss != 0.f) atomicAdd(&loss_acc, my_loss * inv);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x)
+    if (dwl[i] != 0.f) atomicAdd(dW + i, dwl[i]);
+  if (threadIdx.x == 0 && loss_acc != 0.f) atomicAdd(loss, loss_acc);
+}
+
+// Hash-grid gradient only: dgrid += trilinear scatter of dx [n][80] (inputs
+// 0..31) at the records' positions.  One lane per (record, level).
+__global__ __launch_bounds__(kBlockN) void k_nrc_grid_backward(DNrcNet net,
+                                                              const float* __restrict__ rec,
+                                                              const float* __restrict__ dx,
+                                                              int64_t n, float* __restrict__ dgrid) {
+  __shared__ GridLds gl;
+  load_grid_tables(gl, net);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x;
+  if (i >= n * 16) return;
+  const int64_t r = i / 16;
+  const int l = (int)(i % 16);
+  const float d0 = dx[r * 80 + 2 * l], d1 = dx[r * 80 + 2 * l + 1];
+  if (d0 == 0.f && d1 == 0.f) return;
+  float xn[3];
+  normalise(net, rec + r * NRC_REC, xn);
+  uint32_t idx[8];
+  float w[8];
+  level_corners(net, gl, l, xn, idx, w);
+  float* tab = dgrid + ((size_t)l << net.log2_table) * 2;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (w[k] == 0.f) continue;
+    atomicAdd(tab + 2 * (size_t)idx[k], w[k] * d0);
+    atomicAdd(tab + 2 * (size_t)idx[k] + 1, w[k] * d1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_nrc_grid_backward(const DNrcNet& net, const float* rec, const float* dx,
+                                    int64_t n, float* dgrid, hipStream_t st) {
+  int64_t blocks = (n * 16 + kBlockN - 1) / kBlockN;
+  hipLaunchKernelGGL(k_nrc_grid_backward, dim3((unsigned)blocks), dim3(kBlockN), 0, st, net, rec, dx,
+                     n, dgrid);
+  return hipGetLastError();
+}
+static unsigned grid_for(int64_t n, int64_t max_blocks) {
+  int64_t tiles = (n + 15) / 16;
+  int64_t blocks = (tiles + (kBlockN / 64) - 1) / (kBlockN / 64);
+  if (blocks < 1) blocks = 1;
+  if (blocks > max_blocks) blocks = max_blocks;
+  return (unsigned)blocks;
+}
+
+hipError_t launch_nrc_forward(const float* W, const float* x, int64_t n, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_forward, dim3(grid_for(n, 4096)), dim3(kBlockN), 0, st, W, x, n, y);
+  return hipGetLastError();
+}
+hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n,
+                               float* dW, float* dx, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_backward, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, W, x, dy, n,
+                     dW, dx);
+  return hipGetLastError();
+}
+hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_encode, dim3(grid_for(n, 4096)), dim3(kBlockN), 0, st, net, rec, n, x);
+  return hipGetLastError();
+}
+hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
+                            const int* count, int64_t capacity, float inv_spp, float* image,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_infer, dim3(grid_for(capacity, 4096)), dim3(kBlockN), 0, st, net, W, q,
+                     qpix, count, capacity, inv_spp, image);
+  return hipGetLastError();
+}
+hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+                            const int* count, int64_t n, float* dW, float* dgrid, float* loss,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_train, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, net, W, rec,
+                     valid, count, n, dW, dgrid, loss);
+  return hipGetLastError();
+}
+
+}  // namespace drt

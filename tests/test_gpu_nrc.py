@@ -1,0 +1,252 @@
+"""Radiance cache on the GPU vs the FP64 oracle (BF16-emulation mode where
+the GPU computes in BF16), through the C ABI.
+
+Tolerances: the encoding's hash-grid features within 2 x 2.4e-7 x N_l + 1e-6
+at level resolution N_l (a float32 position's error scaled to the level), the
+other inputs within 2e-6; network outputs and gradients ||g - o|| <= 2e-3 ||o||
+against the oracle's BF16 emulation (rounding points are the same; FP32 vs
+FP64 accumulation can flip an individual BF16 rounding, 1 ulp = 2^-8
+relative); the fused training pass within 3x the oracle's own change under
+2-ulp float32 position perturbations; records and images as in
+test_gpu_parity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from test_gpu_parity import check_image
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _drt():
+    import paper_2202_01284_amd as drt
+    return drt
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _records(cfg, n, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array(cfg["bbox_lo"]), np.array(cfg["bbox_hi"])
+    f = np.zeros((n, 16))
+    f[:, 0:3] = lo + rng.random((n, 3)) * (hi - lo)
+    for a in (3, 6):
+        v = rng.normal(size=(n, 3))
+        f[:, a:a + 3] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    f[:, 9] = rng.uniform(0.05, 1.0, n)
+    f[:, 10:13] = rng.uniform(0, 1, (n, 3))
+    f[:, 13:16] = rng.uniform(0, 2, (n, 3))
+    return f.astype(np.float32)
+
+
+@pytest.mark.parametrize("log2_table", [19, 12])
+def test_encode_vs_oracle(log2_table):
+    drt = _drt()
+    sc = scenes.cornell()
+    cfg = scenes.nrc_config(sc, log2_table=log2_table)
+    rng = np.random.default_rng(1)
+    grid = rng.uniform(-1, 1, (16, 1 << log2_table, 2)).astype(np.float16)
+    rec = _records(cfg, 5000, 2)
+    x = drt.nrc_encode(cfg, torch.from_numpy(grid.reshape(-1)).cuda(),
+                       torch.from_numpy(rec).cuda()).cpu().numpy()
+    xo = oracle.nrc_encode(rec[:, :13].astype(np.float64), cfg, grid.astype(np.float32))
+    err = np.abs(x - xo)
+    # a float32 position is off by ~1e-7 of the box; at resolution N that moves
+    # trilinear weights by ~N 1e-7 and a feature by that times the corner spread (<= 2)
+    res = np.array([oracle.level_res(cfg, l) for l in range(16)])
+    tol = np.concatenate([np.repeat(2 * 2.4e-7 * res, 2) + 1e-6, np.full(48, 2e-6)])
+    print("encode max err", err.max(), "max err/tol", (err / tol).max(), flush=True)
+    assert np.all(err <= tol)
+
+
+def test_grid_backward_vs_oracle():
+    drt = _drt()
+    sc = scenes.cornell()
+    cfg = scenes.nrc_config(sc, log2_table=14)
+    rec = _records(cfg, 3000, 3)
+    dx = np.zeros((3000, 80), np.float32)
+    dx[:, :32] = np.random.default_rng(4).normal(size=(3000, 32))
+    g = torch.zeros(16 * (1 << 14) * 2, dtype=torch.float32, device="cuda")
+    drt.nrc_grid_backward(cfg, torch.from_numpy(rec).cuda(), torch.from_numpy(dx).cuda(), g)
+    go = oracle.nrc_grid_backward(rec[:, :13].astype(np.float64), cfg, dx.astype(np.float64))
+    r = rel(g.cpu().numpy(), go)
+    print("grid backward rel", r, flush=True)
+    # float32 normalisation: a scaled position at resolution N is off by up to
+    # ~N 1.2e-7 of a cell, and so is each trilinear weight (N <= 2048)
+    assert r <= 2.5e-4
+
+
+def test_network_forward_vs_bf16_oracle():
+    drt = _drt()
+    sc = scenes.cornell()
+    cfg = scenes.nrc_config(sc)
+    W, _ = scenes.nrc_init(cfg, seed=3)
+    rng = np.random.default_rng(4)
+    n = 4096 + 7                                   # many tiles and a ragged tail
+    x = rng.normal(size=(n, 80)).astype(np.float32)
+    x[:, 68:] = 0
+    y = drt.nrc_forward(torch.from_numpy(W).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    yo = oracle.mlp_forward(x.astype(np.float64), W.astype(np.float64), emu=True)
+    r = rel(y, yo)
+    print("forward rel", r, "vs fp64", rel(y, oracle.mlp_forward(x, W.astype(np.float64))), flush=True)
+    assert r <= 2e-3
+
+
+def test_network_backward_vs_bf16_oracle():
+    drt = _drt()
+    sc = scenes.cornell()
+    cfg = scenes.nrc_config(sc)
+    W, _ = scenes.nrc_init(cfg, seed=5)
+    rng = np.random.default_rng(6)
+    n = 1024 + 9
+    x = rng.normal(size=(n, 80)).astype(np.float32)
+    x[:, 68:] = 0
+    dy = rng.normal(size=(n, 3)).astype(np.float32)
+    dW, dx = drt.nrc_backward(torch.from_numpy(W).cuda(), torch.from_numpy(x).cuda(),
+                              torch.from_numpy(dy).cuda())
+    dWo, dxo = oracle.mlp_backward(x.astype(np.float64), W.astype(np.float64), dy.astype(np.float64),
+                                   emu=True)
+    dW, dx = dW.cpu().numpy(), dx.cpu().numpy()
+    offs = [0, 5120, 9216, 13312, 17408, 17600]
+    for l in range(5):
+        r = rel(dW[offs[l]:offs[l + 1]], dWo[offs[l]:offs[l + 1]])
+        print(f"dW layer {l} rel {r:.3g}", flush=True)
+        assert r <= 2e-3
+    r = rel(dx[:, :32], dxo[:, :32])
+    print("dx rel", r, flush=True)
+    assert r <= 2e-3
+    assert np.all(dx[:, 32:] == 0)
+
+
+def test_collect_vs_oracle():
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64))
+    cfg = scenes.nrc_config(sc)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    rough = torch.from_numpy(sc.roughness).cuda()
+    n = 8192
+    rec, valid, count = drt.nrc_collect(gs, tex, rough, sc.cameras, cfg, n, seed=31)
+    rec, valid, count = rec.cpu().numpy(), valid.cpu().numpy().astype(bool), int(count.item())
+    feat, tgt, vo, amb = oracle.OracleScene(sc).train_records(n, K=3, max_depth=6, rr_depth=3, seed=31)
+    ok = ~amb
+    print("records valid", valid.sum(), "ambiguous", amb.sum(), flush=True)
+    assert count == valid.sum()
+    np.testing.assert_array_equal(valid[ok], vo[ok])
+    m = ok & vo
+    np.testing.assert_allclose(rec[m, :13], feat[m], rtol=1e-3, atol=1e-4)
+    err = np.abs(rec[m, 13:16] - tgt[m])
+    good = (err <= 1e-3 * np.abs(tgt[m]) + 1e-5).all(1)
+    print("target pass", good.mean(), flush=True)
+    assert good.mean() >= 0.999
+
+
+def test_training_pass_vs_oracle():
+    """Loss, network gradient and hash-grid gradient of one fused training pass
+    on oracle-made records.  The network is scaled so its outputs sit near the
+    targets: the relative-L2 gradient 2(y - t)/(y^2 + 0.01) amplifies BF16
+    input-rounding flips (from FP32 vs FP64 encodings) for outputs near 0."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64))
+    cfg = scenes.nrc_config(sc, log2_table=14)
+    W, grid = scenes.nrc_init(cfg, seed=8)
+    W = W.copy()
+    W[17408:] = np.abs(W[17408:]) * 4.0          # positive, larger output layer
+    rng = np.random.default_rng(9)
+    grid = (grid.astype(np.float32) + rng.uniform(-0.5, 0.5, grid.shape)).astype(np.float16)
+    feat, tgt, valid, _ = oracle.OracleScene(sc).train_records(4096 + 5, K=3, max_depth=6, rr_depth=3,
+                                                               seed=12)
+    rec = np.concatenate([feat, tgt], 1).astype(np.float32)
+    dWg = torch.zeros(17600, dtype=torch.float32, device="cuda")
+    dGg = torch.zeros(grid.size, dtype=torch.float32, device="cuda")
+    cnt = torch.tensor([int(valid.sum())], dtype=torch.int32, device="cuda")
+    loss = drt.nrc_train(cfg, torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda(),
+                         torch.from_numpy(rec).cuda(),
+                         torch.from_numpy(valid.astype(np.int32)).cuda(), cnt, dWg, dGg)
+    # oracle: same records (as float32), BF16 emulation
+    f64 = rec[valid, :13].astype(np.float64)
+    t64 = rec[valid, 13:16].astype(np.float64)
+    x = oracle.nrc_encode(f64, cfg, grid.astype(np.float32))
+    y = oracle.mlp_forward(x, W.astype(np.float64), emu=True)
+    lo, dy = oracle.rel_l2(y, t64)
+    dWo, dx = oracle.mlp_backward(x, W.astype(np.float64), dy, emu=True)
+    dGo = oracle.nrc_grid_backward(f64, cfg, dx)
+    # Sensitivity of the oracle itself to float32-sized position errors: the
+    # GPU encodes in FP32 (off by up to 1e-4 at the finest level), which flips
+    # some BF16 roundings of the network inputs; the hash-grid gradient is the
+    # most sensitive output.  Perturb positions by up to 2 float32 ulps.
+    rng2 = np.random.default_rng(13)
+    f64p = f64.copy()
+    f64p[:, :3] *= 1 + rng2.uniform(-2, 2, f64p[:, :3].shape) * 2.0 ** -23
+    xp = oracle.nrc_encode(f64p, cfg, grid.astype(np.float32))
+    yp = oracle.mlp_forward(xp, W.astype(np.float64), emu=True)
+    _, dyp = oracle.rel_l2(yp, t64)
+    dWp, dxp = oracle.mlp_backward(xp, W.astype(np.float64), dyp, emu=True)
+    dGp = oracle.nrc_grid_backward(f64p, cfg, dxp)
+    sens_w, sens_g = rel(dWp, dWo), rel(dGp, dGo)
+    rw, rg = rel(dWg.cpu().numpy(), dWo), rel(dGg.cpu().numpy(), dGo)
+    print(f"loss {loss.item()} {lo}; dW rel {rw:.3g} (oracle ulp-sensitivity {sens_w:.3g}); "
+          f"dgrid rel {rg:.3g} (oracle ulp-sensitivity {sens_g:.3g})", flush=True)
+    assert abs(loss.item() - lo) <= 2e-3 * lo
+    assert rw <= max(3 * sens_w, 2e-3)
+    assert rg <= max(3 * sens_g, 2e-3)
+
+
+def test_cached_render_vs_oracle():
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64))
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    img = drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+                                    torch.from_numpy(grid.reshape(-1)).cuda(), spp=4, seed=5)
+    ref, amb = oracle.OracleScene(sc).render_cached(cfg, grid.astype(np.float32), W.astype(np.float64),
+                                                    K=3, spp=4, max_depth=6, rr_depth=3, seed=5,
+                                                    emu=True, ambiguity=True)
+    check_image(img.cpu().numpy(), ref, "cached render", amb)
+
+
+def test_trained_cache_beats_untrained():
+    """Online training on the GPU (records from plain paths, relative-L2,
+    Adam 1e-2).  The training loss falls, and the cache's bias -- measured on
+    8x8-block averages of a 256-spp cached render against a 4096-spp plain
+    reference, where the variance has been averaged away -- is far smaller
+    after training than for the untrained cache (which drops the radiance
+    past the truncation vertex)."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=64, height=64)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    ref = drt.render_forward(gs, tex, None, sc.cameras, 4096, 6, 3, seed=1284).cpu().numpy()
+    cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
+    spp = 256
+
+    def blocks(img):
+        return img.reshape(8, 8, 8, 8, 3).mean((1, 3))
+
+    def bias(img):
+        return float(np.sqrt(((blocks(img) - blocks(ref)) ** 2).mean()))
+
+    plain = bias(drt.render_forward(gs, tex, None, sc.cameras, spp, 6, 3, seed=77).cpu().numpy())
+    before = bias(cache.render(gs, tex, None, sc.cameras, spp, seed=77).cpu().numpy())
+    losses = []
+    for f in range(200):
+        losses.append(cache.train_frame(gs, tex, None, sc.cameras, seed=1000 + f).item())
+    after = bias(cache.render(gs, tex, None, sc.cameras, spp, seed=77).cpu().numpy())
+    print(f"8x8-block rms error at {spp} spp: plain {plain:.4g} untrained cache {before:.4g} "
+          f"trained cache {after:.4g}; loss {np.mean(losses[:10]):.4g} -> {np.mean(losses[-10:]):.4g}",
+          flush=True)
+    assert np.mean(losses[-10:]) < 0.9 * np.mean(losses[:10])
+    assert after < 0.5 * before
