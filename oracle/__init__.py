@@ -444,5 +444,34 @@ def _train_records(self, n_paths, K=3, cams=None, max_depth=6, rr_depth=3, flags
     return feat, tgt, valid.astype(bool), amb.astype(bool)
 
 
+def _adjoint_cached(self, cfg, grid, W, adj, K=3, cams=None, spp=4, max_depth=6, rr_depth=3,
+                    flags=0, seed=2, pixel_ids=None, emu=True, textures=None, roughness=None,
+                    threads=None):
+    """Gradient of sum_p <adj_p, I_p> for the cached estimator (cache output
+    detached): (list of texture grads, roughness grad)."""
+    cams = self.sc.cameras if cams is None else cams
+    ca = cam_array(cams)
+    Wd, H = cams[0].width, cams[0].height
+    adj = np.asarray(adj, np.float64)
+    if pixel_ids is None:
+        pixel_ids = np.arange(len(cams) * Wd * H, dtype=np.int64)
+    pixel_ids = np.ascontiguousarray(pixel_ids, np.int64)
+    adj = np.ascontiguousarray(adj.reshape(-1, 3), np.float64)
+    assert adj.shape[0] == pixel_ids.size
+    texs, tptr, rough = self._params(textures, roughness)
+    gtex = [np.zeros(t.shape, np.float64) for t in texs]
+    gptr = (_vp * max(1, len(gtex)))(*[_p(g) for g in gtex])
+    grough = np.zeros(max(1, len(self.sc.roughness)), np.float64)
+    g = np.ascontiguousarray(grid, np.float32).reshape(-1)
+    Wv = np.ascontiguousarray(W, np.float64)
+    lib().oracle_adjoint_cached(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)), _c_int(spp),
+                                _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
+                                _c_int(K), _p(nrc_cfg_array(cfg)), _p(g), _p(Wv),
+                                _c_int(1 if emu else 0), _c_i64(pixel_ids.size), _p(pixel_ids),
+                                _p(adj), _c_int(threads or n_threads_default()), gptr, _p(grough))
+    return gtex, grough[:len(self.sc.roughness)]
+
+
 OracleScene.render_cached = _render_cached
+OracleScene.adjoint_cached = _adjoint_cached
 OracleScene.train_records = _train_records

@@ -1785,6 +1785,68 @@ void oracle_render_cached(void* h, const float* const* textures, const float* ro
   });
 }
 
+// Reverse-mode gradient of the cached estimator (same adjoint convention as
+// oracle_adjoint, reverse sweep).  The cache output is detached: the term
+// beta * max(C, 0) at the record vertex enters the sweep like emission found
+// there, so it reaches earlier vertices' BSDF derivatives through beta, and
+// nothing flows through the network or its inputs.
+void oracle_adjoint_cached(void* h, const float* const* textures, const float* roughness,
+                           const double* cams, int n_cams, int spp, int max_depth, int rr_depth,
+                           uint32_t flags, uint64_t seed, int K, const double* cfg,
+                           const float* grid, const double* W, int emu, int64_t n_pix,
+                           const int64_t* pixel_ids, const double* adj, int n_threads,
+                           double* const* grad_tex, double* grad_rough) {
+  const Scene& s = *(Scene*)h;
+  Params P{textures, roughness};
+  Opts opt{spp, max_depth, rr_depth, flags, seed};
+  GridCfg g = grid_cfg(cfg);
+  std::vector<Cam> cs;
+  for (int c = 0; c < n_cams; ++c) cs.push_back(make_cam(cams + 12 * c));
+  const int Wd = cs[0].W, Ht = cs[0].H;
+  int nth = std::max(1, n_threads);
+  std::vector<GradAcc> accs(nth);
+  parallel_for(n_pix, nth, [&](int t, int64_t i) {
+    int64_t pid = pixel_ids[i];
+    int cam = (int)(pid / ((int64_t)Wd * Ht));
+    int y = (int)((pid / Wd) % Ht), x = (int)(pid % Wd);
+    RGB dL(adj[3 * i] / spp, adj[3 * i + 1] / spp, adj[3 * i + 2] / spp);
+    if (is_zero(dL)) return;
+    std::vector<VertexRec> recs;
+    for (int sidx = 0; sidx < spp; ++sidx) {
+      uint64_t gi = (uint64_t)pid * spp + sidx;
+      Stream st = make_stream(seed, gi);
+      V3 o, d;
+      camera_ray(cs[cam], st, x, y, &o, &d);
+      CacheHook ch;
+      ch.K = K;
+      ch.mode = 0;
+      trace_sample(s, P, opt, st, o, d, &recs, nullptr, &ch);
+      if (ch.has) {
+        double enc[80], yv[3];
+        encode(g, grid, ch.feat, enc);
+        mlp_forward(W, enc, emu != 0, nullptr, yv);
+        RGB c;
+        for (int ci = 0; ci < 3; ++ci) c[ci] = ch.beta[ci] * std::max(yv[ci], 0.0);
+        recs.back().emit = recs.back().emit + c;
+      }
+      reverse_sweep(recs, dL, &accs[t]);
+    }
+  });
+  for (auto& a : accs) {
+    for (auto& kv : a.m) {
+      Key k = kv.first;
+      if (is_texel(k)) {
+        int tex = (int)((k >> 40) & 0x7FFFFF);
+        int64_t texel = (int64_t)(k & ((1ull << 40) - 1));
+        if (grad_tex && grad_tex[tex])
+          for (int c = 0; c < 3; ++c) grad_tex[tex][3 * texel + c] += kv.second[c];
+      } else if (grad_rough) {
+        grad_rough[(int)k] += kv.second[0];
+      }
+    }
+  }
+}
+
 // Training records: path j (key = seed, g = j) starts at pixel
 // floor(r n_pix / 2^32) with r the first word of block (camera, dim 2), runs a
 // plain path, and, if it reaches a record vertex, returns its features and

@@ -325,7 +325,7 @@ def cornell(tex_size: int = 64, width: int = 64, height: int = 64, *,
     b.area_light((-0.25, 1.98, -0.25), (0.5, 0, 0), (0, 0, 0.5), (10.0, 10.0, 10.0), m_black)
     tex = np.full((tex_size, tex_size, 3), 0.5, np.float32) if texture is None else texture
     rough = [0.3 if roughness is None else roughness] if conductor else []
-    return b.build(tex_shapes=[(tex_size, tex_size)], textures=[tex], roughness=rough,
+    return b.build(tex_shapes=[tuple(tex.shape[:2])], textures=[tex], roughness=rough,
                    envmap=None, cameras=cameras or [cornell_camera(width, height)],
                    name="cornell")
 
@@ -587,7 +587,7 @@ def procedural(n_grid=512, n_spheres=215, sphere_res=(48, 24), env_size=(2048, 1
     k = extent / 12.0
     cam = Camera((0.0, 5.0 * k + 0.5, 14.0 * k), (0.0, 0.5, 0.0), (0.0, 1.0, 0.0), 50.0,
                  width, height)
-    return b.build(tex_shapes=[(tex_size, tex_size)], textures=[tex], roughness=rough,
+    return b.build(tex_shapes=[tuple(tex.shape[:2])], textures=[tex], roughness=rough,
                    envmap=env, cameras=[cam], name="procedural")
 
 

@@ -205,3 +205,67 @@ def test_training_targets_reassemble_the_plain_estimator():
     img = orc.render(spp=256, max_depth=6, rr_depth=3, seed=22)
     m, se = ltot.mean(), ltot.mean(1).std() / math.sqrt(n)
     assert abs(m - img.mean()) < 4 * se + 4 * img.mean(2).std() / math.sqrt(img.size // 3 * 256), (m, img.mean())
+
+
+def _constant_network(c=(1.5, 1.0, 0.5)):
+    """Weights whose output is the constant c * Y_00: only the band-0 SH input
+    of the outgoing direction (input 32, constant over the sphere) feeds one
+    ReLU chain."""
+    W = np.zeros(oracle.mlp_num_weights())
+    W[32] = 1.0                               # layer 0, row 0, column 32
+    W[64 * 80] = W[64 * 80 + 4096] = W[64 * 80 + 2 * 4096] = 1.0
+    for ch in range(3):
+        W[64 * 80 + 3 * 4096 + ch * 64] = c[ch]
+    return W
+
+
+def test_constant_network_output():
+    W = _constant_network()
+    x = np.random.default_rng(3).normal(size=(5, 80))
+    x[:, 32] = 0.5 / math.sqrt(math.pi)
+    np.testing.assert_allclose(oracle.mlp_forward(x, W), np.tile([1.5, 1.0, 0.5], (5, 1)) * x[:, 32:33],
+                               rtol=1e-14)
+
+
+def test_cached_adjoint_with_zero_network_equals_truncated_plain():
+    sc = scenes.cornell(texture=scenes.random_texture(16), width=16, height=16, conductor=True)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    orc = oracle.OracleScene(sc)
+    adj = np.random.default_rng(5).normal(size=(1, 16, 16, 3))
+    ga, ra = orc.adjoint_cached(cfg, grid, np.zeros(oracle.mlp_num_weights()), adj, K=3, spp=2,
+                                max_depth=6, rr_depth=3, seed=4)
+    gb, rb = orc.adjoint(adj, spp=2, max_depth=3, seed=4)
+    np.testing.assert_allclose(ga[0], gb[0], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(ra, rb, rtol=1e-12, atol=1e-15)
+
+
+def test_cached_adjoint_matches_central_differences():
+    """With a cache whose output does not depend on its inputs the cached
+    estimator is a polynomial of degree <= 2 in the texels (two scattering
+    vertices before the record vertex, no RR before it), so central
+    differences are exact up to rounding."""
+    sc = scenes.cornell(texture=scenes.random_texture(8), width=16, height=16)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    W = _constant_network()
+    orc = oracle.OracleScene(sc)
+    rng = np.random.default_rng(6)
+    adj = rng.normal(size=(1, 16, 16, 3))
+    kw = dict(K=3, spp=2, max_depth=6, rr_depth=3, seed=8, emu=False)
+    # texels on a 2^-10 grid, step 2^-6: the perturbed texels are exact in float32
+    tex = (np.round(sc.textures[0].astype(np.float64) * 1024) / 1024).astype(np.float32)
+    (g,), _ = orc.adjoint_cached(cfg, grid, W, adj, textures=[tex], **kw)
+    assert np.abs(g).max() > 0
+    h = 1.0 / 64
+    for trial in range(6):
+        v = np.zeros_like(tex)
+        sel = rng.choice(tex.size, 12, replace=False)
+        v.reshape(-1)[sel] = rng.choice([-1.0, 1.0], 12)
+        if trial == 0:
+            v = rng.choice([-1.0, 1.0], tex.shape).astype(np.float32)
+        ip = orc.render_cached(cfg, grid, W, textures=[tex + h * v], **{k: kw[k] for k in kw})
+        im = orc.render_cached(cfg, grid, W, textures=[tex - h * v], **{k: kw[k] for k in kw})
+        fd = float(((ip - im) * adj).sum() / (2 * h))
+        an = float((g * v).sum())
+        assert math.isclose(an, fd, rel_tol=1e-9, abs_tol=1e-12), (trial, an, fd)
