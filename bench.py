@@ -209,6 +209,146 @@ def aux_primal_1m(drt, scenes, torch):
             "host_build_s": round(build_s, 2)}
 
 
+def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), ref_spp=4096):
+    """Radiance cache vs plain path tracing at equal RMSE (Cornell box with
+    the random back-wall texture, D = 6, RR from 3, truncation at v3).
+
+    The reference is a plain render at ref_spp.  Both estimators are rendered
+    at each spp in `spps`; RMSE^2 against the reference is corrected for the
+    reference's own variance (V_plain / ref_spp).  The plain spp needed to
+    reach the cache's RMSE is V_plain / RMSE_cache^2, and its time is that
+    times the measured plain time per spp.  Training (65,536 paths a frame)
+    is reported per frame beside it."""
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=R, height=R)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    cams = sc.cameras
+    D, RR = 6, 3
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    ref = torch.zeros((1, R, R, 3), dtype=torch.float64, device="cuda")
+    img = torch.empty((1, R, R, 3), dtype=torch.float32, device="cuda")
+    chunk = 256
+    for c in range(ref_spp // chunk):
+        drt.render_forward(gs, tex, None, cams, chunk, D, RR, seed=100000 + c, out=img)
+        ref += img.double()
+    ref /= ref_spp // chunk
+
+    cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
+    cache.train_frame(gs, tex, None, cams, seed=500)            # warm-up
+    e0, e1 = ev(), ev()
+    torch.cuda.synchronize()
+    e0.record()
+    for f in range(frames):
+        cache.train_frame(gs, tex, None, cams, seed=1000 + f)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / frames
+
+    smax = max(spps)
+    cap = R * R * smax
+    work = (torch.empty((cap, 16), dtype=torch.float32, device="cuda"),
+            torch.empty(cap, dtype=torch.int32, device="cuda"),
+            torch.empty(1, dtype=torch.int32, device="cuda"))
+
+    def timed(fn, reps=3):
+        fn()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def mse(x):
+        return float(((x.double() - ref) ** 2).mean())
+
+    rows = []
+    for s in spps:
+        plain_ms = timed(lambda: drt.render_forward(gs, tex, None, cams, s, D, RR, seed=7, out=img))
+        m_plain = mse(img)
+        cache_ms = timed(lambda: cache.render(gs, tex, None, cams, s, seed=7, out=img, work=work))
+        m_cache = mse(img)
+        v_plain = m_plain / (1.0 / s + 1.0 / ref_spp)            # per-sample variance of plain
+        m_cache_c = max(m_cache - v_plain / ref_spp, 1e-30)        # cache MSE minus reference noise
+        spp_eq = v_plain / m_cache_c
+        plain_eq_ms = spp_eq * plain_ms / s
+        rows.append({"spp": s, "plain_ms": round(plain_ms, 3), "cache_ms": round(cache_ms, 3),
+                     "rmse_plain": round(m_plain ** 0.5, 6), "rmse_cache": round(m_cache ** 0.5, 6),
+                     "plain_spp_at_equal_rmse": round(spp_eq, 3),
+                     "speedup_at_equal_rmse": round(plain_eq_ms / cache_ms, 3),
+                     "speedup_incl_training": round(plain_eq_ms / (cache_ms + train_ms), 3)})
+    return {"workload": f"cornell-box, random 64^2 texture, {R}^2, D6 RR3, cache at v3, "
+                        f"hash grid 16x2^19x2 fp16, 80-64x4-3 bf16 network",
+            "reference_spp": ref_spp, "train_frames": frames, "train_paths_per_frame": 65536,
+            "train_ms_per_frame": round(train_ms, 3),
+            "final_train_loss": round(float(cache.loss.item()), 4), "by_spp": rows}
+
+
+def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps=3):
+    """Gradient step with paths of depth 6 (RR from 3) on the reverse-mode
+    scene, plain vs radiance cache: primal (seed A) -> L2 -> replayed adjoint
+    (seed B) -> Adam, and for the cache one training frame (65,536 paths,
+    network + grid Adam) per step.  HIP-event times of each variant."""
+    D, RR = 6, 3
+    sc = scenes.cornell(tex_size=tex_size, width=R, height=R, conductor=True)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    cams = sc.cameras
+    dev = "cuda"
+    tex = torch.full((tex_size, tex_size, 3), 0.5, dtype=torch.float32, device=dev)
+    rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
+    tex_t = torch.from_numpy(scenes.random_texture(tex_size)).to(dev)
+    target = drt.render_forward(gs, [tex_t], torch.tensor([0.2], device=dev), cams, 64, D, RR, seed=1284)
+    del tex_t
+    img = torch.empty((1, R, R, 3), dtype=torch.float32, device=dev)
+    adj = torch.empty_like(img)
+    gtex, grough = torch.zeros_like(tex), torch.zeros_like(rough)
+    m_t, v_t, m_r, v_r = (torch.zeros_like(tex), torch.zeros_like(tex), torch.zeros_like(rough),
+                          torch.zeros_like(rough))
+    cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
+    for f in range(50):                                  # a briefly trained cache
+        cache.train_frame(gs, [tex], rough, cams, seed=9000 + f)
+    n = R * R * SPP
+    work = drt.cached_work(n, dev, sample_radiance=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(k, cached):
+        if cached:
+            cache.render(gs, [tex], rough, cams, SPP, seed=2 * k + 1, out=img, work=work[:3])
+        else:
+            drt.render_forward(gs, [tex], rough, cams, SPP, D, RR, seed=2 * k + 1, out=img)
+        drt.loss_l2(img, target, adj=adj)
+        if cached:
+            cache.adjoint(gs, [tex], rough, cams, adj, SPP, seed=2 * k + 2, grad_textures=[gtex],
+                          grad_roughness=grough, work=work)
+            cache.train_frame(gs, [tex], rough, cams, seed=20000 + k)
+        else:
+            drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, RR, seed=2 * k + 2,
+                               grad_textures=[gtex], grad_roughness=grough)
+        drt.adam_step(tex, gtex, m_t, v_t, k + 1, lr=1e-2, lo=0.0, hi=1.0, zero_grad=True)
+        drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=1e-2, lo=0.01, hi=1.0, zero_grad=True)
+
+    out = {}
+    for cached in (False, True):
+        step(0, cached)
+        a, b = ev(), ev()
+        a.record()
+        for k in range(1, 1 + steps):
+            step(k, cached)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out["cache" if cached else "plain"] = {"ms_per_step": round(ms, 3),
+                                               "msamples_s": round(n / ms / 1e3, 2)}
+    return {"workload": f"cornell-box + GGX conductor, {tex_size}^2x3 texture, {R}^2 {SPP}spp D{D} "
+                        f"RR{RR}, cache at v3 (one 65,536-path training frame per step)", **out}
+
+
 def cpu_baseline(sc, R, SPP, D, budget_s):
     """FP64 oracle on a bounded, seeded sample of the workload's pixels:
     primal (seed A) + adjoint (seed B) per pixel, all host threads."""

@@ -336,6 +336,27 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
                                      int32_t* query_pixels, int32_t* query_count,
                                      int64_t capacity, float* image, void* hip_stream);
 
+/* Reverse-mode gradient of the cached estimator (cache output detached:
+ * the network and its inputs receive no gradient; the term beta * max(C, 0)
+ * at the record vertex reaches earlier vertices' BSDF derivatives through
+ * beta, as in the PRB replay of Sec. "Physically Based Differentiable
+ * Rendering").  Three launches on the stream: a cached pass with seed
+ * opts->seed that writes each sample's truncated radiance to
+ * sample_radiance and its query (with the sample index) to queries /
+ * query_ids; the network answers the queries into sample_radiance; the
+ * replay then starts every sample from its stored estimate (no second
+ * forward pass).  Gradients are ADDED to grads as in drt_render_adjoint.
+ * sample_radiance: device float [n_cams*W*H*spp][3] (scratch);
+ * queries [capacity][16], query_ids int32 [capacity], query_count int32 [1]
+ * (scratch); capacity >= n_cams*W*H*spp <= INT32_MAX. */
+drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
+                                     const drt_camera* cams, int32_t n_cams,
+                                     const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                     const float* weights, const uint16_t* grid, float* queries,
+                                     int32_t* query_ids, int32_t* query_count, int64_t capacity,
+                                     float* sample_radiance, const float* adj_image,
+                                     const drt_grads* grads, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

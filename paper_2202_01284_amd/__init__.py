@@ -135,6 +135,10 @@ _SIGS = {
                                            ctypes.POINTER(drt_render_opts),
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp,
                                            _vp, _c_i64, _vp, _vp]),
+    "drt_render_adjoint_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                           _c_i32, ctypes.POINTER(drt_render_opts),
+                                           ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp,
+                                           _c_i64, _vp, _vp, ctypes.POINTER(drt_grads), _vp]),
 }
 
 
@@ -284,6 +288,7 @@ class Scene:
                                     ctypes.byref(h)), "drt_scene_upload")
         self.handle = h
         self.info = _info(h)
+        self.tex_shapes = [(int(t[0]), int(t[1]), 3) for t in sc.tex_shapes]
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -322,19 +327,31 @@ def _cams(cams) -> "ctypes.Array":
 
 def _params(scene: Scene, textures, roughness):
     p = drt_params()
+    textures = list(textures or [])
+    if len(textures) != len(scene.tex_shapes):
+        raise ValueError(f"scene has {len(scene.tex_shapes)} textures, got {len(textures)}")
     for i, t in enumerate(textures):
-        _expect(t, f"texture {i}")
+        _expect(t, f"texture {i}", scene.tex_shapes[i])
         p.textures[i] = t.data_ptr()
+    if scene.n_roughness > 0:
+        if roughness is None or roughness.numel() < scene.n_roughness:
+            raise ValueError(f"scene has {scene.n_roughness} roughness slots")
     if roughness is not None and roughness.numel() > 0:
         _expect(roughness, "roughness")
         p.roughness = roughness.data_ptr()
     return p
 
 
-def _expect(t, what):
+def _image_shape(cams):
+    return (len(cams), cams[0].height, cams[0].width, 3)
+
+
+def _expect(t, what, shape=None):
     torch = _torch()
     if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
         raise ValueError(f"{what} must be a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
 def _opts(spp, max_depth, rr_depth, seed, flags, stats):
@@ -359,6 +376,7 @@ def render_forward(scene: Scene, textures: Sequence, roughness, cams, spp: int, 
     W, H = cams[0].width, cams[0].height
     if out is None:
         out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=scene.buffer.device)
+    _expect(out, "out", _image_shape(cams))
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
@@ -373,18 +391,22 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
     """Adds d<adj, I>/d params into grad_textures / grad_roughness (allocated
     as zeros when not given) and returns them."""
     torch = _torch()
-    _expect(adj_image, "adj_image")
+    _expect(adj_image, "adj_image", _image_shape(cams))
     if grad_textures is None:
         grad_textures = [torch.zeros_like(t) for t in textures]
     if grad_roughness is None and roughness is not None and roughness.numel() > 0:
         grad_roughness = torch.zeros_like(roughness)
     g = drt_grads()
+    if len(grad_textures) > len(scene.tex_shapes):
+        raise ValueError("more gradient textures than scene textures")
     for i, t in enumerate(grad_textures):
         if t is not None:
-            _expect(t, f"grad texture {i}")
+            _expect(t, f"grad texture {i}", scene.tex_shapes[i])
             g.textures[i] = t.data_ptr()
     if grad_roughness is not None:
         _expect(grad_roughness, "grad roughness")
+        if grad_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
         g.roughness = grad_roughness.data_ptr()
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
@@ -609,6 +631,7 @@ def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     W, H = cams[0].width, cams[0].height
     if out is None:
         out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=dev)
+    _expect(out, "out", _image_shape(cams))
     cap = len(cams) * W * H * spp
     if work is None:
         work = (torch.empty((cap, NRC_RECORD), dtype=torch.float32, device=dev),
@@ -625,6 +648,62 @@ def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
                                          qcount.data_ptr(), q.shape[0], out.data_ptr(),
                                          _stream(stream)), "drt_render_forward_cached")
     return out
+
+
+def cached_work(n_samples: int, device="cuda", sample_radiance: bool = False):
+    """Scratch buffers of the cached render / adjoint for n_samples samples:
+    (queries [n,16], query ids [n], count [1]) and, for the adjoint, the
+    per-sample radiance [n,3]."""
+    torch = _torch()
+    w = (torch.empty((n_samples, NRC_RECORD), dtype=torch.float32, device=device),
+         torch.empty(n_samples, dtype=torch.int32, device=device),
+         torch.empty(1, dtype=torch.int32, device=device))
+    if sample_radiance:
+        w = w + (torch.empty((n_samples, 3), dtype=torch.float32, device=device),)
+    return w
+
+
+def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, weights, grid,
+                          adj_image, spp: int, max_depth: int = 6, rr_depth: int = 3, seed: int = 2,
+                          flags: int = 0, grad_textures=None, grad_roughness=None, work=None,
+                          stats=None, stream=None):
+    """Adds the gradient of <adj, I_cached> (cache output detached) into
+    grad_textures / grad_roughness and returns them."""
+    torch = _torch()
+    _expect(adj_image, "adj_image", _image_shape(cams))
+    if grad_textures is None:
+        grad_textures = [torch.zeros_like(t) for t in textures]
+    if grad_roughness is None and roughness is not None and roughness.numel() > 0:
+        grad_roughness = torch.zeros_like(roughness)
+    g = drt_grads()
+    if len(grad_textures) > len(scene.tex_shapes):
+        raise ValueError("more gradient textures than scene textures")
+    for i, t in enumerate(grad_textures):
+        if t is not None:
+            _expect(t, f"grad texture {i}", scene.tex_shapes[i])
+            g.textures[i] = t.data_ptr()
+    if grad_roughness is not None:
+        _expect(grad_roughness, "grad roughness")
+        if grad_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
+        g.roughness = grad_roughness.data_ptr()
+    n = len(cams) * cams[0].width * cams[0].height * spp
+    if work is None:
+        work = cached_work(n, scene.buffer.device, sample_radiance=True)
+    q, qid, qcount, lsamp = work
+    if q.shape[0] < n or lsamp.shape[0] < n or qid.shape[0] < n:
+        raise ValueError(f"cached adjoint work buffers hold fewer than {n} samples")
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
+    c = nrc_config(cfg)
+    _check(lib.drt_render_adjoint_cached(scene.handle, ctypes.byref(p), ca, len(cams),
+                                         ctypes.byref(o), ctypes.byref(c), weights.data_ptr(),
+                                         grid.data_ptr(), q.data_ptr(), qid.data_ptr(),
+                                         qcount.data_ptr(), q.shape[0], lsamp.data_ptr(),
+                                         adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
+           "drt_render_adjoint_cached")
+    return grad_textures, grad_roughness
 
 
 class NrcCache:
@@ -667,6 +746,13 @@ class NrcCache:
         adam_step(self.grid, self.dG, self.mG, self.vG, self.step, lr=self.lr, beta1=0.9,
                   beta2=0.99, eps=1e-8, zero_grad=True, half_out=self.grid16)
         return self.loss
+
+    def adjoint(self, scene: Scene, textures, roughness, cams, adj_image, spp: int, seed: int,
+                max_depth=6, rr_depth=3, grad_textures=None, grad_roughness=None, work=None):
+        return render_adjoint_cached(scene, textures, roughness, cams, self.cfg, self.W,
+                                     self.grid16, adj_image, spp, max_depth, rr_depth, seed,
+                                     grad_textures=grad_textures, grad_roughness=grad_roughness,
+                                     work=work)
 
     def render(self, scene: Scene, textures, roughness, cams, spp: int, seed: int, max_depth=6,
                rr_depth=3, out=None, work=None):

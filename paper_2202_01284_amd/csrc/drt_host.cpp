@@ -877,4 +877,49 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
   return ok();
 }
 
+drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
+                                     const drt_camera* cams, int32_t n_cams,
+                                     const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                     const float* weights, const uint16_t* grid, float* queries,
+                                     int32_t* query_ids, int32_t* query_count, int64_t capacity,
+                                     float* sample_radiance, const float* adj_image,
+                                     const drt_grads* grads, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  DNrcNet net;
+  st = nrc_net(cfg, grid, &net);
+  if (st != DRT_OK) return st;
+  if (!weights || !grid || !queries || !query_ids || !query_count || !sample_radiance ||
+      !adj_image || !grads)
+    return fail(DRT_EINVAL, "null pointer argument");
+  int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
+  if (capacity < need || need > INT32_MAX)
+    return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
+  DGrads dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
+  dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e = launch_zero(query_count, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  DNrcIO io = {};
+  io.rec = queries;
+  io.qpix = query_ids;
+  io.count = query_count;
+  io.capacity = capacity;
+  io.K = cfg->trunc_vertex;
+  io.lsamp = sample_radiance;
+  e = launch_render_cached(scene->dev, dp, dc, dr, nullptr, io, stream);
+  if (e != hipSuccess) return hip_fail(e, "render_cached launch");
+  e = launch_nrc_infer(net, weights, queries, query_ids, query_count, need, 1.0f, sample_radiance,
+                       stream);
+  if (e != hipSuccess) return hip_fail(e, "nrc_infer launch");
+  e = launch_render_adjoint_cached(scene->dev, dp, dc, dr, adj_image, dg, io, stream);
+  if (e != hipSuccess) return hip_fail(e, "render_adjoint_cached launch");
+  return ok();
+}
+
 }  // extern "C"

@@ -135,6 +135,7 @@ struct DNrcIO {
   int* count;       // appended queries / valid records
   int64_t capacity; // queries the buffer holds
   int K;            // record vertex index
+  float* lsamp;     // per-sample radiance [n_samples][3] (cached adjoint), else null
 };
 
 // Launchers (drt_kernels.hip).
@@ -148,6 +149,9 @@ hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c,
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st);
+hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
+                                        const DRender& r, const float* adj, const DGrads& g,
+                                        const DNrcIO& io, hipStream_t st);
 hipError_t launch_trace(const DScene& s, const float* rays, int64_t n, int mode, drt_hit* hits,
                         hipStream_t st);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,

@@ -649,16 +649,30 @@ DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, ui
 // (features, throughput, pixel) for the radiance cache to answer.
 // MODE_TRAIN: a path records the features of its record vertex, goes on as a
 // plain path, and writes target = (radiance after the record point) / beta.
+// MODE_CACHED_SAMPLES: as MODE_CACHED, but each sample's radiance goes to
+// io.lsamp[g] and its query carries the sample index g instead of the pixel.
+// MODE_ADJOINT_CACHED: pass B only, from Lrem = io.lsamp[g] (the cached
+// estimate with the cache's answer already added); the replay stops at the
+// record vertex, so the detached cache term reaches earlier vertices through
+// Lrem and nothing is scattered for the network.
 // Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
 // ---------------------------------------------------------------------------
-enum { MODE_PRIMAL = 0, MODE_ADJOINT = 1, MODE_CACHED = 2, MODE_TRAIN = 3 };
+enum {
+  MODE_PRIMAL = 0,
+  MODE_ADJOINT = 1,
+  MODE_CACHED = 2,
+  MODE_TRAIN = 3,
+  MODE_CACHED_SAMPLES = 4,
+  MODE_ADJOINT_CACHED = 5
+};
 
 template <int MODE>
 DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
                       const LdsTables& tab, int cam, int x, int y, uint64_t g_base, int n_samples,
                       f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
                       f3& out) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool ADJ = MODE == MODE_ADJOINT || MODE == MODE_ADJOINT_CACHED;
+  constexpr bool QUERY = MODE == MODE_CACHED || MODE == MODE_CACHED_SAMPLES;
   const int W = C.width, H = C.height;
   const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
   const int n_em = s.n_ems;
@@ -789,22 +803,24 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
               f3 alb = type == DRT_BSDF_CONDUCTOR ? sh.f0
                        : (type == DRT_BSDF_DIELECTRIC ? mk(1, 1, 1) : sh.albedo);
               float* rec = nullptr;
-              if (MODE == MODE_CACHED) {
+              if (QUERY) {
                 int slot = atomicAdd(io.count, 1);
                 if (slot < io.capacity) {
                   rec = io.rec + (size_t)NRC_REC * slot;
-                  io.qpix[slot] = (int)pix;
+                  io.qpix[slot] = MODE == MODE_CACHED_SAMPLES ? (int)glo : (int)pix;
                   rec[13] = beta.x;
                   rec[14] = beta.y;
                   rec[15] = beta.z;
                 }
-                stop_here = true;
-                done = true;
-              } else {
+              } else if (MODE == MODE_TRAIN) {
                 rec = io.rec + (size_t)NRC_REC * g_base;
                 recorded = true;
                 beta_at = beta;
                 L_at = L;
+              }
+              if (MODE != MODE_TRAIN) {
+                stop_here = true;
+                done = true;
               }
               if (rec) {
                 rec[0] = p.x; rec[1] = p.y; rec[2] = p.z;
@@ -947,6 +963,14 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   // path ends early waits for the wave
   for (;;) {
     start();
+    if constexpr (MODE == MODE_ADJOINT_CACHED) {
+      const float* ls = io.lsamp + 3 * (g_base + (uint64_t)sidx);
+      Lrem = mk(ls[0], ls[1], ls[2]);
+      while (!step(std::true_type{})) {
+      }
+      if (++sidx == n_samples) break;
+      continue;
+    }
     while (!step(std::false_type{})) {
     }
     if (MODE == MODE_TRAIN) {
@@ -967,6 +991,11 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       while (!step(std::true_type{})) {
       }
       cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z))));
+    } else if (MODE == MODE_CACHED_SAMPLES) {
+      float* ls = io.lsamp + 3 * (g_base + (uint64_t)sidx);
+      ls[0] = L.x;
+      ls[1] = L.y;
+      ls[2] = L.z;
     } else {
       acc = acc + L;
     }
@@ -1002,8 +1031,9 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 // megakernels: one 16x16 pixel tile per workgroup
 // ---------------------------------------------------------------------------
 // STATS = false compiles the counters out (they are never read).
-// CACHED: paths stop at their record vertex and append cache queries.
-template <bool STATS, bool CACHED>
+// MODE: MODE_PRIMAL, MODE_CACHED (paths stop at their record vertex and
+// append cache queries) or MODE_CACHED_SAMPLES (per-sample radiance, no image).
+template <bool STATS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, DCams C, DRender R,
                                                            float* __restrict__ image, DNrcIO io) {
   __shared__ int stack[kStackDepth * kBlock];
@@ -1019,23 +1049,26 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
     Sink none{&tab, nullptr, nullptr};
     f3 acc;
     const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
-    render_pixel<CACHED ? MODE_CACHED : MODE_PRIMAL>(s, P, C, R, tab, cam, x, y,
-                                                     pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
-                                                     stack + threadIdx.x, cnt, none, io, acc);
-    const float inv = 1.0f / (float)R.spp;
-    float* out = image + 3 * (((size_t)cam * H + y) * W + x);
-    out[0] = acc.x * inv;
-    out[1] = acc.y * inv;
-    out[2] = acc.z * inv;
+    render_pixel<MODE>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
+                       stack + threadIdx.x, cnt, none, io, acc);
+    if (MODE != MODE_CACHED_SAMPLES) {
+      const float inv = 1.0f / (float)R.spp;
+      float* out = image + 3 * (((size_t)cam * H + y) * W + x);
+      out[0] = acc.x * inv;
+      out[1] = acc.y * inv;
+      out[2] = acc.z * inv;
+    }
   }
   if constexpr (STATS) flush_counters(R, cnt);
 }
 
 // Held to 128 VGPRs (4 waves per SIMD): measured faster than 3 waves at 131.
-template <bool STATS>
+// MODE: MODE_ADJOINT (both passes) or MODE_ADJOINT_CACHED (replay from the
+// per-sample cached estimates in io.lsamp).
+template <bool STATS, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
                                                            const float* __restrict__ adj,
-                                                           DGrads G) {
+                                                           DGrads G, DNrcIO io) {
   __shared__ int stack[kStackDepth * kBlock];
   __shared__ LdsTables tab;
   __shared__ float rough_acc[kMaxRoughLds];
@@ -1055,9 +1088,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (nonzero(dL)) {
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
       f3 unused;
-      DNrcIO none_io = {};
-      render_pixel<MODE_ADJOINT>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
-                                 stack + threadIdx.x, cnt, sink, none_io, unused);
+      render_pixel<MODE>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
+                         stack + threadIdx.x, cnt, sink, io, unused);
     }
   }
   __syncthreads();
@@ -1204,11 +1236,11 @@ hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams&
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
   DNrcIO none = {};
   if (r.stats)
-    hipLaunchKernelGGL((k_render_forward<true, false>), grid, dim3(kBlock), 0, st, s, p, c, r,
-                       image, none);
-  else
-    hipLaunchKernelGGL((k_render_forward<false, false>), grid, dim3(kBlock), 0, st, s, p, c,
+    hipLaunchKernelGGL((k_render_forward<true, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p, c,
                        r, image, none);
+  else
+    hipLaunchKernelGGL((k_render_forward<false, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p,
+                       c, r, image, none);
   return hipGetLastError();
 }
 
@@ -1216,8 +1248,12 @@ hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& 
                                 const DRender& r, float* image, const DNrcIO& io,
                                 hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
-  hipLaunchKernelGGL((k_render_forward<false, true>), grid, dim3(kBlock), 0, st, s, p, c, r,
-                     image, io);
+  if (io.lsamp)
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, image, io);
+  else
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED>), grid, dim3(kBlock), 0, st, s, p,
+                       c, r, image, io);
   return hipGetLastError();
 }
 
@@ -1233,12 +1269,26 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  DNrcIO none = {};
   if (r.stats)
-    hipLaunchKernelGGL((k_render_adjoint<true>), grid, dim3(kBlock), 0, st, s, p, c,
-                       r, adj, g);
+    hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
+                       c, r, adj, g, none);
   else
-    hipLaunchKernelGGL((k_render_adjoint<false>), grid, dim3(kBlock), 0, st, s, p, c,
-                       r, adj, g);
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
+                       c, r, adj, g, none);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
+                                        const DRender& r, const float* adj, const DGrads& g,
+                                        const DNrcIO& io, hipStream_t st) {
+  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  if (r.stats)
+    hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, adj, g, io);
+  else
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, adj, g, io);
   return hipGetLastError();
 }
 

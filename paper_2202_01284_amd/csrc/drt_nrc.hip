@@ -36,6 +36,10 @@ constexpr int kW0 = 0, kW1 = 64 * 80, kW2 = kW1 + 4096, kW3 = kW2 + 4096, kW4 = 
 constexpr int kW4Pad = 16 * 64;             // output layer padded to 16 rows in LDS
 constexpr int kLdsW = kW4 + kW4Pad;         // bf16 weights staged in LDS
 constexpr int kBlockN = 256;                // 4 waves per workgroup
+// dW accumulators in LDS: rows padded by 4 floats so that the 4 lane groups
+// (rows 4 apart) of an accumulation fall in different banks
+constexpr int kP0 = 0, kP1 = 64 * 84, kP2 = kP1 + 64 * 68, kP3 = kP2 + 64 * 68, kP4 = kP3 + 64 * 68;
+constexpr int kLdsDW = kP4 + 3 * 68;
 
 DEV uint16_t f2bf(float f) {
   uint32_t b = __float_as_uint(f);
@@ -67,33 +71,47 @@ DEV bf16x4 zero_b() {
 }
 
 // ---------------------------------------------------------------------------
-// weights in LDS
+// weights in LDS, in MFMA fragment order: each 16x16 tile (t, s) of a layer
+// (rows 16t.., cols 16s..) is 256 contiguous bf16 laid out as the A operand
+// is held -- lane r + 16g owns row 16t + r, cols 16s + 4g .. +3 -- so an A
+// load is one contiguous 8-byte read per lane (no bank conflicts).  Layer 4
+// is padded to 16 rows (rows 3..15 zero).
 // ---------------------------------------------------------------------------
+DEV int frag_index(int row, int col, int K) {
+  const int t = row >> 4, r = row & 15, s = col >> 4, g = (col >> 2) & 3, j = col & 3;
+  return ((t * (K >> 4) + s) << 8) + ((r + 16 * g) << 2) + j;
+}
+
 DEV void stage_weights(uint16_t* wl, const float* __restrict__ W) {
   for (int i = threadIdx.x; i < kLdsW; i += blockDim.x) {
-    float v;
-    if (i < kW4) {
-      v = W[i];
-    } else {
-      int r = (i - kW4) / 64, c = (i - kW4) % 64;
-      v = r < 3 ? W[kW4 + r * 64 + c] : 0.f;
-    }
+    int base, K;
+    if (i < kW1) { base = kW0; K = 80; }
+    else if (i < kW2) { base = kW1; K = 64; }
+    else if (i < kW3) { base = kW2; K = 64; }
+    else if (i < kW4) { base = kW3; K = 64; }
+    else { base = kW4; K = 64; }
+    const int e = i - base, tile = e >> 8, ln = (e & 255) >> 2, j = e & 3;
+    const int row = 16 * (tile / (K >> 4)) + (ln & 15);
+    const int col = 16 * (tile % (K >> 4)) + 4 * (ln >> 4) + j;
+    const float v = (base == kW4 && row >= 3) ? 0.f : W[base + row * K + col];
     wl[i] = f2bf(v);
   }
 }
-// A operand of W (rows 16t.., cols 16s..): 4 contiguous bf16 per lane
+// A operand of W (rows 16t.., cols 16s..)
 DEV bf16x4 ldA(const uint16_t* w, int K, int t, int s, int lane) {
-  return *reinterpret_cast<const bf16x4*>(w + (16 * t + (lane & 15)) * K + 16 * s + 4 * (lane >> 4));
+  return *reinterpret_cast<const bf16x4*>(w + ((t * (K >> 4) + s) << 8) + 4 * lane);
 }
-// A operand of W^T (rows = inputs 16t.., k = outputs 16s..)
+// A operand of W^T (rows = inputs 16t.., k = outputs 16s..): lane r + 16g
+// needs W[16s + 4g + j][16t + r], j = 0..3
 DEV bf16x4 ldAT(const uint16_t* w, int K, int t, int s, int lane) {
-  const uint16_t* p = w + (16 * s + 4 * (lane >> 4)) * K + 16 * t + (lane & 15);
-  bf16x4 r;
-  r[0] = (short)p[0];
-  r[1] = (short)p[K];
-  r[2] = (short)p[2 * K];
-  r[3] = (short)p[3 * K];
-  return r;
+  const int r = lane & 15, g = lane >> 4;
+  const uint16_t* p = w + ((s * (K >> 4) + t) << 8) + ((4 * g + 16 * (r >> 2)) << 2) + (r & 3);
+  bf16x4 v;
+  v[0] = (short)p[0];
+  v[1] = (short)p[4];
+  v[2] = (short)p[8];
+  v[3] = (short)p[12];
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -274,9 +292,23 @@ DEV void accumulate_dw(float* dwl, int K, int out_tiles, int out_rows, const uin
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         int r = 16 * t + 4 * g + j;
-        if (r < out_rows && d[j] != 0.f) atomicAdd(dwl + r * K + 16 * u + (lane & 15), d[j]);
+        if (r < out_rows && d[j] != 0.f) atomicAdd(dwl + r * (K + 4) + 16 * u + (lane & 15), d[j]);
       }
     }
+  }
+}
+
+// dW[i] += the block's accumulators (row-major index i, padded LDS rows)
+DEV void flush_dw(const float* dwl, float* __restrict__ dW) {
+  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) {
+    int pi;
+    if (i < kW1) pi = kP0 + (i / 80) * 84 + i % 80;
+    else if (i < kW2) pi = kP1 + ((i - kW1) >> 6) * 68 + ((i - kW1) & 63);
+    else if (i < kW3) pi = kP2 + ((i - kW2) >> 6) * 68 + ((i - kW2) & 63);
+    else if (i < kW4) pi = kP3 + ((i - kW3) >> 6) * 68 + ((i - kW3) & 63);
+    else pi = kP4 + ((i - kW4) >> 6) * 68 + ((i - kW4) & 63);
+    const float v = dwl[pi];
+    if (v != 0.f) atomicAdd(dW + i, v);
   }
 }
 
@@ -291,14 +323,14 @@ DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts&
   // output layer
   stage(st_dh, &dyb, 1, lane);
   stage(st_h, A.h4, 4, lane);
-  accumulate_dw(dwl + kW4, 64, 1, 3, st_dh, st_h, lane);
+  accumulate_dw(dwl + kP4, 64, 1, 3, st_dh, st_h, lane);
   bf16x4 g4[4], g3[4], g2[4], g1[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
   // hidden layers 3, 2, 1
   stage(st_dh, g4, 4, lane);
   stage(st_h, A.h3, 4, lane);
-  accumulate_dw(dwl + kW3, 64, 4, 64, st_dh, st_h, lane);
+  accumulate_dw(dwl + kP3, 64, 4, 64, st_dh, st_h, lane);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = zero4();
@@ -307,7 +339,7 @@ DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts&
   }
   stage(st_dh, g3, 4, lane);
   stage(st_h, A.h2, 4, lane);
-  accumulate_dw(dwl + kW2, 64, 4, 64, st_dh, st_h, lane);
+  accumulate_dw(dwl + kP2, 64, 4, 64, st_dh, st_h, lane);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = zero4();
@@ -316,7 +348,7 @@ DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts&
   }
   stage(st_dh, g2, 4, lane);
   stage(st_h, A.h1, 4, lane);
-  accumulate_dw(dwl + kW1, 64, 4, 64, st_dh, st_h, lane);
+  accumulate_dw(dwl + kP1, 64, 4, 64, st_dh, st_h, lane);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = zero4();
@@ -326,7 +358,7 @@ DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts&
   // input layer
   stage(st_dh, g1, 4, lane);
   stage(st_h, A.h0, 5, lane);
-  accumulate_dw(dwl + kW0, 80, 4, 64, st_dh, st_h, lane);
+  accumulate_dw(dwl + kP0, 80, 4, 64, st_dh, st_h, lane);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     f32x4 acc = zero4();
@@ -384,10 +416,10 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restric
                                                          float* __restrict__ dW,
                                                          float* __restrict__ dx) {
   __shared__ uint16_t wl[kLdsW];
-  __shared__ float dwl[kW4 + 3 * 64];
+  __shared__ float dwl[kLdsDW];
   __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
   stage_weights(wl, W);
-  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) dwl[i] = 0.f;
+  for (int i = threadIdx.x; i < kLdsDW; i += blockDim.x) dwl[i] = 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const int64_t n_tiles = (n + 15) / 16;
@@ -413,8 +445,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restric
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x)
-    if (dwl[i] != 0.f) atomicAdd(dW + i, dwl[i]);
+  flush_dw(dwl, dW);
 }
 
 // Encoding only: records [n][16] -> x [n][80] (FP32, before BF16 rounding).
@@ -489,13 +520,13 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float*
                                                       float* __restrict__ dgrid,
                                                       float* __restrict__ loss) {
   __shared__ uint16_t wl[kLdsW];
-  __shared__ float dwl[kW4 + 3 * 64];
+  __shared__ float dwl[kLdsDW];
   __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
   __shared__ GridLds gl;
   __shared__ float loss_acc;
   stage_weights(wl, W);
   load_grid_tables(gl, net);
-  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) dwl[i] = 0.f;
+  for (int i = threadIdx.x; i < kLdsDW; i += blockDim.x) dwl[i] = 0.f;
   if (threadIdx.x == 0) loss_acc = 0.f;
   __syncthreads();
   const int n_valid = *count;
@@ -552,8 +583,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float*
   }
   if (my_loss != 0.f) atomicAdd(&loss_acc, my_loss * inv);
   __syncthreads();
-  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x)
-    if (dwl[i] != 0.f) atomicAdd(dW + i, dwl[i]);
+  flush_dw(dwl, dW);
   if (threadIdx.x == 0 && loss_acc != 0.f) atomicAdd(loss, loss_acc);
 }
 
@@ -622,14 +652,16 @@ hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, fl
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
                             const int* count, int64_t capacity, float inv_spp, float* image,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_nrc_infer, dim3(grid_for(capacity, 4096)), dim3(kBlockN), 0, st, net, W, q,
+  // persistent: 4 workgroups per CU (LDS-limited), each wave loops over tiles
+  hipLaunchKernelGGL(k_nrc_infer, dim3(grid_for(capacity, 1024)), dim3(kBlockN), 0, st, net, W, q,
                      qpix, count, capacity, inv_spp, image);
   return hipGetLastError();
 }
 hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
                             const int* count, int64_t n, float* dW, float* dgrid, float* loss,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_nrc_train, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, net, W, rec,
+  // one workgroup per CU fits in LDS; every workgroup flushes 17,600 dW atomics
+  hipLaunchKernelGGL(k_nrc_train, dim3(grid_for(n, 256)), dim3(kBlockN), 0, st, net, W, rec,
                      valid, count, n, dW, dgrid, loss);
   return hipGetLastError();
 }

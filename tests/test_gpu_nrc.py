@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import scenes
-from test_gpu_parity import check_image
+from test_gpu_parity import check_grad, check_image, unambiguous_adjoint
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -214,6 +214,62 @@ def test_cached_render_vs_oracle():
                                                     K=3, spp=4, max_depth=6, rr_depth=3, seed=5,
                                                     emu=True, ambiguity=True)
     check_image(img.cpu().numpy(), ref, "cached render", amb)
+
+
+def _cached_adjoint_case(zero_network=False):
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64))
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    W = W.copy()
+    W[17408:] = np.abs(W[17408:]) * 4.0      # cache term comparable to the tail it replaces
+    if zero_network:
+        W[:] = 0
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    rough = torch.from_numpy(sc.roughness).cuda()
+    return drt, sc, cfg, W, grid, gs, tex, rough
+
+
+def test_cached_adjoint_vs_oracle():
+    """Replayed adjoint of the cached estimator (cache output detached)
+    against the oracle's reverse sweep with the BF16-emulated network."""
+    drt, sc, cfg, W, grid, gs, tex, rough = _cached_adjoint_case()
+    orc = oracle.OracleScene(sc)
+    spp, seed = 4, 2
+    kw = dict(K=3, spp=spp, max_depth=6, rr_depth=3, seed=seed, emu=True)
+    _, amb = orc.render_cached(cfg, grid.astype(np.float32), W.astype(np.float64), ambiguity=True, **kw)
+    adj = np.random.default_rng(11).normal(size=(1, 64, 64, 3)).astype(np.float32)
+    adj = unambiguous_adjoint(orc, adj, amb)
+    print("pixels set aside", int((amb > 0).sum()), flush=True)
+    gt, gr = drt.render_adjoint_cached(gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+                                       torch.from_numpy(grid.reshape(-1)).cuda(),
+                                       torch.from_numpy(adj).cuda(), spp, 6, 3, seed)
+    (ot,), orough = orc.adjoint_cached(cfg, grid.astype(np.float32), W.astype(np.float64),
+                                       adj.astype(np.float64), **kw)
+    check_grad(gt[0].cpu().numpy(), ot, "cached adjoint, texture")
+    check_grad(gr.cpu().numpy(), orough, "cached adjoint, roughness")
+    # the cache term reaches the gradient: it differs from the truncated
+    # estimator's (zero cache) by much more than the tolerance
+    (zt,), _ = orc.adjoint_cached(cfg, grid.astype(np.float32), np.zeros_like(W, np.float64),
+                                  adj.astype(np.float64), **kw)
+    d = np.linalg.norm(ot - zt) / np.linalg.norm(ot)
+    print("cache term share of the texture gradient", d, flush=True)
+    assert d > 0.02
+
+
+def test_cached_adjoint_zero_network_equals_plain_depth3():
+    """With a zero network the cached adjoint is the plain adjoint at max
+    depth 3 on the same streams (GPU against GPU)."""
+    drt, sc, cfg, W, grid, gs, tex, rough = _cached_adjoint_case(zero_network=True)
+    adj = torch.from_numpy(np.random.default_rng(12).normal(size=(1, 64, 64, 3)).astype(np.float32)).cuda()
+    gt, gr = drt.render_adjoint_cached(gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+                                       torch.from_numpy(grid.reshape(-1)).cuda(), adj, 4, 6, 3, 5)
+    pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 4, 3, seed=5)
+    r = rel(gt[0].cpu().numpy(), pt[0].cpu().numpy())
+    print("zero-cache adjoint vs plain depth-3 adjoint rel", r, flush=True)
+    assert r <= 1e-5
+    assert abs(gr.item() - pr.item()) <= 1e-5 * abs(pr.item())
 
 
 def test_trained_cache_beats_untrained():
