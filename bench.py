@@ -11,7 +11,10 @@ the same kernel).  Inputs are resident in HBM before timing starts.
 Reported: Msamples/s = 1024*1024*16 / step time; the adjoint kernel's
 roofline (ALU bound; algorithmic FLOPs from the traversal/shading counters of
 a stats run, divided by its HIP-event launch duration); the FP64 CPU oracle's
-throughput on a bounded sample of the same workload.
+throughput on a bounded sample of the same workload; and the radiance cache
+against plain path tracing (depth 6, RR from 3): time to equal RMSE for the
+primal at 1024^2 against a 4096-spp plain reference, and the gradient step
+with the cache in the primal and in the replay (plus one training frame).
 """
 import argparse
 import json
@@ -42,6 +45,8 @@ def main():
     ap.add_argument("--target-spp", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-aux", action="store_true", help="skip the 1M-triangle primal figure")
+    ap.add_argument("--no-cache", action="store_true",
+                    help="skip the radiance-cache comparison (equal RMSE, cached gradient step)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
@@ -132,6 +137,12 @@ def main():
     if not args.no_aux:
         aux = aux_primal_1m(drt, scenes, torch)
 
+    cache = None
+    if not args.no_cache:
+        cache = {"equal_rmse": cache_equal_rmse(drt, scenes, torch, R=args.res),
+                 "gradient_step": cache_gradient_step(drt, scenes, torch, R=args.res, SPP=args.spp,
+                                                      tex_size=args.tex)}
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc, R, SPP, D, args.cpu_seconds)
@@ -156,6 +167,7 @@ def main():
                    "target_spp": args.target_spp},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cache": cache,
         "aux": aux,
     }
     print(json.dumps(line), flush=True)
@@ -247,11 +259,7 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
     torch.cuda.synchronize()
     train_ms = e0.elapsed_time(e1) / frames
 
-    smax = max(spps)
-    cap = R * R * smax
-    work = (torch.empty((cap, 16), dtype=torch.float32, device="cuda"),
-            torch.empty(cap, dtype=torch.int32, device="cuda"),
-            torch.empty(1, dtype=torch.int32, device="cuda"))
+    work = drt.cached_work(R * R * max(spps), "cuda")
 
     def timed(fn, reps=3):
         fn()

@@ -316,24 +316,40 @@ drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
                            const drt_nrc_config* cfg, int64_t n_paths, float* records,
                            int32_t* valid, int32_t* count, void* hip_stream);
 
+/* Bytes of device workspace drt_nrc_train needs for n records (the BF16
+ * layer inputs and output gradients of every record, 1216 B per record
+ * rounded up to 16-record tiles). */
+int64_t drt_nrc_train_workspace_bytes(int64_t n);
+
 /* One training pass: relative-L2 loss (Mueller et al. 2021: mean over valid
  * records and channels of (y - t)^2 / (y^2 + 0.01), y held fixed in the
  * denominator) -> network and grid gradients ADDED to dW [17600] and dgrid
- * [levels][2^log2_table][2] (float); *loss is set to the loss. */
+ * [levels][2^log2_table][2] (float); *loss is set to the loss.  workspace:
+ * device scratch of at least drt_nrc_train_workspace_bytes(n) bytes,
+ * 16-byte aligned (overwritten). */
 drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,
                          const float* records, const int32_t* valid, const int32_t* count,
-                         int64_t n, float* dW, float* dgrid, float* loss, void* hip_stream);
+                         int64_t n, void* workspace, int64_t workspace_bytes, float* dW,
+                         float* dgrid, float* loss, void* hip_stream);
+
+/* Entries of the int32 query scratch of the cached calls for `capacity`
+ * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
+ * bin histogram [4096]. */
+int64_t drt_nrc_query_ints(int64_t capacity);
 
 /* Primal render with the cache: image = (1/spp) sum over samples of the
- * path radiance up to the record vertex plus beta * max(C, 0) there.
- * queries: device float [capacity][16], query_pixels: int32 [capacity],
- * query_count: int32 [1] (scratch, set by the call); capacity >= n_cams*W*H*spp.
- * The cache terms are added with float atomics (order not deterministic). */
+ * path radiance up to the record vertex plus beta * max(C, 0) there.  The
+ * queries are sorted by a 16^3 Morton cell of their position before the
+ * network answers them (hash-table gathers of nearby queries share cache
+ * lines).  Scratch (device, overwritten): queries float [capacity][16],
+ * query_ints int32 [drt_nrc_query_ints(capacity)], query_count int32 [1];
+ * capacity >= n_cams*W*H*spp <= INT32_MAX.  The cache terms are added with
+ * float atomics (summation order not deterministic). */
 drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
-                                     int32_t* query_pixels, int32_t* query_count,
+                                     int32_t* query_ints, int32_t* query_count,
                                      int64_t capacity, float* image, void* hip_stream);
 
 /* Reverse-mode gradient of the cached estimator (cache output detached:
@@ -346,14 +362,13 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
  * query_ids; the network answers the queries into sample_radiance; the
  * replay then starts every sample from its stored estimate (no second
  * forward pass).  Gradients are ADDED to grads as in drt_render_adjoint.
- * sample_radiance: device float [n_cams*W*H*spp][3] (scratch);
- * queries [capacity][16], query_ids int32 [capacity], query_count int32 [1]
- * (scratch); capacity >= n_cams*W*H*spp <= INT32_MAX. */
+ * sample_radiance: device float [n_cams*W*H*spp][3] (scratch); queries,
+ * query_ints, query_count and capacity as for drt_render_forward_cached. */
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
-                                     int32_t* query_ids, int32_t* query_count, int64_t capacity,
+                                     int32_t* query_ints, int32_t* query_count, int64_t capacity,
                                      float* sample_radiance, const float* adj_image,
                                      const drt_grads* grads, void* hip_stream);
 

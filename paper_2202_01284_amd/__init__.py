@@ -128,13 +128,15 @@ _SIGS = {
     "drt_nrc_collect": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                  ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_nrc_config),
                                  _c_i64, _vp, _vp, _vp, _vp]),
+    "drt_nrc_train_workspace_bytes": (_c_i64, [_c_i64]),
     "drt_nrc_train": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp, _c_i64, _vp,
-                               _vp, _vp, _vp]),
+                               _c_i64, _vp, _vp, _vp, _vp]),
     "drt_render_forward_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params),
                                            ctypes.POINTER(drt_camera), _c_i32,
                                            ctypes.POINTER(drt_render_opts),
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp,
                                            _vp, _c_i64, _vp, _vp]),
+    "drt_nrc_query_ints": (_c_i64, [_c_i64]),
     "drt_render_adjoint_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                            _c_i32, ctypes.POINTER(drt_render_opts),
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp,
@@ -610,15 +612,24 @@ def nrc_collect(scene: Scene, textures, roughness, cams, cfg: dict, n_paths: int
     return rec, valid, count
 
 
-def nrc_train(cfg: dict, weights, grid, records, valid, count, dW, dgrid, loss=None, stream=None):
+def nrc_train_workspace(n: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(int(lib.drt_nrc_train_workspace_bytes(n)), dtype=torch.uint8, device=device)
+
+
+def nrc_train(cfg: dict, weights, grid, records, valid, count, dW, dgrid, loss=None, workspace=None,
+              stream=None):
     torch = _torch()
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device=weights.device)
+    n = records.shape[0]
+    if workspace is None:
+        workspace = nrc_train_workspace(n, weights.device)
     c = nrc_config(cfg)
     _check(lib.drt_nrc_train(ctypes.byref(c), weights.data_ptr(), grid.data_ptr(),
-                             records.data_ptr(), valid.data_ptr(), count.data_ptr(),
-                             records.shape[0], dW.data_ptr(), dgrid.data_ptr(), loss.data_ptr(),
-                             _stream(stream)), "drt_nrc_train")
+                             records.data_ptr(), valid.data_ptr(), count.data_ptr(), n,
+                             workspace.data_ptr(), workspace.numel(), dW.data_ptr(),
+                             dgrid.data_ptr(), loss.data_ptr(), _stream(stream)), "drt_nrc_train")
     return loss
 
 
@@ -634,10 +645,9 @@ def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     _expect(out, "out", _image_shape(cams))
     cap = len(cams) * W * H * spp
     if work is None:
-        work = (torch.empty((cap, NRC_RECORD), dtype=torch.float32, device=dev),
-                torch.empty(cap, dtype=torch.int32, device=dev),
-                torch.empty(1, dtype=torch.int32, device=dev))
-    q, qpix, qcount = work
+        work = cached_work(cap, dev)
+    q, qpix, qcount = work[:3]
+    _check_work(q, qpix, cap)
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
@@ -652,15 +662,22 @@ def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
 
 def cached_work(n_samples: int, device="cuda", sample_radiance: bool = False):
     """Scratch buffers of the cached render / adjoint for n_samples samples:
-    (queries [n,16], query ids [n], count [1]) and, for the adjoint, the
-    per-sample radiance [n,3]."""
+    (queries [n,16], query ints [drt_nrc_query_ints(n)], count [1]) and, for
+    the adjoint, the per-sample radiance [n,3]."""
     torch = _torch()
     w = (torch.empty((n_samples, NRC_RECORD), dtype=torch.float32, device=device),
-         torch.empty(n_samples, dtype=torch.int32, device=device),
+         torch.empty(int(lib.drt_nrc_query_ints(n_samples)), dtype=torch.int32, device=device),
          torch.empty(1, dtype=torch.int32, device=device))
     if sample_radiance:
         w = w + (torch.empty((n_samples, 3), dtype=torch.float32, device=device),)
     return w
+
+
+def _check_work(q, ints, n):
+    if q.shape[0] < n:
+        raise ValueError(f"query buffer holds fewer than {n} queries")
+    if ints.numel() < int(lib.drt_nrc_query_ints(q.shape[0])):
+        raise ValueError("query int scratch is smaller than drt_nrc_query_ints(capacity)")
 
 
 def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, weights, grid,
@@ -691,8 +708,9 @@ def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     if work is None:
         work = cached_work(n, scene.buffer.device, sample_radiance=True)
     q, qid, qcount, lsamp = work
-    if q.shape[0] < n or lsamp.shape[0] < n or qid.shape[0] < n:
-        raise ValueError(f"cached adjoint work buffers hold fewer than {n} samples")
+    _check_work(q, qid, n)
+    if lsamp.shape[0] < n:
+        raise ValueError(f"cached adjoint sample buffer holds fewer than {n} samples")
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
@@ -727,6 +745,7 @@ class NrcCache:
         self.lr = lr
         self.step = 0
         self.buf = None
+        self.ws = None
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
 
     def train_frame(self, scene: Scene, textures, roughness, cams, seed: int, max_depth: int = 6,
@@ -739,7 +758,10 @@ class NrcCache:
                         torch.empty(1, dtype=torch.int32, device=dev))
         rec, valid, count = nrc_collect(scene, textures, roughness, cams, self.cfg, self.n_paths,
                                         seed, max_depth, rr_depth, out=self.buf)
-        nrc_train(self.cfg, self.W, self.grid16, rec, valid, count, self.dW, self.dG, self.loss)
+        if self.ws is None:
+            self.ws = nrc_train_workspace(self.n_paths, self.W.device)
+        nrc_train(self.cfg, self.W, self.grid16, rec, valid, count, self.dW, self.dG, self.loss,
+                  workspace=self.ws)
         self.step += 1
         adam_step(self.W, self.dW, self.mW, self.vW, self.step, lr=self.lr, beta1=0.9, beta2=0.99,
                   eps=1e-8, zero_grad=True)

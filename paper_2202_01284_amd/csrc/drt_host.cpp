@@ -569,6 +569,34 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   return DRT_OK;
 }
 
+// Query buffers of the cached calls: the int32 scratch holds ids | order |
+// bins | histogram (drt_nrc_query_ints).
+static DNrcIO query_io(const DNrcNet& net, const drt_nrc_config* cfg, float* queries,
+                       int32_t* ints, int32_t* count, int64_t capacity) {
+  DNrcIO io = {};
+  io.rec = queries;
+  io.qpix = ints;
+  io.count = count;
+  io.capacity = capacity;
+  io.K = cfg->trunc_vertex;
+  io.qbin = reinterpret_cast<uint32_t*>(ints + 2 * capacity);
+  for (int a = 0; a < 3; ++a) {
+    io.lo[a] = net.lo[a];
+    io.inv_ext[a] = net.inv_ext[a];
+  }
+  return io;
+}
+
+// Sort the queries by spatial bin, then let the network answer them.
+static hipError_t answer_queries(const DNrcNet& net, const float* weights, const DNrcIO& io,
+                                 int64_t need, float scale, float* out, hipStream_t st) {
+  int* order = io.qpix + io.capacity;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(io.qpix + 3 * io.capacity);
+  hipError_t e = launch_query_sort(io.qbin, io.count, need, hist, order, st);
+  if (e != hipSuccess) return e;
+  return launch_nrc_infer(net, weights, io.rec, io.qpix, order, io.count, need, scale, out, st);
+}
+
 drt_status nrc_net(const drt_nrc_config* c, const uint16_t* grid, DNrcNet* net) {
   if (!c) return fail(DRT_EINVAL, "cache config is NULL");
   if (c->levels != DRT_NRC_LEVELS || c->features != 2)
@@ -822,30 +850,41 @@ drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
   return ok();
 }
 
+int64_t drt_nrc_train_workspace_bytes(int64_t n) { return n < 0 ? 0 : nrc_train_workspace_bytes(n); }
+
 drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,
                          const float* records, const int32_t* valid, const int32_t* count,
-                         int64_t n, float* dW, float* dgrid, float* loss, void* hip_stream) {
+                         int64_t n, void* workspace, int64_t workspace_bytes, float* dW,
+                         float* dgrid, float* loss, void* hip_stream) {
   DNrcNet net;
   drt_status st = nrc_net(cfg, grid, &net);
   if (st != DRT_OK) return st;
-  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(DRT_EINVAL, "n out of range");
   if (!weights || !grid || !count || !dW || !dgrid || !loss)
     return fail(DRT_EINVAL, "null pointer argument");
   if (n > 0 && (!records || !valid)) return fail(DRT_EINVAL, "records and valid are required");
+  if (n > 0 && (!workspace || workspace_bytes < nrc_train_workspace_bytes(n)))
+    return fail(DRT_EINVAL, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                (long long)nrc_train_workspace_bytes(n));
+  if (((uintptr_t)workspace & 15) != 0) return fail(DRT_EINVAL, "workspace is not 16-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   hipError_t e = launch_zero(loss, 1, stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
   if (n == 0) return ok();
-  e = launch_nrc_train(net, weights, records, valid, count, n, dW, dgrid, loss, stream);
+  e = launch_nrc_train2(net, weights, records, valid, count, n, workspace, dW, dgrid, loss, stream);
   if (e != hipSuccess) return hip_fail(e, "nrc_train launch");
   return ok();
+}
+
+int64_t drt_nrc_query_ints(int64_t capacity) {
+  return capacity < 0 ? 0 : 3 * capacity + kQueryBins;
 }
 
 drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
-                                     int32_t* query_pixels, int32_t* query_count,
+                                     int32_t* query_ints, int32_t* query_count,
                                      int64_t capacity, float* image, void* hip_stream) {
   DParams dp;
   DCams dc;
@@ -855,25 +894,19 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
   DNrcNet net;
   st = nrc_net(cfg, grid, &net);
   if (st != DRT_OK) return st;
-  if (!weights || !grid || !queries || !query_pixels || !query_count || !image)
+  if (!weights || !grid || !queries || !query_ints || !query_count || !image)
     return fail(DRT_EINVAL, "null pointer argument");
   int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
   hipStream_t stream = (hipStream_t)hip_stream;
+  DNrcIO io = query_io(net, cfg, queries, query_ints, query_count, capacity);
   hipError_t e = launch_zero(query_count, 1, stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
-  DNrcIO io = {};
-  io.rec = queries;
-  io.qpix = query_pixels;
-  io.count = query_count;
-  io.capacity = capacity;
-  io.K = cfg->trunc_vertex;
   e = launch_render_cached(scene->dev, dp, dc, dr, image, io, stream);
   if (e != hipSuccess) return hip_fail(e, "render_cached launch");
-  e = launch_nrc_infer(net, weights, queries, query_pixels, query_count, need,
-                       1.0f / (float)opts->spp, image, stream);
-  if (e != hipSuccess) return hip_fail(e, "nrc_infer launch");
+  e = answer_queries(net, weights, io, need, 1.0f / (float)opts->spp, image, stream);
+  if (e != hipSuccess) return hip_fail(e, "cache query launch");
   return ok();
 }
 
@@ -881,7 +914,7 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
-                                     int32_t* query_ids, int32_t* query_count, int64_t capacity,
+                                     int32_t* query_ints, int32_t* query_count, int64_t capacity,
                                      float* sample_radiance, const float* adj_image,
                                      const drt_grads* grads, void* hip_stream) {
   DParams dp;
@@ -892,7 +925,7 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   DNrcNet net;
   st = nrc_net(cfg, grid, &net);
   if (st != DRT_OK) return st;
-  if (!weights || !grid || !queries || !query_ids || !query_count || !sample_radiance ||
+  if (!weights || !grid || !queries || !query_ints || !query_count || !sample_radiance ||
       !adj_image || !grads)
     return fail(DRT_EINVAL, "null pointer argument");
   int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
@@ -903,20 +936,14 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
   dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
   hipStream_t stream = (hipStream_t)hip_stream;
+  DNrcIO io = query_io(net, cfg, queries, query_ints, query_count, capacity);
+  io.lsamp = sample_radiance;
   hipError_t e = launch_zero(query_count, 1, stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
-  DNrcIO io = {};
-  io.rec = queries;
-  io.qpix = query_ids;
-  io.count = query_count;
-  io.capacity = capacity;
-  io.K = cfg->trunc_vertex;
-  io.lsamp = sample_radiance;
   e = launch_render_cached(scene->dev, dp, dc, dr, nullptr, io, stream);
   if (e != hipSuccess) return hip_fail(e, "render_cached launch");
-  e = launch_nrc_infer(net, weights, queries, query_ids, query_count, need, 1.0f, sample_radiance,
-                       stream);
-  if (e != hipSuccess) return hip_fail(e, "nrc_infer launch");
+  e = answer_queries(net, weights, io, need, 1.0f, sample_radiance, stream);
+  if (e != hipSuccess) return hip_fail(e, "cache query launch");
   e = launch_render_adjoint_cached(scene->dev, dp, dc, dr, adj_image, dg, io, stream);
   if (e != hipSuccess) return hip_fail(e, "render_adjoint_cached launch");
   return ok();

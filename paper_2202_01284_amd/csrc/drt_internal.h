@@ -136,7 +136,26 @@ struct DNrcIO {
   int64_t capacity; // queries the buffer holds
   int K;            // record vertex index
   float* lsamp;     // per-sample radiance [n_samples][3] (cached adjoint), else null
+  uint32_t* qbin;   // queries: spatial bin of each query (null: not binned)
+  float lo[3], inv_ext[3];  // scene box of the cache (query binning)
 };
+
+// Spatial binning of cache queries: 16 cells per axis of the cache's box,
+// Morton order (12 bits), so that bin-sorted queries gather nearby table entries.
+constexpr int kQueryBinBits = 4;
+constexpr int kQueryBins = 1 << (3 * kQueryBinBits);
+__host__ __device__ inline uint32_t query_bin(float x, float y, float z, const float lo[3],
+                                              const float inv_ext[3]) {
+  const float v[3] = {x, y, z};
+  uint32_t m = 0;
+  for (int a = 0; a < 3; ++a) {
+    float t = (v[a] - lo[a]) * inv_ext[a] * (float)(1 << kQueryBinBits);
+    int c = (int)t;
+    c = c < 0 ? 0 : (c > (1 << kQueryBinBits) - 1 ? (1 << kQueryBinBits) - 1 : c);
+    for (int b = 0; b < kQueryBinBits; ++b) m |= (uint32_t)((c >> b) & 1) << (3 * b + a);
+  }
+  return m;
+}
 
 // Launchers (drt_kernels.hip).
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
@@ -168,13 +187,18 @@ hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, 
                                float* dW, float* dx, hipStream_t st);
 hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
                              hipStream_t st);
+// Counting sort of the queries by spatial bin: order[] = query indices, bin
+// by bin.  hist: kQueryBins words of scratch.
+hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t capacity,
+                             uint32_t* hist, int* order, hipStream_t st);
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
-                            const int* count, int64_t capacity, float inv_spp, float* image,
-                            hipStream_t st);
+                            const int* order, const int* count, int64_t capacity, float inv_spp,
+                            float* image, hipStream_t st);
 hipError_t launch_nrc_grid_backward(const DNrcNet& net, const float* rec, const float* dx,
                                     int64_t n, float* dgrid, hipStream_t st);
-hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
-                            const int* count, int64_t n, float* dW, float* dgrid, float* loss,
-                            hipStream_t st);
+int64_t nrc_train_workspace_bytes(int64_t n);
+hipError_t launch_nrc_train2(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+                             const int* count, int64_t n, void* ws, float* dW, float* dgrid,
+                             float* loss, hipStream_t st);
 
 }  // namespace drt

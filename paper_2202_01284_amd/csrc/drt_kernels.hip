@@ -808,6 +808,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                 if (slot < io.capacity) {
                   rec = io.rec + (size_t)NRC_REC * slot;
                   io.qpix[slot] = MODE == MODE_CACHED_SAMPLES ? (int)glo : (int)pix;
+                  if (io.qbin) io.qbin[slot] = query_bin(p.x, p.y, p.z, io.lo, io.inv_ext);
                   rec[13] = beta.x;
                   rec[14] = beta.y;
                   rec[15] = beta.z;

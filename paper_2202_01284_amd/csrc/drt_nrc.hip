@@ -470,10 +470,114 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float
   }
 }
 
-// Cache queries: image[pixel] += beta * max(C(record), 0) / spp.
+// Counting sort of cache queries by spatial bin (three launches): per-block
+// LDS histograms added to hist; one-block exclusive scan of hist; per-block
+// ranges reserved in the scanned cursors and filled through LDS atomics.  The
+// order inside a bin is arbitrary.  Blocks take the same grid-stride subsets
+// in the first and last launch.
+constexpr int kSortBlocks = 256;
+
+// What is sorted: cache queries with precomputed bins (qbin, first *count
+// of capacity), or training records binned from their positions (valid ones
+// of n, qbin null).
+struct BinSrc {
+  const uint32_t* qbin;
+  const int* count;
+  int64_t capacity;
+  const float* rec;
+  const int* valid;
+  float lo[3], inv_ext[3];
+};
+DEV int64_t bin_n(const BinSrc& b) { return b.count ? min((int64_t)*b.count, b.capacity) : b.capacity; }
+DEV bool bin_of(const BinSrc& b, int64_t i, uint32_t& bin) {
+  if (b.qbin) {
+    bin = b.qbin[i];
+    return true;
+  }
+  if (!b.valid[i]) return false;
+  const float* r = b.rec + i * NRC_REC;
+  bin = query_bin(r[0], r[1], r[2], b.lo, b.inv_ext);
+  return true;
+}
+
+__global__ __launch_bounds__(kBlockN) void k_query_hist(BinSrc src, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kQueryBins];
+  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN) h[i] = 0;
+  __syncthreads();
+  const int64_t n = bin_n(src);
+  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlockN) {
+    uint32_t b;
+    if (bin_of(src, i, b)) atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist) {
+  static_assert(kQueryBins == 4 * 1024, "one block of 1024 threads, 4 bins each");
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  uint32_t a[4], sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = hist[4 * t + k];
+    sum += a[k];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hist[4 * t + k] = run;
+    run += a[k];
+  }
+}
+
+__global__ __launch_bounds__(kBlockN) void k_query_scatter(BinSrc src, uint32_t* __restrict__ cursor,
+                                                          int* __restrict__ order) {
+  __shared__ uint32_t h[kQueryBins];
+  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN) h[i] = 0;
+  __syncthreads();
+  const int64_t n = bin_n(src);
+  const int64_t stride = (int64_t)gridDim.x * kBlockN;
+  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += stride) {
+    uint32_t b;
+    if (bin_of(src, i, b)) atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN)
+    if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += stride) {
+    uint32_t b;
+    if (bin_of(src, i, b)) order[atomicAdd(&h[b], 1u)] = (int)i;
+  }
+}
+
+static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hipStream_t st) {
+  hipError_t e = launch_zero(hist, kQueryBins, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_query_hist, dim3(kSortBlocks), dim3(kBlockN), 0, st, src, hist);
+  hipLaunchKernelGGL(k_query_scan, dim3(1), dim3(1024), 0, st, hist);
+  hipLaunchKernelGGL(k_query_scatter, dim3(kSortBlocks), dim3(kBlockN), 0, st, src, hist, order);
+  return hipGetLastError();
+}
+
+// Cache queries: image[qpix] += beta * max(C(record), 0) * inv_spp, for the
+// queries in `order` (spatially sorted; null: in slot order).  Each XCD
+// (workgroups are dealt to the 8 XCDs round-robin) walks its own contiguous
+// range of tiles, so its L2 holds the table entries of one region at a time.
 __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float* __restrict__ W,
                                                       const float* __restrict__ q,
                                                       const int* __restrict__ qpix,
+                                                      const int* __restrict__ order,
                                                       const int* __restrict__ count,
                                                       int64_t capacity, float inv_spp,
                                                       float* __restrict__ image) {
@@ -485,12 +589,18 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float*
   const int64_t n = min((int64_t)*count, capacity);
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const int64_t n_tiles = (n + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
-  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
-  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
-    int64_t sample = tile * 16 + (lane & 15);
-    bool valid = sample < n;
-    const float* rec = q + (valid ? sample : 0) * NRC_REC;
+  const int n_x = min(8, (int)gridDim.x);
+  const int xcd = blockIdx.x % n_x;
+  const int64_t blocks_x = (gridDim.x - 1 - xcd) / n_x + 1;
+  const int64_t waves_x = blocks_x * (kBlockN / 64);
+  const int64_t per = (n_tiles + n_x - 1) / n_x;
+  const int64_t t1 = min(n_tiles, (int64_t)(xcd + 1) * per);
+  for (int64_t tile = (int64_t)xcd * per + (blockIdx.x / n_x) * (kBlockN / 64) + (threadIdx.x >> 6);
+       tile < t1; tile += waves_x) {
+    int64_t slot = tile * 16 + (lane & 15);
+    bool valid = slot < n;
+    int64_t qi = valid ? (order ? (int64_t)order[slot] : slot) : 0;
+    const float* rec = q + qi * NRC_REC;
     float in[5][4];
     encode_lane(net, gl, rec, valid, g, in);
     Acts A;
@@ -498,7 +608,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float*
     for (int s = 0; s < 5; ++s) A.h0[s] = pack4(in[s][0], in[s][1], in[s][2], in[s][3]);
     f32x4 y = forward_tile(wl, A, lane);
     if (g == 0 && valid) {
-      float* px = image + 3 * (size_t)qpix[sample];
+      float* px = image + 3 * (size_t)qpix[qi];
       float c0 = rec[13] * fmaxf(y[0], 0.f) * inv_spp;
       float c1 = rec[14] * fmaxf(y[1], 0.f) * inv_spp;
       float c2 = rec[15] * fmaxf(y[2], 0.f) * inv_spp;
@@ -509,37 +619,63 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float*
   }
 }
 
-// One training pass over records [n][16] with valid flags: relative-L2 loss
-// (mean over valid records and channels), dW and hash-grid gradients
-// accumulated (FP32 atomics), loss added to loss[0].
-__global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float* __restrict__ W,
-                                                      const float* __restrict__ rec,
-                                                      const int* __restrict__ valid,
-                                                      const int* __restrict__ count, int64_t n,
-                                                      float* __restrict__ dW,
-                                                      float* __restrict__ dgrid,
-                                                      float* __restrict__ loss) {
+// ---------------------------------------------------------------------------
+// training in two phases
+// ---------------------------------------------------------------------------
+// Phase 1 (k_nrc_train_fb): per 16-record tile, forward, relative-L2 output
+// gradient, backward propagation of the deltas (no weight gradient), hash-grid
+// gradient atomics, and the tile's operands of the weight gradient written to
+// a workspace: 38 chunks of 16 features x 16 samples, each stored as the
+// register layout holds it (lane r + 16g: features 4g..4g+3 of sample r, one
+// 8-byte store per lane).  Chunk map: h0 0-4, h1 5-8, h2 9-12, h3 13-16,
+// h4 17-20 (layer inputs), g1 21-24, g2 25-28, g3 29-32, g4 33-36 (masked
+// gradients of the hidden outputs), dy 37 (output gradient, rows 0..2).
+// Phase 2 (k_nrc_dw, k_nrc_dw_reduce): dW_l = sum over records of
+// delta_l (x) h_l, split over records.
+constexpr int kChunks = 38;
+
+// Store one chunk transposed to the operand layout of the weight gradient:
+// lane r + 16g of the stored chunk holds feature r, samples 4g..4g+3.  The
+// register layout (features 4g..4g+3 of sample r) is turned through a
+// 16x16 bf16 block of this wave's LDS.
+DEV void put_chunk(bf16x4* ws, uint16_t* tb, int64_t tile, int c, bf16x4 v, int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) tb[(4 * g + j) * 16 + r] = (uint16_t)v[j];
+  __builtin_amdgcn_wave_barrier();
+  ws[((size_t)tile * kChunks + c) * 64 + lane] = *reinterpret_cast<const bf16x4*>(tb + r * 16 + 4 * g);
+}
+
+// Records are taken in the spatially sorted order of the valid ones
+// (order[0 .. *count)), so a tile's records are close together.
+__global__ __launch_bounds__(kBlockN) void k_nrc_train_fb(DNrcNet net, const float* __restrict__ W,
+                                                         const float* __restrict__ rec,
+                                                         const int* __restrict__ order,
+                                                         const int* __restrict__ count, int64_t n,
+                                                         bf16x4* __restrict__ ws,
+                                                         float* __restrict__ dgrid,
+                                                         float* __restrict__ loss) {
   __shared__ uint16_t wl[kLdsW];
-  __shared__ float dwl[kLdsDW];
-  __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
+  __shared__ uint16_t tbuf[kBlockN / 64][256];
   __shared__ GridLds gl;
   __shared__ float loss_acc;
   stage_weights(wl, W);
   load_grid_tables(gl, net);
-  for (int i = threadIdx.x; i < kLdsDW; i += blockDim.x) dwl[i] = 0.f;
   if (threadIdx.x == 0) loss_acc = 0.f;
   __syncthreads();
-  const int n_valid = *count;
+  uint16_t* tb = tbuf[threadIdx.x >> 6];
+  const int64_t n_valid = min((int64_t)*count, n);
   const float inv = n_valid > 0 ? 1.0f / (3.0f * (float)n_valid) : 0.f;
   const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t n_tiles = (n_valid + 15) / 16;
   const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
   float my_loss = 0.f;
   for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
-    int64_t sample = tile * 16 + (lane & 15);
-    bool ok = sample < n && valid[sample] != 0;
-    const float* r = rec + (sample < n ? sample : 0) * NRC_REC;
+    int64_t slot = tile * 16 + (lane & 15);
+    bool ok = slot < n_valid;
+    const float* r = rec + (ok ? (int64_t)order[slot] : 0) * NRC_REC;
     float in[5][4];
     encode_lane(net, gl, r, ok, g, in);
     Acts A;
@@ -556,8 +692,50 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float*
         d[c] = 2.0f * e / den * inv;
       }
     }
+    const bf16x4 dyb = g == 0 ? pack4(d[0], d[1], d[2], 0.f) : zero_b();
+    bf16x4 g4[4], g3[4], g2[4], g1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 acc = zero4();
+      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW3, 64, t, s, lane), g4[s], acc);
+      g3[t] = mask_pack(acc, A.h3[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 acc = zero4();
+      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW2, 64, t, s, lane), g3[s], acc);
+      g2[t] = mask_pack(acc, A.h2[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f32x4 acc = zero4();
+      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
+      g1[t] = mask_pack(acc, A.h1[t]);
+    }
     f32x4 dx[2];
-    backward_tile(wl, dwl, st[threadIdx.x >> 6], A, d, dx, lane);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      f32x4 acc = zero4();
+      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
+      dx[t] = acc;
+    }
+    // operands of the weight gradient
+#pragma unroll
+    for (int c = 0; c < 5; ++c) put_chunk(ws, tb, tile, c, A.h0[c], lane);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      put_chunk(ws, tb, tile, 5 + c, A.h1[c], lane);
+      put_chunk(ws, tb, tile, 9 + c, A.h2[c], lane);
+      put_chunk(ws, tb, tile, 13 + c, A.h3[c], lane);
+      put_chunk(ws, tb, tile, 17 + c, A.h4[c], lane);
+      put_chunk(ws, tb, tile, 21 + c, g1[c], lane);
+      put_chunk(ws, tb, tile, 25 + c, g2[c], lane);
+      put_chunk(ws, tb, tile, 29 + c, g3[c], lane);
+      put_chunk(ws, tb, tile, 33 + c, g4[c], lane);
+    }
+    put_chunk(ws, tb, tile, 37, dyb, lane);
     if (ok) {
       // this lane holds d/d inputs {4g+j} and {16+4g+j}: levels 2g, 2g+1, 8+2g, 9+2g
       float xn[3];
@@ -583,8 +761,93 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train(DNrcNet net, const float*
   }
   if (my_loss != 0.f) atomicAdd(&loss_acc, my_loss * inv);
   __syncthreads();
-  flush_dw(dwl, dW);
   if (threadIdx.x == 0 && loss_acc != 0.f) atomicAdd(loss, loss_acc);
+}
+
+// Phase 2: workgroup b takes record tiles [b T, (b+1) T) and writes its
+// partial weight gradient to part[b][17600]; k_nrc_dw_reduce adds the
+// partials into dW.  Wave 0 owns layer 0 (20 output tiles), waves 1 and 2
+// layers 1 and 2 (16 each), wave 3 layers 3 and 4 (16 + 4); operands come
+// straight from the workspace (already in operand layout, one 8-byte load
+// per lane) and the sums stay in MFMA accumulators.
+constexpr int kDwBlockTiles = 16;
+
+template <int NO, int NI>
+DEV void dw_layer(const bf16x4* __restrict__ ws, int64_t t0, int64_t t1, int dc0, int hc0,
+                  f32x4 (&acc)[NO][NI], int lane) {
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    const bf16x4* base = ws + (size_t)tile * kChunks * 64 + lane;
+    bf16x4 a[NO], b[NI];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) a[o] = base[(dc0 + o) * 64];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) b[i] = base[(hc0 + i) * 64];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int i = 0; i < NI; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
+  }
+}
+
+// D[4g + j][r] of output tile (o, i) = dW[16 o + 4g + j][16 i + r]
+template <int NO, int NI>
+DEV void dw_store(float* __restrict__ part, int base, int K, int rows, const f32x4 (&acc)[NO][NI],
+                  int lane) {
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * o + 4 * g + j;
+        if (row < rows) part[base + row * K + 16 * i + r] = acc[o][i][j];
+      }
+}
+
+template <int NO, int NI>
+DEV void dw_job(const bf16x4* ws, int64_t t0, int64_t t1, int dc0, int hc0, float* part, int base,
+                int K, int rows, int lane) {
+  f32x4 acc[NO][NI];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int i = 0; i < NI; ++i) acc[o][i] = zero4();
+  dw_layer<NO, NI>(ws, t0, t1, dc0, hc0, acc, lane);
+  dw_store<NO, NI>(part, base, K, rows, acc, lane);
+}
+
+__global__ __launch_bounds__(kBlockN) void k_nrc_dw(const bf16x4* __restrict__ ws,
+                                                   const int* __restrict__ count, int64_t n,
+                                                   float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t n_tiles = (min((int64_t)*count, n) + 15) / 16;   // tiles phase 1 wrote
+  const int64_t t0 = (int64_t)blockIdx.x * kDwBlockTiles;
+  const int64_t t1 = min(n_tiles, t0 + kDwBlockTiles);
+  float* p = part + (size_t)blockIdx.x * (kW4 + 3 * 64);
+  if (wv == 0) {
+    dw_job<4, 5>(ws, t0, t1, 21, 0, p, kW0, 80, 64, lane);
+  } else if (wv == 1) {
+    dw_job<4, 4>(ws, t0, t1, 25, 5, p, kW1, 64, 64, lane);
+  } else if (wv == 2) {
+    dw_job<4, 4>(ws, t0, t1, 29, 9, p, kW2, 64, 64, lane);
+  } else {
+    dw_job<4, 4>(ws, t0, t1, 33, 13, p, kW3, 64, 64, lane);
+    dw_job<1, 4>(ws, t0, t1, 37, 17, p, kW4, 64, 3, lane);
+  }
+}
+
+// dW[i] += sum over workgroups b of part[b][i]: workgroup (x, y) sums
+// partials 16y .. 16y+15 of weights 256x .. 256x+255 and adds the sum.
+constexpr int kReduceSlice = 16;
+__global__ __launch_bounds__(kBlockN) void k_nrc_dw_reduce(const float* __restrict__ part, int nb,
+                                                          float* __restrict__ dW) {
+  const int i = blockIdx.x * kBlockN + threadIdx.x;
+  if (i >= kW4 + 3 * 64) return;
+  const int b0 = blockIdx.y * kReduceSlice, b1 = min(nb, b0 + kReduceSlice);
+  float s = 0.f;
+  for (int b = b0; b < b1; ++b) s += part[(size_t)b * (kW4 + 3 * 64) + i];
+  if (s != 0.f) atomicAdd(dW + i, s);
 }
 
 // Hash-grid gradient only: dgrid += trilinear scatter of dx [n][80] (inputs
@@ -649,20 +912,60 @@ hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, fl
   hipLaunchKernelGGL(k_nrc_encode, dim3(grid_for(n, 4096)), dim3(kBlockN), 0, st, net, rec, n, x);
   return hipGetLastError();
 }
+hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t capacity,
+                             uint32_t* hist, int* order, hipStream_t st) {
+  BinSrc src = {};
+  src.qbin = qbin;
+  src.count = count;
+  src.capacity = capacity;
+  return sort_by_bin(src, hist, order, st);
+}
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
-                            const int* count, int64_t capacity, float inv_spp, float* image,
-                            hipStream_t st) {
+                            const int* order, const int* count, int64_t capacity, float inv_spp,
+                            float* image, hipStream_t st) {
   // persistent: 4 workgroups per CU (LDS-limited), each wave loops over tiles
   hipLaunchKernelGGL(k_nrc_infer, dim3(grid_for(capacity, 1024)), dim3(kBlockN), 0, st, net, W, q,
-                     qpix, count, capacity, inv_spp, image);
+                     qpix, order, count, capacity, inv_spp, image);
   return hipGetLastError();
 }
-hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
-                            const int* count, int64_t n, float* dW, float* dgrid, float* loss,
-                            hipStream_t st) {
-  // one workgroup per CU fits in LDS; every workgroup flushes 17,600 dW atomics
-  hipLaunchKernelGGL(k_nrc_train, dim3(grid_for(n, 256)), dim3(kBlockN), 0, st, net, W, rec,
-                     valid, count, n, dW, dgrid, loss);
+// workspace: operand chunks of every record tile | phase-2 partials |
+// sorted record order [n] | bin histogram
+static int64_t dw_blocks(int64_t n) { return ((n + 15) / 16 + kDwBlockTiles - 1) / kDwBlockTiles; }
+static int64_t ws_chunk_bytes(int64_t n) { return ((n + 15) / 16) * kChunks * 64 * 8; }
+static int64_t ws_part_bytes(int64_t n) { return dw_blocks(n) * (kW4 + 3 * 64) * 4; }
+int64_t nrc_train_workspace_bytes(int64_t n) {
+  return ws_chunk_bytes(n) + ws_part_bytes(n) + n * 4 + kQueryBins * 4;
+}
+
+hipError_t launch_nrc_train2(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+                             const int* count, int64_t n, void* ws, float* dW, float* dgrid,
+                             float* loss, hipStream_t st) {
+  const int64_t n_tiles = (n + 15) / 16;
+  if (n_tiles == 0) return hipSuccess;
+  char* base = static_cast<char*>(ws);
+  float* part = reinterpret_cast<float*>(base + ws_chunk_bytes(n));
+  int* order = reinterpret_cast<int*>(base + ws_chunk_bytes(n) + ws_part_bytes(n));
+  uint32_t* hist = reinterpret_cast<uint32_t*>(order + n);
+  BinSrc src = {};
+  src.capacity = n;
+  src.rec = rec;
+  src.valid = valid;
+  for (int a = 0; a < 3; ++a) {
+    src.lo[a] = net.lo[a];
+    src.inv_ext[a] = net.inv_ext[a];
+  }
+  hipError_t e = sort_by_bin(src, hist, order, st);
+  if (e != hipSuccess) return e;
+  // 2 workgroups per CU fit in registers; waves loop over tiles
+  hipLaunchKernelGGL(k_nrc_train_fb, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, net, W, rec,
+                     order, count, n, reinterpret_cast<bf16x4*>(ws), dgrid, loss);
+  const int64_t blocks = dw_blocks(n);
+  hipLaunchKernelGGL(k_nrc_dw, dim3((unsigned)blocks), dim3(kBlockN), 0, st,
+                     reinterpret_cast<const bf16x4*>(ws), count, n, part);
+  hipLaunchKernelGGL(k_nrc_dw_reduce,
+                     dim3((kW4 + 3 * 64 + kBlockN - 1) / kBlockN,
+                          (unsigned)((blocks + kReduceSlice - 1) / kReduceSlice)),
+                     dim3(kBlockN), 0, st, part, (int)blocks, dW);
   return hipGetLastError();
 }
 

@@ -216,6 +216,41 @@ def test_cached_render_vs_oracle():
     check_image(img.cpu().numpy(), ref, "cached render", amb)
 
 
+def test_query_sort_is_a_bin_ordered_permutation():
+    """After a cached render the int scratch holds, per query, its spatial bin
+    (16^3 Morton cell of the cache box) and the bin-sorted order: a
+    permutation of the query slots with non-decreasing bins."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=96, height=80)
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    spp = 3
+    cap = 96 * 80 * spp + 17
+    work = drt.cached_work(cap)
+    drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+                              torch.from_numpy(grid.reshape(-1)).cuda(), spp=spp, seed=5, work=work)
+    q, ints, count = (t.cpu().numpy() for t in work)
+    n = int(count[0])
+    assert 0 < n <= 96 * 80 * spp
+    order = ints[cap:cap + n]
+    bins = ints[2 * cap:2 * cap + n].view(np.uint32)
+    np.testing.assert_array_equal(np.sort(order), np.arange(n))
+    assert np.all(np.diff(bins[order].astype(np.int64)) >= 0)
+    # bins agree with the positions: Morton code of the 16^3 cell
+    lo, hi = np.array(cfg["bbox_lo"], np.float32), np.array(cfg["bbox_hi"], np.float32)
+    inv = (1.0 / (hi.astype(np.float64) - lo)).astype(np.float32)
+    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(16)).astype(np.int64), 0, 15)
+    m = np.zeros(n, np.int64)
+    for b in range(4):
+        for a in range(3):
+            m |= ((c[:, a] >> b) & 1) << (3 * b + a)
+    agree = (m == bins).mean()
+    print("queries", n, "bins used", len(np.unique(bins)), "bin agreement", agree, flush=True)
+    assert agree >= 0.999          # float32 rounding at cell faces may differ
+
+
 def _cached_adjoint_case(zero_network=False):
     drt = _drt()
     sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64))
