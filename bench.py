@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Algorithmic work per counted unit (derivation in the design notes):
-FLOP_PER_NODE = 40.0      # two child slab tests
+FLOP_PER_NODE = 80.0      # four child slab tests (four-wide BVH node)
 FLOP_PER_TRI = 40.0       # one watertight triangle test
 FLOP_PER_VERTEX = 200.0   # shading a scattering vertex: frame, BSDF eval + sample, light sample, MIS
 PEAK_FP32_VALU = 78.6     # TFLOP/s: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32

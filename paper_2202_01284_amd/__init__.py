@@ -294,7 +294,7 @@ class Scene:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and lib is not None:          # module globals may be gone at interpreter exit
             lib.drt_scene_destroy(h)
             self.handle = None
 

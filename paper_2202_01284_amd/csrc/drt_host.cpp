@@ -241,13 +241,8 @@ struct Builder {
 };
 
 void set_child_box(DNode& n, int slot, const Box& b) {
-  if (slot == 0) {
-    n.lo0x = b.lo[0]; n.lo0y = b.lo[1]; n.lo0z = b.lo[2];
-    n.hi0x = b.hi[0]; n.hi0y = b.hi[1]; n.hi0z = b.hi[2];
-  } else {
-    n.lo1x = b.lo[0]; n.lo1y = b.lo[1]; n.lo1z = b.lo[2];
-    n.hi1x = b.hi[0]; n.hi1y = b.hi[1]; n.hi1z = b.hi[2];
-  }
+  n.lox[slot] = b.lo[0]; n.loy[slot] = b.lo[1]; n.loz[slot] = b.lo[2];
+  n.hix[slot] = b.hi[0]; n.hiy[slot] = b.hi[1]; n.hiz[slot] = b.hi[2];
 }
 
 }  // namespace
@@ -332,35 +327,54 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
     b.nodes[root].child[1] = r;
   }
 
-  // flatten: every interior build node becomes a DNode (pre-order)
+  // four-wide nodes: every binary interior node at even depth becomes one;
+  // its children are its grandchildren, or a child itself where that child
+  // is a leaf (pre-order numbering)
+  auto slots_of = [&](int id, int out[4]) {
+    int n = 0;
+    for (int c : b.nodes[id].child) {
+      const BuildNode& cn = b.nodes[c];
+      if (cn.child[0] < 0) out[n++] = c;
+      else { out[n++] = cn.child[0]; out[n++] = cn.child[1]; }
+    }
+    return n;
+  };
   std::vector<int> dn_of(b.nodes.size(), -1);
   std::vector<int> order;
   std::vector<int> stack{root};
   while (!stack.empty()) {
     int id = stack.back();
     stack.pop_back();
-    const BuildNode& bn = b.nodes[id];
-    if (bn.child[0] < 0) continue;
     dn_of[id] = (int)order.size();
     order.push_back(id);
-    if (bn.child[0] >= 0) {
-      stack.push_back(bn.child[1]);
-      stack.push_back(bn.child[0]);
-    }
+    int sl[4];
+    int n = slots_of(id, sl);
+    for (int k = n - 1; k >= 0; --k)
+      if (b.nodes[sl[k]].child[0] >= 0) stack.push_back(sl[k]);
   }
   DNode* nodes = (DNode*)&P->bytes[off[0]];
   int n_leaves = 0;
   for (size_t k = 0; k < order.size(); ++k) {
-    const BuildNode& bn = b.nodes[order[k]];
     DNode& n = nodes[k];
     std::memset(&n, 0, sizeof(n));
-    for (int s = 0; s < 2; ++s) {
-      const BuildNode& ch = b.nodes[bn.child[s]];
+    int sl[4];
+    int ns = slots_of(order[k], sl);
+    for (int s = 0; s < 4; ++s) {
+      if (s >= ns) {
+        n.child[s] = 0;
+        n.count[s] = -1;
+        continue;
+      }
+      const BuildNode& ch = b.nodes[sl[s]];
       set_child_box(n, s, ch.box);
-      int c, cnt;
-      if (ch.child[0] < 0) { c = ch.begin; cnt = ch.count; ++n_leaves; }
-      else { c = dn_of[bn.child[s]]; cnt = 0; }
-      if (s == 0) { n.c0 = c; n.n0 = cnt; } else { n.c1 = c; n.n1 = cnt; }
+      if (ch.child[0] < 0) {
+        n.child[s] = ch.begin;
+        n.count[s] = ch.count;
+        ++n_leaves;
+      } else {
+        n.child[s] = dn_of[sl[s]];
+        n.count[s] = 0;
+      }
     }
   }
   // triangles in leaf order

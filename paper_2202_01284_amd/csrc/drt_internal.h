@@ -11,25 +11,27 @@
 
 namespace drt {
 
-// BVH traversal stack depth (entries per lane, held in LDS).  The builder
-// guarantees that no path from the root crosses more than
-// kMaxInteriorDepth interior nodes, so the stack never holds more than
-// kMaxInteriorDepth + 1 <= kStackDepth entries.
-constexpr int kStackDepth = 32;
-constexpr int kMaxInteriorDepth = 30;
+// BVH traversal stack depth (entries per lane, held in LDS).  The binary
+// build keeps interior nodes at depth < kMaxInteriorDepth; the four-wide
+// nodes are the binary interior nodes at even depth (so at most 12 levels
+// of them), and a visit pushes at most 3 children, so the stack never holds
+// more than 3 x 12 = 36 <= kStackDepth entries.  38 entries x 256 lanes
+// keep four workgroups per CU within the 160 KB of LDS.
+constexpr int kStackDepth = 38;
+constexpr int kMaxInteriorDepth = 24;
 constexpr int kBlock = 256;            // threads per workgroup of the megakernels
 constexpr int kTile = 16;              // workgroup = 16 x 16 pixel tile
 constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
 
-// Two-child BVH node, 64 bytes: the boxes of both children and, per child,
-// either an interior node index (n == 0) or a leaf's triangle range.
+// Four-child BVH node, 128 bytes (one L2 line): the children's boxes as
+// structure of arrays and, per child, an interior node index (count 0), a
+// leaf's triangle range (count > 0) or nothing (count -1).
 struct alignas(16) DNode {
-  float lo0x, lo0y, lo0z, hi0x;
-  float hi0y, hi0z, lo1x, lo1y;
-  float lo1z, hi1x, hi1y, hi1z;
-  int32_t c0, c1, n0, n1;
+  float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+  int32_t child[4];
+  int32_t count[4];
 };
-static_assert(sizeof(DNode) == 64, "DNode");
+static_assert(sizeof(DNode) == 128, "DNode");
 
 // Triangle in BVH leaf order, 48 bytes: vertices, original id, flags.
 struct alignas(16) DTri {

@@ -202,6 +202,17 @@ DEV DTri load_tri(const DScene& s, int i) {
 // together whatever ray each carries.
 // any = false: closest hit in (tmin, tmax), ties to the lowest original id.
 // any = true: true iff a non-null triangle is hit in (tmin, tmax).
+DEV void cswap(float& ka, int& va, float& kb, int& vb) {
+  if (kb < ka) {
+    float k = ka; ka = kb; kb = k;
+    int v = va; va = vb; vb = v;
+  }
+}
+
+// Closest (any = false) or any hit in (tmin, tmax] over the four-wide BVH.
+// Per node: four slab tests; the triangles of every hit leaf child in one
+// loop; hit interior children sorted near to far, the nearest visited next
+// and the others pushed far first.
 DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool any, Hit& h,
                   int* stk, Counters& cnt) {
   float tbest = tmax;
@@ -211,17 +222,21 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
   int node = 0, sp = 0;
   for (;;) {
     const float4* np = reinterpret_cast<const float4*>(s.nodes + node);
-    float4 a = np[0], b = np[1], c = np[2];
-    int4 q = reinterpret_cast<const int4*>(np)[3];
+    const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+    const int4 ch = reinterpret_cast<const int4*>(np)[6], cn = reinterpret_cast<const int4*>(np)[7];
     cnt.nodes++;
-    float tn0, tn1;
-    bool h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, tn0);
-    bool h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, tn1);
-    // leaf children: test their triangles now (one loop over both ranges)
-    int l0 = (h0 && q.z > 0) ? q.z : 0;
-    int l1 = (h1 && q.w > 0) ? q.w : 0;
-    for (int j = 0; j < l0 + l1; ++j) {
-      int i = j < l0 ? q.x + j : q.y + (j - l0);
+    float t0, t1, t2, t3;
+    const bool h0 = cn.x >= 0 && slab(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmin, tbest, t0);
+    const bool h1 = cn.y >= 0 && slab(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmin, tbest, t1);
+    const bool h2 = cn.z >= 0 && slab(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmin, tbest, t2);
+    const bool h3 = cn.w >= 0 && slab(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmin, tbest, t3);
+    // leaf children: test their triangles now (one loop over the ranges)
+    const int e0 = (h0 && cn.x > 0) ? cn.x : 0;
+    const int e1 = e0 + ((h1 && cn.y > 0) ? cn.y : 0);
+    const int e2 = e1 + ((h2 && cn.z > 0) ? cn.z : 0);
+    const int e3 = e2 + ((h3 && cn.w > 0) ? cn.w : 0);
+    for (int j = 0; j < e3; ++j) {
+      const int i = j < e0 ? ch.x + j : (j < e1 ? ch.y + (j - e0) : (j < e2 ? ch.z + (j - e1) : ch.w + (j - e2)));
       DTri T = load_tri(s, i);
       cnt.tris++;
       if (any && (T.flags & 1)) continue;
@@ -245,22 +260,27 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       }
     }
     if (found) break;
-    h0 = h0 && q.z == 0;
-    h1 = h1 && q.w == 0;
-    if (h0 && h1) {
-      bool near0 = tn0 <= tn1;
-      stk[sp * kBlock] = near0 ? q.y : q.x;
-      ++sp;
-      node = near0 ? q.x : q.y;
-    } else if (h0) {
-      node = q.x;
-    } else if (h1) {
-      node = q.y;
-    } else {
+    // interior children hit: keys finite for them, +inf otherwise
+    float k0 = (h0 && cn.x == 0) ? fminf(t0, 3.0e38f) : INFINITY;
+    float k1 = (h1 && cn.y == 0) ? fminf(t1, 3.0e38f) : INFINITY;
+    float k2 = (h2 && cn.z == 0) ? fminf(t2, 3.0e38f) : INFINITY;
+    float k3 = (h3 && cn.w == 0) ? fminf(t3, 3.0e38f) : INFINITY;
+    int v0 = ch.x, v1 = ch.y, v2 = ch.z, v3 = ch.w;
+    cswap(k0, v0, k1, v1);
+    cswap(k2, v2, k3, v3);
+    cswap(k0, v0, k2, v2);
+    cswap(k1, v1, k3, v3);
+    cswap(k1, v1, k2, v2);
+    if (k0 == INFINITY) {
       if (sp == 0) break;
       --sp;
       node = stk[sp * kBlock];
+      continue;
     }
+    node = v0;
+    if (k3 != INFINITY) stk[(sp++) * kBlock] = v3;
+    if (k2 != INFINITY) stk[(sp++) * kBlock] = v2;
+    if (k1 != INFINITY) stk[(sp++) * kBlock] = v1;
   }
   return any ? found : h.tri >= 0;
 }

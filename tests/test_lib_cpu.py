@@ -74,30 +74,52 @@ def test_invalid_arguments_rejected_before_launch():
 # packed BVH walked in NumPy
 # ---------------------------------------------------------------------------
 
-NODE = np.dtype([("b", "<f4", 12), ("c0", "<i4"), ("c1", "<i4"), ("n0", "<i4"), ("n1", "<i4")])
+NODE = np.dtype([("lox", "<f4", 4), ("hix", "<f4", 4), ("loy", "<f4", 4), ("hiy", "<f4", 4),
+                 ("loz", "<f4", 4), ("hiz", "<f4", 4), ("child", "<i4", 4), ("count", "<i4", 4)])
 TRI = np.dtype([("p", "<f4", 9), ("prim", "<i4"), ("flags", "<i4"), ("pad", "<i4")])
+
+
+def _box(nd, s):
+    lo = np.array([nd["lox"][s], nd["loy"][s], nd["loz"][s]])
+    hi = np.array([nd["hix"][s], nd["hiy"][s], nd["hiz"][s]])
+    return lo, hi
 
 
 def _unpack(sc):
     buf, info = drt.scene_pack(sc)
-    nodes = np.frombuffer(buf[:info["n_nodes"] * 64].tobytes(), NODE)
-    off_tris = (info["n_nodes"] * 0 + max(1, sc.n_triangles) * 64 + 255) // 256 * 256
+    nodes = np.frombuffer(buf[:info["n_nodes"] * 128].tobytes(), NODE)
+    off_tris = (max(1, sc.n_triangles) * 128 + 255) // 256 * 256
     tris = np.frombuffer(buf[off_tris:off_tris + 48 * sc.n_triangles].tobytes(), TRI)
     return nodes, tris, info
 
 
-@pytest.mark.parametrize("name", ["soup", "cornell", "zoo", "one"])
+def _depths(nodes):
+    depth = {0: 0}
+    for k, nd in enumerate(nodes):
+        for s in range(4):
+            if nd["count"][s] == 0:
+                depth[int(nd["child"][s])] = depth[k] + 1
+    return depth
+
+
+@pytest.mark.parametrize("name", ["soup", "cornell", "zoo", "one", "big"])
 def test_packed_bvh_structure(name):
     sc = {"soup": lambda: scenes.triangle_soup(500, seed=2), "cornell": scenes.cornell,
-          "zoo": scenes.bsdf_zoo, "one": lambda: scenes.triangle_soup(1, seed=1)}[name]()
+          "zoo": scenes.bsdf_zoo, "one": lambda: scenes.triangle_soup(1, seed=1),
+          "big": lambda: scenes.triangle_soup(20000, seed=5)}[name]()
     nodes, tris, info = _unpack(sc)
-    assert info["max_depth"] <= 30 and info["forced_leaves"] == 0
-    # every triangle referenced by exactly one leaf; leaves' boxes contain their triangles
+    assert info["max_depth"] <= 24 and info["n_nodes"] == len(nodes)
+    # the traversal stack bound: at most 12 levels of four-wide nodes
+    assert max(_depths(nodes).values()) <= 11
+    # every triangle referenced by exactly one leaf; boxes contain what they hold
     seen = np.zeros(sc.n_triangles, int)
     P = sc.positions
     for nd in nodes:
-        for s, (c, n) in enumerate(((nd["c0"], nd["n0"]), (nd["c1"], nd["n1"]))):
-            lo, hi = nd["b"][6 * s:6 * s + 3], nd["b"][6 * s + 3:6 * s + 6]
+        for s in range(4):
+            c, n = int(nd["child"][s]), int(nd["count"][s])
+            if n < 0:
+                continue
+            lo, hi = _box(nd, s)
             if n > 0:
                 for i in range(c, c + n):
                     seen[tris[i]["prim"]] += 1
@@ -106,8 +128,10 @@ def test_packed_bvh_structure(name):
                     np.testing.assert_array_equal(v, P[sc.indices[tris[i]["prim"]]])
             else:
                 ch = nodes[c]
-                assert (ch["b"][[0, 1, 2]] >= lo).all() and (ch["b"][[6, 7, 8]] >= lo).all()
-                assert (ch["b"][[3, 4, 5]] <= hi).all() and (ch["b"][[9, 10, 11]] <= hi).all()
+                for s2 in range(4):
+                    if ch["count"][s2] >= 0:
+                        lo2, hi2 = _box(ch, s2)
+                        assert (lo2 >= lo).all() and (hi2 <= hi).all()
     if name == "one":
         assert (seen == 2).all()   # a single triangle sits in both root children
     else:
@@ -122,9 +146,11 @@ def _walk(nodes, tris, o, d):
     inv = 1.0 / np.where(np.abs(d) < 1e-30, 1e-30, d)
     while stack:
         nd = nodes[stack.pop()]
-        for s, (c, n) in enumerate(((nd["c0"], nd["n0"]), (nd["c1"], nd["n1"]))):
-            lo = nd["b"][6 * s:6 * s + 3].astype(float)
-            hi = nd["b"][6 * s + 3:6 * s + 6].astype(float)
+        for s in range(4):
+            c, n = int(nd["child"][s]), int(nd["count"][s])
+            if n < 0:
+                continue
+            lo, hi = (x.astype(float) for x in _box(nd, s))
             t0, t1 = (lo - o) * inv, (hi - o) * inv
             tn = max(np.minimum(t0, t1).max(), 0.0)
             tf = min(np.maximum(t0, t1).min(), best_t)
