@@ -192,6 +192,28 @@ class OracleScene:
                              _c_int(threads or n_threads_default()), gptr, _p(grough))
         return gtex, grough[:len(self.sc.roughness)]
 
+    def jvp(self, tex_tangents, rough_tangent=None, cams=None, spp=4, max_depth=3, rr_depth=1 << 30,
+            flags=0, seed=2, pixel_ids=None, textures=None, roughness=None, threads=None):
+        """Forward-mode image derivative along (texture tangents, roughness
+        tangent): [n_cams, H, W, 3], or [n, 3] for given pixel ids."""
+        cams = self.sc.cameras if cams is None else cams
+        ca = cam_array(cams)
+        W, H = cams[0].width, cams[0].height
+        full = pixel_ids is None
+        if full:
+            pixel_ids = np.arange(len(cams) * W * H, dtype=np.int64)
+        pixel_ids = np.ascontiguousarray(pixel_ids, np.int64)
+        texs, tptr, rough = self._params(textures, roughness)
+        tt = [None if t is None else np.ascontiguousarray(t, np.float64) for t in tex_tangents]
+        ttp = (_vp * max(1, len(tt)))(*[None if t is None else _p(t) for t in tt])
+        rt = None if rough_tangent is None else np.ascontiguousarray(rough_tangent, np.float64)
+        out = np.zeros((pixel_ids.size, 3))
+        lib().oracle_jvp(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)), _c_int(spp),
+                         _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed), ttp,
+                         None if rt is None else _p(rt), _c_i64(pixel_ids.size), _p(pixel_ids),
+                         _c_int(threads or n_threads_default()), _p(out))
+        return out.reshape(len(cams), H, W, 3) if full else out
+
     def trace(self, o, d, tmin=None, tmax=None, any_hit=False, threads=None):
         """Brute-force ray queries: (prim, t, bary[3], ambiguous)."""
         o = np.ascontiguousarray(o, np.float64).reshape(-1, 3)

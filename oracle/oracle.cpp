@@ -1454,6 +1454,51 @@ void oracle_render(void* h, const float* const* textures, const float* roughness
   });
 }
 
+// Forward-mode derivative of the image along a parameter direction v:
+// out_p = sum over parameters of (d I_p / d param) v_param, per channel, with
+// the same attached/detached split as the reverse sweep (texel albedos and
+// roughness attached through the BSDF values, sampling and MIS weights
+// detached).  tex_tangent[t]: [H][W][3] per texture (may be NULL);
+// rough_tangent: one value per roughness slot (may be NULL).
+void oracle_jvp(void* h, const float* const* textures, const float* roughness,
+                const double* cams, int n_cams, int spp, int max_depth, int rr_depth,
+                uint32_t flags, uint64_t seed, const double* const* tex_tangent,
+                const double* rough_tangent, int64_t n_pix, const int64_t* pixel_ids, int n_threads,
+                double* out) {
+  const Scene& s = *(Scene*)h;
+  Params P{textures, roughness};
+  Opts opt{spp, max_depth, rr_depth, flags, seed};
+  std::vector<Cam> cs;
+  for (int c = 0; c < n_cams; ++c) cs.push_back(make_cam(cams + 12 * c));
+  const int W = cs[0].W, H = cs[0].H;
+  parallel_for(n_pix, n_threads, [&](int, int64_t i) {
+    int64_t pid = pixel_ids[i];
+    int cam = (int)(pid / ((int64_t)W * H));
+    int y = (int)((pid / W) % H), x = (int)(pid % W);
+    RGB acc;
+    for (int sidx = 0; sidx < spp; ++sidx) {
+      uint64_t g = (uint64_t)pid * spp + sidx;
+      Stream st = make_stream(seed, g);
+      V3 o, d;
+      camera_ray(cs[cam], st, x, y, &o, &d);
+      Tangent tl;
+      trace_sample(s, P, opt, st, o, d, nullptr, &tl);
+      for (auto& e : tl.e) {
+        Key k = e.first;
+        if (is_texel(k)) {
+          int tex = (int)((k >> 40) & 0x7FFFFF);
+          int64_t texel = (int64_t)(k & ((1ull << 40) - 1));
+          if (tex_tangent && tex_tangent[tex])
+            for (int c = 0; c < 3; ++c) acc[c] += e.second[c] * tex_tangent[tex][3 * texel + c];
+        } else if (rough_tangent) {
+          for (int c = 0; c < 3; ++c) acc[c] += e.second[c] * rough_tangent[(int)k];
+        }
+      }
+    }
+    for (int c = 0; c < 3; ++c) out[3 * i + c] = acc[c] / spp;
+  });
+}
+
 // Radiance estimates along explicit rays: ray i uses samples g = i*spp + s.
 void oracle_radiance(void* h, const float* const* textures, const float* roughness, int64_t n,
                      const double* o, const double* d, int spp, int max_depth, int rr_depth,
