@@ -215,6 +215,19 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
                               const float* adj_image, const drt_grads* grads, void* hip_stream);
 
+/* Forward-mode derivative of the primal image along a parameter direction
+ * (Sec. "Physically Based Differentiable Rendering" describes the forward
+ * mode used to check and visualise derivatives): image_tangent = d I / d params
+ * . direction, [n_cams][H][W][3] float, written (not added).  The direction
+ * uses the drt_grads layout, read only: direction->textures[t] [H][W][3] per
+ * scene texture (NULL: zero), direction->roughness one value per slot (NULL:
+ * zero).  Same sample streams, detached sampling and attached BSDF values
+ * as drt_render_adjoint, so with equal opts <adj, image_tangent> equals
+ * <gradient from drt_render_adjoint(adj), direction> up to rounding. */
+drt_status drt_render_jvp(const drt_scene* scene, const drt_params* params, const drt_camera* cams,
+                          int32_t n_cams, const drt_render_opts* opts, const drt_grads* direction,
+                          float* image_tangent, void* hip_stream);
+
 /* Ray queries against the scene BVH.
  * rays: device float [n][8] = (ox, oy, oz, tmin, dx, dy, dz, tmax), d unit length.
  * mode 0 (closest): hits[i] = {t, b1, b2, prim} with prim = -1 on a miss;

@@ -113,6 +113,8 @@ _SIGS = {
     "drt_scene_destroy": (_c_i32, [_vp]),
     "drt_render_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                     _c_i32, ctypes.POINTER(drt_render_opts), _vp, _vp]),
+    "drt_render_jvp": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
+                                ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_grads), _vp, _vp]),
     "drt_render_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                     _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                     ctypes.POINTER(drt_grads), _vp]),
@@ -417,6 +419,37 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
                                   adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
            "drt_render_adjoint")
     return grad_textures, grad_roughness
+
+
+def render_jvp(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,
+               rr_depth: int = NO_RR, seed: int = 2, flags: int = 0, tan_textures=None,
+               tan_roughness=None, out=None, stream=None):
+    """Forward-mode image derivative along (tan_textures, tan_roughness):
+    [n_cams, H, W, 3] float32 (device)."""
+    torch = _torch()
+    W, H = cams[0].width, cams[0].height
+    if out is None:
+        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=scene.buffer.device)
+    _expect(out, "out", _image_shape(cams))
+    t = drt_grads()
+    tan_textures = list(tan_textures or [])
+    if len(tan_textures) > len(scene.tex_shapes):
+        raise ValueError("more tangent textures than scene textures")
+    for i, x in enumerate(tan_textures):
+        if x is not None:
+            _expect(x, f"tangent texture {i}", scene.tex_shapes[i])
+            t.textures[i] = x.data_ptr()
+    if tan_roughness is not None:
+        _expect(tan_roughness, "tangent roughness")
+        if tan_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"tangent roughness needs {scene.n_roughness} entries")
+        t.roughness = tan_roughness.data_ptr()
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    _check(lib.drt_render_jvp(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                              ctypes.byref(t), out.data_ptr(), _stream(stream)), "drt_render_jvp")
+    return out
 
 
 def trace(scene: Scene, rays, mode: int = 0, stream=None):

@@ -742,6 +742,24 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
   return ok();
 }
 
+drt_status drt_render_jvp(const drt_scene* scene, const drt_params* params, const drt_camera* cams,
+                          int32_t n_cams, const drt_render_opts* opts, const drt_grads* direction,
+                          float* image_tangent, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!direction || !image_tangent) return fail(DRT_EINVAL, "direction and image_tangent are required");
+  DGrads dt;
+  std::memset(&dt, 0, sizeof(dt));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dt.tex[t] = direction->textures[t];
+  dt.rough = scene->dev.n_rough > 0 ? direction->roughness : nullptr;
+  hipError_t e = launch_render_jvp(scene->dev, dp, dc, dr, dt, image_tangent, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "render_jvp launch");
+  return ok();
+}
+
 drt_status drt_trace(const drt_scene* scene, const float* rays, int64_t n, int32_t mode,
                      drt_hit* hits, void* hip_stream) {
   if (!scene) return fail(DRT_EINVAL, "scene is required");

@@ -675,6 +675,10 @@ DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, ui
 // estimate with the cache's answer already added); the replay stops at the
 // record vertex, so the detached cache term reaches earlier vertices through
 // Lrem and nothing is scattered for the network.
+// MODE_JVP: forward-mode derivative along a parameter direction (tangent
+// textures in tab.gtex, tangent roughness in sink.rough_global): the tangents
+// of beta and L ride along the path; `out` receives the sum of the sample
+// radiance tangents.  Attached and detached terms as in the replay.
 // Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
 // ---------------------------------------------------------------------------
 enum {
@@ -683,7 +687,8 @@ enum {
   MODE_CACHED = 2,
   MODE_TRAIN = 3,
   MODE_CACHED_SAMPLES = 4,
-  MODE_ADJOINT_CACHED = 5
+  MODE_ADJOINT_CACHED = 5,
+  MODE_JVP = 6
 };
 
 template <int MODE>
@@ -692,6 +697,10 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                       f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
                       f3& out) {
   constexpr bool ADJ = MODE == MODE_ADJOINT || MODE == MODE_ADJOINT_CACHED;
+  constexpr bool JVP = MODE == MODE_JVP;
+  // modes with a record vertex (cache queries, training records, cached replay)
+  constexpr bool HOOK = MODE == MODE_CACHED || MODE == MODE_TRAIN || MODE == MODE_CACHED_SAMPLES ||
+                        MODE == MODE_ADJOINT_CACHED;
   constexpr bool QUERY = MODE == MODE_CACHED || MODE == MODE_CACHED_SAMPLES;
   const int W = C.width, H = C.height;
   const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
@@ -703,6 +712,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   int sidx = 0;
   uint32_t glo = 0, ghi = 0;
   f3 beta, L, Lrem = mk(0, 0, 0), o, d, prev_p;
+  f3 tbeta = mk(0, 0, 0), tL = mk(0, 0, 0);  // tangents (MODE_JVP)
   float prev_pdf;
   int k;
   // record vertex (MODE_TRAIN)
@@ -716,6 +726,8 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     camera_ray(C.cam[cam], W, H, x, y, glo, ghi, R, o, d);
     beta = mk(1, 1, 1);
     L = mk(0, 0, 0);
+    tbeta = mk(0, 0, 0);
+    tL = mk(0, 0, 0);
     prev_pdf = 0.f;  // 0: the next emitter hit takes no MIS weight
     prev_p = o;
     k = 1;
@@ -728,8 +740,9 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   // other passes compile without them.
   auto step = [&](auto replay) -> bool {
     constexpr bool RB = ADJ && decltype(replay)::value;
+    constexpr bool DER = RB || JVP;  // BSDF parameter derivatives needed
     bool done = false, nee = false;
-    f3 nee_c = mk(0, 0, 0), nee_gt = mk(0, 0, 0), so = o, sd = d;
+    f3 nee_c = mk(0, 0, 0), nee_gt = mk(0, 0, 0), nee_t = mk(0, 0, 0), so = o, sd = d;
     float nee_gr = 0.f, stmax = 0.f;
     bool bsdf_pend = false;
     f3 rat_alb = mk(0, 0, 0), rat_alpha = mk(0, 0, 0);
@@ -750,6 +763,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
           f3 c = beta * env_lookup(s, row, col) * w;
           L = L + c;
           if (RB) Lrem = Lrem - c;
+          if (JVP) tL = tL + tbeta * env_lookup(s, row, col) * w;
         }
         done = true;
       } else {
@@ -772,6 +786,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
           f3 c = beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
           L = L + c;
           if (RB) Lrem = Lrem - c;
+          if (JVP) tL = tL + tbeta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
         }
         if (k == R.max_depth) {
           done = true;
@@ -811,8 +826,18 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
             }
             vrslot = M.rough_slot;
             if (vrslot >= 0) sh.alpha = P.rough[vrslot];
+            // the direction's components at this vertex (MODE_JVP)
+            f3 vt = mk(0, 0, 0);
+            float vr = 0.f;
+            if (JVP) {
+              if (vtex >= 0 && tab.gtex[vtex]) {
+                const float* tp = tab.gtex[vtex] + 3 * (size_t)vtexel;
+                vt = mk(tp[0], tp[1], tp[2]);
+              }
+              if (vrslot >= 0 && sink.rough_global) vr = sink.rough_global[vrslot];
+            }
             bool stop_here = false;
-            if (MODE >= MODE_CACHED && !recorded && k >= io.K) {
+            if (HOOK && !recorded && k >= io.K) {
               // features of the record vertex: position, direction back along
               // the ray, normal facing it, roughness (1 unless microfacet),
               // albedo (f0 for a conductor, 1 for a dielectric)
@@ -890,11 +915,14 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                 valid = true;
               }
               if (valid) {
-                BEval fe = bsdf_eval<RB>(sh, wi, to_local(fr, wl));
+                BEval fe = bsdf_eval<DER>(sh, wi, to_local(fr, wl));
                 if (nonzero(fe.f)) {
                   float w = delta ? 1.0f : power_heuristic(p_sel * pdf_l, fe.pdf);
                   f3 coef = beta * Le * (w / (p_sel * pdf_l));
                   nee_c = coef * fe.f;
+                  if (JVP)
+                    nee_t = tbeta * Le * (w / (p_sel * pdf_l)) * fe.f +
+                            coef * (fe.dalb * vt + fe.dalpha * vr);
                   if (RB) {
                     nee_gt = dL * coef * fe.dalb;
                     f3 g = dL * coef * fe.dalpha;
@@ -919,7 +947,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
             f3 wo;
             BEval be;
             const bool ok = !stop_here &&
-                            bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
+                            bsdf_sample<DER>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
             if (RB) {
               bsdf_pend = ok;
               if (bsdf_pend) {
@@ -932,6 +960,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
               }
             }
             if (ok) {
+              if (JVP) tbeta = (tbeta * be.f + beta * (be.dalb * vt + be.dalpha * vr)) * (1.0f / be.pdf);
               beta = beta * be.f * (1.0f / be.pdf);
               prev_pdf = be.pdf;
               prev_p = p;
@@ -940,8 +969,12 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
               d = wow;
               if (k >= R.rr_depth) {
                 float q = fminf(maxc(beta), 0.95f);
-                if (u01(r1.z) >= q) done = true;
-                else beta = beta * (1.0f / q);
+                if (u01(r1.z) >= q) {
+                  done = true;
+                } else {
+                  beta = beta * (1.0f / q);
+                  if (JVP) tbeta = tbeta * (1.0f / q);
+                }
               }
             } else {
               done = true;
@@ -960,6 +993,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       cnt.shadow++;
       if (!traverse(s, rp, 0.f, stmax, true, h, stk, cnt)) {
         L = L + nee_c;
+        if (JVP) tL = tL + nee_t;
         if (RB) {
           Lrem = Lrem - nee_c;
           gtex = nee_gt;
@@ -1012,6 +1046,8 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       while (!step(std::true_type{})) {
       }
       cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z))));
+    } else if (JVP) {
+      acc = acc + tL;
     } else if (MODE == MODE_CACHED_SAMPLES) {
       float* ls = io.lsamp + 3 * (g_base + (uint64_t)sidx);
       ls[0] = L.x;
@@ -1122,6 +1158,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
   }
   if constexpr (STATS) flush_counters(R, cnt);
+}
+
+// Forward-mode derivative of the image along the direction T (tangent
+// textures and roughness): out = (1/spp) sum of the sample radiance tangents.
+__global__ __launch_bounds__(kBlock) void k_render_jvp(DScene s, DParams P, DCams C, DRender R,
+                                                       DGrads T, float* __restrict__ image) {
+  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ LdsTables tab;
+  load_tables(tab, s, P, &T);
+  __syncthreads();
+  const int W = C.width, H = C.height;
+  const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
+  const int y = blockIdx.y * kTile + (threadIdx.x / kTile);
+  const int cam = blockIdx.z;
+  Counters cnt = {};
+  if (x < W && y < H) {
+    Sink dir{&tab, nullptr, T.rough};
+    DNrcIO none = {};
+    f3 acc;
+    const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
+    render_pixel<MODE_JVP>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
+                           stack + threadIdx.x, cnt, dir, none, acc);
+    const float inv = 1.0f / (float)R.spp;
+    float* out = image + 3 * pix;
+    out[0] = acc.x * inv;
+    out[1] = acc.y * inv;
+    out[2] = acc.z * inv;
+  }
 }
 
 // Training paths of the radiance cache: path j (counter g = j) starts at the
@@ -1310,6 +1374,13 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
   else
     hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED>), grid, dim3(kBlock), 0, st,
                        s, p, c, r, adj, g, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_jvp(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
+                             const DGrads& t, float* image, hipStream_t st) {
+  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  hipLaunchKernelGGL(k_render_jvp, grid, dim3(kBlock), 0, st, s, p, c, r, t, image);
   return hipGetLastError();
 }
 
