@@ -72,3 +72,13 @@ def test_jvp_adjoint_dot_product_identity(case):
         rhs += float((gr.cpu().numpy().astype(np.float64) * vr).sum())
     print(case, "<dI, Jv>", lhs, "<J^T dI, v>", rhs, flush=True)
     assert abs(lhs - rhs) <= 1e-4 * max(abs(lhs), abs(rhs))
+
+
+def test_jvp_zero_direction_is_zero():
+    drt = _drt()
+    make, kw = ADJ_CASES["cornell_conductor"]
+    sc = make()
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    jv = drt.render_jvp(gs, tex, rough, sc.cameras, 2, 3, seed=3).cpu().numpy()
+    assert np.all(jv == 0)

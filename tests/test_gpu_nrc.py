@@ -341,3 +341,30 @@ def test_trained_cache_beats_untrained():
           flush=True)
     assert np.mean(losses[-10:]) < 0.9 * np.mean(losses[:10])
     assert after < 0.5 * before
+
+
+def test_degenerate_cache_inputs():
+    """No record vertex within reach (K beyond the maximum depth): the cached
+    render is the plain render, sample for sample, and collection yields no
+    records; training on no valid records gives zero loss and gradients; a
+    zero image adjoint gives zero cached gradients."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=32, height=32)
+    cfg = dict(scenes.nrc_config(sc), trunc_vertex=7)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    Wt, gt = torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda()
+    img = drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wt, gt, spp=4, seed=5)
+    ref = drt.render_forward(gs, tex, None, sc.cameras, 4, 6, 3, seed=5)
+    np.testing.assert_array_equal(img.cpu().numpy(), ref.cpu().numpy())
+    rec, valid, count = drt.nrc_collect(gs, tex, None, sc.cameras, cfg, 1000, seed=3)
+    assert int(count.item()) == 0 and int(valid.sum().item()) == 0
+    dW = torch.zeros(17600, device="cuda")
+    dG = torch.zeros(grid.size, device="cuda")
+    loss = drt.nrc_train(cfg, Wt, gt, rec, valid, count, dW, dG)
+    assert loss.item() == 0.0 and dW.abs().sum().item() == 0 and dG.abs().sum().item() == 0
+    cfg3 = scenes.nrc_config(sc)
+    adj = torch.zeros((1, 32, 32, 3), device="cuda")
+    g, _ = drt.render_adjoint_cached(gs, tex, None, sc.cameras, cfg3, Wt, gt, adj, 4, 6, 3, 2)
+    assert g[0].abs().sum().item() == 0

@@ -206,3 +206,48 @@ def test_scene_info_and_env_tables():
     ext = (sc.positions.max(0) - sc.positions.min(0)).max()
     assert abs(info["eps"] - 1e-4 * ext) < 1e-9
     assert info["device_bytes"] <= drt.scene_plan(sc)
+
+
+def test_cache_and_jvp_arguments_rejected_before_launch():
+    """Argument checks of the radiance-cache and forward-mode entry points
+    fail before anything is enqueued (the pointers below are never read)."""
+    sc = scenes.cornell()
+    cfg = scenes.nrc_config(sc)
+    c = drt.nrc_config(cfg)
+    fake = 1 << 20                       # non-null, never dereferenced
+    n = 1000
+    need = int(drt.lib.drt_nrc_train_workspace_bytes(n))
+    assert need >= n * 1216
+    assert drt.lib.drt_nrc_train_workspace_bytes(-1) == 0
+    args = lambda ws, wsb: (ctypes.byref(c), fake, fake, fake, fake, fake, n, ws, wsb,  # noqa: E731
+                            fake, fake, fake, None)
+    assert drt.lib.drt_nrc_train(*args(fake, need - 1)) == -1          # workspace too small
+    assert b"workspace" in drt.lib.drt_last_error()
+    assert drt.lib.drt_nrc_train(*args(fake + 4, need)) == -1          # not 16-byte aligned
+    assert drt.lib.drt_nrc_train(*args(None, need)) == -1
+    bad = drt.nrc_config(dict(cfg, levels=8))
+    assert drt.lib.drt_nrc_train(ctypes.byref(bad), fake, fake, fake, fake, fake, n, fake, need,
+                                 fake, fake, fake, None) == -5         # unsupported
+    bad = drt.nrc_config(dict(cfg, log2_table=30))
+    assert drt.lib.drt_nrc_train(ctypes.byref(bad), fake, fake, fake, fake, fake, n, fake, need,
+                                 fake, fake, fake, None) != 0
+    assert drt.lib.drt_nrc_query_ints(10) == 3 * 10 + 4096
+    assert drt.lib.drt_nrc_query_ints(-3) == 0
+    # scenes packed on the host are rejected by every rendering entry point
+    desc = drt.make_desc(sc)
+    size = drt.scene_plan(sc)
+    h = ctypes.c_void_p()
+    raw = (ctypes.c_ubyte * size)()
+    assert drt.lib.drt_scene_pack(ctypes.byref(desc), ctypes.addressof(raw), size, ctypes.byref(h)) == 0
+    p = drt.drt_params()
+    cams = drt._cams(sc.cameras)
+    o = drt._opts(1, 3, 1 << 30, 1, 0, None)
+    g = drt.drt_grads()
+    assert drt.lib.drt_render_jvp(h, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(g),
+                                  fake, None) == -4
+    assert drt.lib.drt_render_jvp(None, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(g),
+                                  fake, None) == -1
+    assert drt.lib.drt_render_adjoint_cached(h, ctypes.byref(p), cams, 1, ctypes.byref(o),
+                                             ctypes.byref(c), fake, fake, fake, fake, fake, 10, fake,
+                                             fake, ctypes.byref(g), None) == -4
+    drt.lib.drt_scene_destroy(h)
