@@ -141,7 +141,8 @@ def main():
     if not args.no_cache:
         cache = {"equal_rmse": cache_equal_rmse(drt, scenes, torch, R=args.res),
                  "gradient_step": cache_gradient_step(drt, scenes, torch, R=args.res, SPP=args.spp,
-                                                      tex_size=args.tex)}
+                                                      tex_size=args.tex),
+                 "gradient_bias": cache_gradient_bias(drt, scenes, torch, tex_size=args.tex)}
 
     cpu = None
     if not args.no_cpu:
@@ -355,6 +356,77 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
                                                "msamples_s": round(n / ms / 1e3, 2)}
     return {"workload": f"cornell-box + GGX conductor, {tex_size}^2x3 texture, {R}^2 {SPP}spp D{D} "
                         f"RR{RR}, cache at v3 (one 65,536-path training frame per step)", **out}
+
+
+def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=256, tex_size=4096,
+                        train_frames=100):
+    """Gradient error at matched wall time, cache vs plain (16 views at
+    512^2 in one launch, depth 6, RR from 3, 4096^2x3 texture + roughness):
+    the image adjoint is 2 (I - T) / N of a 32-spp primal against a 256-spp
+    target; the reference gradient is the plain replayed adjoint at ref_spp;
+    the cached gradient (32 spp, cache trained for train_frames frames) is
+    timed, and the plain gradient is taken at the spp that costs the same
+    time.  Errors are ||g - g_ref|| / ||g_ref|| per texel and on the means of
+    64x64-texel blocks (where sampling noise averages out and bias remains)."""
+    D, RR = 6, 3
+    sc = scenes.cornell(tex_size=tex_size, width=R, height=R, conductor=True)
+    cams = scenes.ring_cameras(n_cams, R, R)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    dev = "cuda"
+    tex = torch.full((tex_size, tex_size, 3), 0.5, dtype=torch.float32, device=dev)
+    rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
+    tex_t = torch.from_numpy(scenes.random_texture(tex_size)).to(dev)
+    target = drt.render_forward(gs, [tex_t], torch.tensor([0.2], device=dev), cams, 256, D, RR, seed=1284)
+    del tex_t
+    img = drt.render_forward(gs, [tex], rough, cams, spp, D, RR, seed=11)
+    adj = torch.empty_like(img)
+    drt.loss_l2(img, target, adj=adj)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def grad(fn):
+        gt, gr = torch.zeros_like(tex), torch.zeros_like(rough)
+        fn(gt, gr)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        gt.zero_()
+        gr.zero_()
+        a.record()
+        fn(gt, gr)
+        b.record()
+        torch.cuda.synchronize()
+        return gt, gr, a.elapsed_time(b)
+
+    g_ref, _, _ = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, ref_spp, D, RR,
+                                                           seed=101, grad_textures=[gt], grad_roughness=gr))
+    cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
+    for f in range(train_frames):
+        cache.train_frame(gs, [tex], rough, cams, seed=3000 + f)
+    work = drt.cached_work(n_cams * R * R * spp, dev, sample_radiance=True)
+    g_c, _, t_c = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
+                                                    grad_textures=[gt], grad_roughness=gr, work=work))
+    _, _, t_p32 = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, spp, D, RR, seed=105,
+                                                         grad_textures=[gt], grad_roughness=gr))
+    spp_p = max(1, int(round(spp * t_c / t_p32)))
+    g_p, _, t_p = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, spp_p, D, RR,
+                                                         seed=107, grad_textures=[gt], grad_roughness=gr))
+
+    def err(g):
+        d = (g - g_ref).double()
+        full = float(d.norm() / g_ref.double().norm())
+        b = tex_size // 64
+        blk = lambda x: x.double().reshape(b, 64, b, 64, 3).mean((1, 3))  # noqa: E731
+        block = float((blk(g) - blk(g_ref)).norm() / blk(g_ref).norm())
+        return round(full, 4), round(block, 4)
+
+    ec, ep = err(g_c), err(g_p)
+    return {"workload": f"{n_cams} views x {R}^2, depth {D} RR{RR}, {tex_size}^2x3 texture, "
+                        f"reference: plain adjoint at {ref_spp} spp",
+            "cache": {"spp": spp, "ms": round(t_c, 2), "rel_err_texel": ec[0], "rel_err_64x64_blocks": ec[1]},
+            "plain_matched_time": {"spp": spp_p, "ms": round(t_p, 2), "rel_err_texel": ep[0],
+                                   "rel_err_64x64_blocks": ep[1]},
+            "train_frames": train_frames}
 
 
 def cpu_baseline(sc, R, SPP, D, budget_s):
