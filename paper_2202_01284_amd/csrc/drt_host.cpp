@@ -241,8 +241,9 @@ struct Builder {
 };
 
 void set_child_box(DNode& n, int slot, const Box& b) {
-  n.lox[slot] = b.lo[0]; n.loy[slot] = b.lo[1]; n.loz[slot] = b.lo[2];
-  n.hix[slot] = b.hi[0]; n.hiy[slot] = b.hi[1]; n.hiz[slot] = b.hi[2];
+  float* f = n.box[slot];
+  f[0] = b.lo[0]; f[1] = b.lo[1]; f[2] = b.lo[2];
+  f[3] = b.hi[0]; f[4] = b.hi[1]; f[5] = b.hi[2];
 }
 
 }  // namespace

@@ -23,11 +23,12 @@ constexpr int kBlock = 256;            // threads per workgroup of the megakerne
 constexpr int kTile = 16;              // workgroup = 16 x 16 pixel tile
 constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
 
-// Four-child BVH node, 128 bytes (one L2 line): the children's boxes as
-// structure of arrays and, per child, an interior node index (count 0), a
-// leaf's triangle range (count > 0) or nothing (count -1).
+// Four-child BVH node, 128 bytes (one L2 line): per child its box (lo xyz,
+// hi xyz; two children per three float4, so the boxes are loaded and tested
+// in pairs) and an interior node index (count 0), a leaf's triangle range
+// (count > 0) or nothing (count -1).
 struct alignas(16) DNode {
-  float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+  float box[4][6];
   int32_t child[4];
   int32_t count[4];
 };

@@ -222,14 +222,20 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
   int node = 0, sp = 0;
   for (;;) {
     const float4* np = reinterpret_cast<const float4*>(s.nodes + node);
-    const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
     const int4 ch = reinterpret_cast<const int4*>(np)[6], cn = reinterpret_cast<const int4*>(np)[7];
     cnt.nodes++;
     float t0, t1, t2, t3;
-    const bool h0 = cn.x >= 0 && slab(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmin, tbest, t0);
-    const bool h1 = cn.y >= 0 && slab(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmin, tbest, t1);
-    const bool h2 = cn.z >= 0 && slab(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmin, tbest, t2);
-    const bool h3 = cn.w >= 0 && slab(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmin, tbest, t3);
+    bool h0, h1, h2, h3;
+    {  // children 0 and 1: three float4 (fewer live registers than all four boxes)
+      const float4 a = np[0], b = np[1], c = np[2];
+      h0 = cn.x >= 0 && slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0);
+      h1 = cn.y >= 0 && slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1);
+    }
+    {  // children 2 and 3
+      const float4 a = np[3], b = np[4], c = np[5];
+      h2 = cn.z >= 0 && slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2);
+      h3 = cn.w >= 0 && slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3);
+    }
     // leaf children: test their triangles now (one loop over the ranges)
     const int e0 = (h0 && cn.x > 0) ? cn.x : 0;
     const int e1 = e0 + ((h1 && cn.y > 0) ? cn.y : 0);

@@ -74,15 +74,12 @@ def test_invalid_arguments_rejected_before_launch():
 # packed BVH walked in NumPy
 # ---------------------------------------------------------------------------
 
-NODE = np.dtype([("lox", "<f4", 4), ("hix", "<f4", 4), ("loy", "<f4", 4), ("hiy", "<f4", 4),
-                 ("loz", "<f4", 4), ("hiz", "<f4", 4), ("child", "<i4", 4), ("count", "<i4", 4)])
+NODE = np.dtype([("box", "<f4", (4, 6)), ("child", "<i4", 4), ("count", "<i4", 4)])
 TRI = np.dtype([("p", "<f4", 9), ("prim", "<i4"), ("flags", "<i4"), ("pad", "<i4")])
 
 
 def _box(nd, s):
-    lo = np.array([nd["lox"][s], nd["loy"][s], nd["loz"][s]])
-    hi = np.array([nd["hix"][s], nd["hiy"][s], nd["hiz"][s]])
-    return lo, hi
+    return nd["box"][s][:3].copy(), nd["box"][s][3:].copy()
 
 
 def _unpack(sc):
