@@ -15,12 +15,12 @@ namespace drt {
 // build keeps interior nodes at depth < kMaxInteriorDepth; the four-wide
 // nodes are the binary interior nodes at even depth (so at most 12 levels
 // of them), and a visit pushes at most 3 children, so the stack never holds
-// more than 3 x 12 = 36 <= kStackDepth entries.  38 entries x 256 lanes
-// keep four workgroups per CU within the 160 KB of LDS.
-constexpr int kStackDepth = 38;
+// more than 3 x 12 = 36 = kStackDepth entries.  36 entries x 64 lanes keep
+// sixteen one-wave workgroups per CU within the 160 KB of LDS.
+constexpr int kStackDepth = 36;
 constexpr int kMaxInteriorDepth = 24;
-constexpr int kBlock = 256;            // threads per workgroup of the megakernels
-constexpr int kTile = 16;              // workgroup = 16 x 16 pixel tile
+constexpr int kBlock = 64;             // threads per workgroup of the megakernels (one wave)
+constexpr int kTile = 8;               // workgroup = 8 x 8 pixel tile
 constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
 
 // Four-child BVH node, 128 bytes (one L2 line): per child its box (lo xyz,

@@ -10,7 +10,7 @@
 // surgery": f'/f applied to the replayed radiance; Sec. "Differentiating
 // polymorphism": implicit parameter reads become atomic scatter-reductions).
 //
-// Design for CDNA4: wave64, 16x16-pixel workgroups, BVH traversal stack in
+// Design for CDNA4: wave64, one-wave 8x8-pixel workgroups, BVH traversal stack in
 // LDS (one column per lane, no bank conflicts), the paper's polymorphic BSDF
 // call as a switch on the material id with the albedo/roughness fetch hoisted
 // out of it, roughness gradients pre-reduced in LDS per workgroup, texel
@@ -1091,7 +1091,7 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 }
 
 // ---------------------------------------------------------------------------
-// megakernels: one 16x16 pixel tile per workgroup
+// megakernels: one 8x8 pixel tile per workgroup (one wave)
 // ---------------------------------------------------------------------------
 // STATS = false compiles the counters out (they are never read).
 // MODE: MODE_PRIMAL, MODE_CACHED (paths stop at their record vertex and

@@ -515,15 +515,12 @@ __global__ __launch_bounds__(kBlockN) void k_query_hist(BinSrc src, uint32_t* __
 }
 
 __global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist) {
-  static_assert(kQueryBins == 4 * 1024, "one block of 1024 threads, 4 bins each");
+  constexpr int kPer = kQueryBins / 1024;   // bins per thread
+  static_assert(kPer * 1024 == kQueryBins, "one block of 1024 threads");
   __shared__ uint32_t part[1024];
   const int t = threadIdx.x;
-  uint32_t a[4], sum = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    a[k] = hist[4 * t + k];
-    sum += a[k];
-  }
+  uint32_t sum = 0;
+  for (int k = 0; k < kPer; ++k) sum += hist[kPer * t + k];
   part[t] = sum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -533,10 +530,10 @@ __global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist
     __syncthreads();
   }
   uint32_t run = part[t] - sum;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    hist[4 * t + k] = run;
-    run += a[k];
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t a = hist[kPer * t + k];
+    hist[kPer * t + k] = run;
+    run += a;
   }
 }
 
