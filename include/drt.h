@@ -307,11 +307,15 @@ drt_status drt_nrc_encode(const drt_nrc_config* cfg, const uint16_t* grid, const
 
 /* Network only (test hooks): y [n][3] = net(x); inputs rounded to BF16.
  * backward: dW [DRT_NRC_WEIGHTS] += d<dy, y>/dW; dx [n][80] = d<dy, y>/dx for
- * inputs 0..31 (the hash features), 0 for the others; dx may be NULL. */
+ * inputs 0..31 (the hash features), 0 for the others; dx may be NULL.  The
+ * backward runs the training kernels' backward and weight-gradient passes
+ * and needs their workspace (drt_nrc_train_workspace_bytes(n), 16-byte
+ * aligned). */
 drt_status drt_nrc_forward(const float* weights, const float* x, int64_t n, float* y,
                            void* hip_stream);
 drt_status drt_nrc_backward(const float* weights, const float* x, const float* dy, int64_t n,
-                            float* dW, float* dx, void* hip_stream);
+                            void* workspace, int64_t workspace_bytes, float* dW, float* dx,
+                            void* hip_stream);
 
 /* Hash-grid gradient only (test hook): dgrid [levels][2^log2_table][2] +=
  * the trilinear scatter of dx [n][80] (inputs 0..31) at the records'

@@ -126,7 +126,7 @@ _SIGS = {
     "drt_nrc_encode": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _c_i64, _vp, _vp]),
     "drt_nrc_forward": (_c_i32, [_vp, _vp, _c_i64, _vp, _vp]),
     "drt_nrc_grid_backward": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _c_i64, _vp, _vp]),
-    "drt_nrc_backward": (_c_i32, [_vp, _vp, _vp, _c_i64, _vp, _vp, _vp]),
+    "drt_nrc_backward": (_c_i32, [_vp, _vp, _vp, _c_i64, _vp, _c_i64, _vp, _vp, _vp]),
     "drt_nrc_collect": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                  ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_nrc_config),
                                  _c_i64, _vp, _vp, _vp, _vp]),
@@ -614,13 +614,16 @@ def nrc_forward(weights, x, stream=None):
     return y
 
 
-def nrc_backward(weights, x, dy, dW=None, stream=None):
+def nrc_backward(weights, x, dy, dW=None, workspace=None, stream=None):
     torch = _torch()
     n = x.shape[0]
     if dW is None:
         dW = torch.zeros(NRC_WEIGHTS, dtype=torch.float32, device=x.device)
+    if workspace is None:
+        workspace = nrc_train_workspace(n, x.device)
     dx = torch.empty((n, NRC_INPUTS), dtype=torch.float32, device=x.device)
-    _check(lib.drt_nrc_backward(weights.data_ptr(), x.data_ptr(), dy.data_ptr(), n, dW.data_ptr(),
+    _check(lib.drt_nrc_backward(weights.data_ptr(), x.data_ptr(), dy.data_ptr(), n,
+                                workspace.data_ptr(), workspace.numel(), dW.data_ptr(),
                                 dx.data_ptr(), _stream(stream)), "drt_nrc_backward")
     return dW, dx
 

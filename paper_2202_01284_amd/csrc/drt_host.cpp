@@ -847,11 +847,16 @@ drt_status drt_nrc_forward(const float* weights, const float* x, int64_t n, floa
 }
 
 drt_status drt_nrc_backward(const float* weights, const float* x, const float* dy, int64_t n,
-                            float* dW, float* dx, void* hip_stream) {
-  if (n < 0) return fail(DRT_EINVAL, "n < 0");
+                            void* workspace, int64_t workspace_bytes, float* dW, float* dx,
+                            void* hip_stream) {
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(DRT_EINVAL, "n out of range");
   if (n == 0) return ok();
-  if (!weights || !x || !dy || !dW) return fail(DRT_EINVAL, "null pointer argument");
-  hipError_t e = launch_nrc_backward(weights, x, dy, n, dW, dx, (hipStream_t)hip_stream);
+  if (!weights || !x || !dy || !dW || !workspace) return fail(DRT_EINVAL, "null pointer argument");
+  if (workspace_bytes < nrc_train_workspace_bytes(n))
+    return fail(DRT_EINVAL, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                (long long)nrc_train_workspace_bytes(n));
+  if (((uintptr_t)workspace & 15) != 0) return fail(DRT_EINVAL, "workspace is not 16-byte aligned");
+  hipError_t e = launch_nrc_backward(weights, x, dy, n, workspace, dW, dx, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "nrc_backward launch");
   return ok();
 }

@@ -188,7 +188,7 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n,
 hipError_t launch_zero(void* p, int64_t n_words, hipStream_t st);
 // Launchers (drt_nrc.hip).
 hipError_t launch_nrc_forward(const float* W, const float* x, int64_t n, float* y, hipStream_t st);
-hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n,
+hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n, void* ws,
                                float* dW, float* dx, hipStream_t st);
 hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
                              hipStream_t st);

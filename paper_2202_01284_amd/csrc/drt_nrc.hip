@@ -36,10 +36,6 @@ constexpr int kW0 = 0, kW1 = 64 * 80, kW2 = kW1 + 4096, kW3 = kW2 + 4096, kW4 = 
 constexpr int kW4Pad = 16 * 64;             // output layer padded to 16 rows in LDS
 constexpr int kLdsW = kW4 + kW4Pad;         // bf16 weights staged in LDS
 constexpr int kBlockN = 256;                // 4 waves per workgroup
-// dW accumulators in LDS: rows padded by 4 floats so that the 4 lane groups
-// (rows 4 apart) of an accumulation fall in different banks
-constexpr int kP0 = 0, kP1 = 64 * 84, kP2 = kP1 + 64 * 68, kP3 = kP2 + 64 * 68, kP4 = kP3 + 64 * 68;
-constexpr int kLdsDW = kP4 + 3 * 68;
 
 DEV uint16_t f2bf(float f) {
   uint32_t b = __float_as_uint(f);
@@ -257,115 +253,11 @@ DEV f32x4 forward_tile(const uint16_t* wl, Acts& A, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// backward for one tile: dW accumulated into LDS (FP32), dX of inputs 0..31
+// backward helpers
 // ---------------------------------------------------------------------------
 DEV bf16x4 mask_pack(f32x4 g, bf16x4 h) {
   return pack4(h[0] != 0 ? g[0] : 0.f, h[1] != 0 ? g[1] : 0.f, h[2] != 0 ? g[2] : 0.f,
                h[3] != 0 ? g[3] : 0.f);
-}
-
-// stage a [features][16 samples] block from B-layout chunks (lane holds
-// features 16c + 4g + j of sample lane%16)
-DEV void stage(uint16_t* st, const bf16x4* chunks, int n_chunks, int lane) {
-  const int g = lane >> 4, smp = lane & 15;
-  // the previous reads of this wave's staging block are complete (LDS is in
-  // order per wave); keep the compiler from moving the accesses across
-  __builtin_amdgcn_wave_barrier();
-  for (int c = 0; c < n_chunks; ++c)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) st[(16 * c + 4 * g + j) * 16 + smp] = (uint16_t)chunks[c][j];
-  __builtin_amdgcn_wave_barrier();
-}
-// operand of a staged block: rows 16u.. (lane%16), k = samples 4g..4g+3
-DEV bf16x4 ld_staged(const uint16_t* st, int u, int lane) {
-  return *reinterpret_cast<const bf16x4*>(st + (16 * u + (lane & 15)) * 16 + 4 * (lane >> 4));
-}
-
-// dW[out][in] += sum over the tile's samples of dH[s][out] H[s][in]
-DEV void accumulate_dw(float* dwl, int K, int out_tiles, int out_rows, const uint16_t* st_dh,
-                       const uint16_t* st_h, int lane) {
-  const int g = lane >> 4;
-  for (int t = 0; t < out_tiles; ++t) {
-    bf16x4 a = ld_staged(st_dh, t, lane);
-    for (int u = 0; u < K / 16; ++u) {
-      f32x4 d = mfma(a, ld_staged(st_h, u, lane), zero4());
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int r = 16 * t + 4 * g + j;
-        if (r < out_rows && d[j] != 0.f) atomicAdd(dwl + r * (K + 4) + 16 * u + (lane & 15), d[j]);
-      }
-    }
-  }
-}
-
-// dW[i] += the block's accumulators (row-major index i, padded LDS rows)
-DEV void flush_dw(const float* dwl, float* __restrict__ dW) {
-  for (int i = threadIdx.x; i < kW4 + 3 * 64; i += blockDim.x) {
-    int pi;
-    if (i < kW1) pi = kP0 + (i / 80) * 84 + i % 80;
-    else if (i < kW2) pi = kP1 + ((i - kW1) >> 6) * 68 + ((i - kW1) & 63);
-    else if (i < kW3) pi = kP2 + ((i - kW2) >> 6) * 68 + ((i - kW2) & 63);
-    else if (i < kW4) pi = kP3 + ((i - kW3) >> 6) * 68 + ((i - kW3) & 63);
-    else pi = kP4 + ((i - kW4) >> 6) * 68 + ((i - kW4) & 63);
-    const float v = dwl[pi];
-    if (v != 0.f) atomicAdd(dW + i, v);
-  }
-}
-
-// dY: lane group 0 holds the output gradients (rows 0..2) of its sample.
-// Returns dX chunks 0, 1 (inputs 0..31) in D layout.
-DEV void backward_tile(const uint16_t* wl, float* dwl, uint16_t* st, const Acts& A, f32x4 dy,
-                       f32x4 dx[2], int lane) {
-  const int g = lane >> 4;
-  bf16x4 dyb = g == 0 ? pack4(dy[0], dy[1], dy[2], 0.f) : zero_b();
-  uint16_t* st_dh = st;             // [64][16]
-  uint16_t* st_h = st + 64 * 16;    // [80][16]
-  // output layer
-  stage(st_dh, &dyb, 1, lane);
-  stage(st_h, A.h4, 4, lane);
-  accumulate_dw(dwl + kP4, 64, 1, 3, st_dh, st_h, lane);
-  bf16x4 g4[4], g3[4], g2[4], g1[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
-  // hidden layers 3, 2, 1
-  stage(st_dh, g4, 4, lane);
-  stage(st_h, A.h3, 4, lane);
-  accumulate_dw(dwl + kP3, 64, 4, 64, st_dh, st_h, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f32x4 acc = zero4();
-    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW3, 64, t, s, lane), g4[s], acc);
-    g3[t] = mask_pack(acc, A.h3[t]);
-  }
-  stage(st_dh, g3, 4, lane);
-  stage(st_h, A.h2, 4, lane);
-  accumulate_dw(dwl + kP2, 64, 4, 64, st_dh, st_h, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f32x4 acc = zero4();
-    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW2, 64, t, s, lane), g3[s], acc);
-    g2[t] = mask_pack(acc, A.h2[t]);
-  }
-  stage(st_dh, g2, 4, lane);
-  stage(st_h, A.h1, 4, lane);
-  accumulate_dw(dwl + kP1, 64, 4, 64, st_dh, st_h, lane);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f32x4 acc = zero4();
-    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
-    g1[t] = mask_pack(acc, A.h1[t]);
-  }
-  // input layer
-  stage(st_dh, g1, 4, lane);
-  stage(st_h, A.h0, 5, lane);
-  accumulate_dw(dwl + kP0, 80, 4, 64, st_dh, st_h, lane);
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    f32x4 acc = zero4();
-    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
-    dx[t] = acc;
-  }
-  (void)g;
 }
 
 // ---------------------------------------------------------------------------
@@ -407,45 +299,6 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_forward(const float* __restrict
       y[3 * sample + 2] = out[2];
     }
   }
-}
-
-// Network only: dW += d<dy, y>/dW, dx = d<dy, y>/dx (inputs 0..31; others 0).
-__global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restrict__ W,
-                                                         const float* __restrict__ x,
-                                                         const float* __restrict__ dy, int64_t n,
-                                                         float* __restrict__ dW,
-                                                         float* __restrict__ dx) {
-  __shared__ uint16_t wl[kLdsW];
-  __shared__ float dwl[kLdsDW];
-  __shared__ uint16_t st[kBlockN / 64][(64 + 80) * 16];
-  stage_weights(wl, W);
-  for (int i = threadIdx.x; i < kLdsDW; i += blockDim.x) dwl[i] = 0.f;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t n_tiles = (n + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
-  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
-  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
-    int64_t sample = tile * 16 + (lane & 15);
-    Acts A;
-    load_inputs(x, n, sample, lane, A.h0);
-    forward_tile(wl, A, lane);
-    f32x4 d = zero4();
-    if (g == 0 && sample < n) {
-      d[0] = dy[3 * sample];
-      d[1] = dy[3 * sample + 1];
-      d[2] = dy[3 * sample + 2];
-    }
-    f32x4 dxv[2];
-    backward_tile(wl, dwl, st[threadIdx.x >> 6], A, d, dxv, lane);
-    if (dx && sample < n) {
-      for (int t = 0; t < 5; ++t)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dx[sample * 80 + 16 * t + 4 * g + j] = t < 2 ? dxv[t][j] : 0.f;
-    }
-  }
-  __syncthreads();
-  flush_dw(dwl, dW);
 }
 
 // Encoding only: records [n][16] -> x [n][80] (FP32, before BF16 rounding).
@@ -644,6 +497,56 @@ DEV void put_chunk(bf16x4* ws, uint16_t* tb, int64_t tile, int c, bf16x4 v, int 
   ws[((size_t)tile * kChunks + c) * 64 + lane] = *reinterpret_cast<const bf16x4*>(tb + r * 16 + 4 * g);
 }
 
+// Backward propagation of one tile without the weight gradient: the masked
+// deltas of every layer (from the output gradient dyb, B layout), dx of
+// inputs 0..31, and the weight-gradient operands written to the workspace
+// (chunk map above).
+DEV void backprop_tile(const uint16_t* wl, uint16_t* tb, bf16x4* ws, int64_t tile, const Acts& A,
+                       bf16x4 dyb, f32x4 dx[2], int lane) {
+  bf16x4 g4[4], g3[4], g2[4], g1[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW3, 64, t, s, lane), g4[s], acc);
+    g3[t] = mask_pack(acc, A.h3[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW2, 64, t, s, lane), g3[s], acc);
+    g2[t] = mask_pack(acc, A.h2[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
+    g1[t] = mask_pack(acc, A.h1[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x4 acc = zero4();
+    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
+    dx[t] = acc;
+  }
+  // operands of the weight gradient
+#pragma unroll
+  for (int c = 0; c < 5; ++c) put_chunk(ws, tb, tile, c, A.h0[c], lane);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    put_chunk(ws, tb, tile, 5 + c, A.h1[c], lane);
+    put_chunk(ws, tb, tile, 9 + c, A.h2[c], lane);
+    put_chunk(ws, tb, tile, 13 + c, A.h3[c], lane);
+    put_chunk(ws, tb, tile, 17 + c, A.h4[c], lane);
+    put_chunk(ws, tb, tile, 21 + c, g1[c], lane);
+    put_chunk(ws, tb, tile, 25 + c, g2[c], lane);
+    put_chunk(ws, tb, tile, 29 + c, g3[c], lane);
+    put_chunk(ws, tb, tile, 33 + c, g4[c], lane);
+  }
+  put_chunk(ws, tb, tile, 37, dyb, lane);
+}
+
 // Records are taken in the spatially sorted order of the valid ones
 // (order[0 .. *count)), so a tile's records are close together.
 __global__ __launch_bounds__(kBlockN) void k_nrc_train_fb(DNrcNet net, const float* __restrict__ W,
@@ -690,49 +593,8 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train_fb(DNrcNet net, const flo
       }
     }
     const bf16x4 dyb = g == 0 ? pack4(d[0], d[1], d[2], 0.f) : zero_b();
-    bf16x4 g4[4], g3[4], g2[4], g1[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = zero4();
-      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW3, 64, t, s, lane), g4[s], acc);
-      g3[t] = mask_pack(acc, A.h3[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = zero4();
-      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW2, 64, t, s, lane), g3[s], acc);
-      g2[t] = mask_pack(acc, A.h2[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f32x4 acc = zero4();
-      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
-      g1[t] = mask_pack(acc, A.h1[t]);
-    }
     f32x4 dx[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      f32x4 acc = zero4();
-      for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
-      dx[t] = acc;
-    }
-    // operands of the weight gradient
-#pragma unroll
-    for (int c = 0; c < 5; ++c) put_chunk(ws, tb, tile, c, A.h0[c], lane);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      put_chunk(ws, tb, tile, 5 + c, A.h1[c], lane);
-      put_chunk(ws, tb, tile, 9 + c, A.h2[c], lane);
-      put_chunk(ws, tb, tile, 13 + c, A.h3[c], lane);
-      put_chunk(ws, tb, tile, 17 + c, A.h4[c], lane);
-      put_chunk(ws, tb, tile, 21 + c, g1[c], lane);
-      put_chunk(ws, tb, tile, 25 + c, g2[c], lane);
-      put_chunk(ws, tb, tile, 29 + c, g3[c], lane);
-      put_chunk(ws, tb, tile, 33 + c, g4[c], lane);
-    }
-    put_chunk(ws, tb, tile, 37, dyb, lane);
+    backprop_tile(wl, tb, ws, tile, A, dyb, dx, lane);
     if (ok) {
       // this lane holds d/d inputs {4g+j} and {16+4g+j}: levels 2g, 2g+1, 8+2g, 9+2g
       float xn[3];
@@ -759,6 +621,40 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_train_fb(DNrcNet net, const flo
   if (my_loss != 0.f) atomicAdd(&loss_acc, my_loss * inv);
   __syncthreads();
   if (threadIdx.x == 0 && loss_acc != 0.f) atomicAdd(loss, loss_acc);
+}
+
+// Network only (test hook), phase 1 on explicit inputs x [n][80] and output
+// gradients dy [n][3]: dx [n][80] (inputs 0..31; others 0) and the weight-
+// gradient operands; phase 2 then adds dW as in training.
+__global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restrict__ W,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ dy, int64_t n,
+                                                         bf16x4* __restrict__ ws,
+                                                         float* __restrict__ dx) {
+  __shared__ uint16_t wl[kLdsW];
+  __shared__ uint16_t tbuf[kBlockN / 64][256];
+  stage_weights(wl, W);
+  __syncthreads();
+  uint16_t* tb = tbuf[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlockN / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlockN / 64);
+  for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+    int64_t sample = tile * 16 + (lane & 15);
+    Acts A;
+    load_inputs(x, n, sample, lane, A.h0);
+    forward_tile(wl, A, lane);
+    const bool ok = g == 0 && sample < n;
+    const bf16x4 dyb = ok ? pack4(dy[3 * sample], dy[3 * sample + 1], dy[3 * sample + 2], 0.f) : zero_b();
+    f32x4 dxv[2];
+    backprop_tile(wl, tb, ws, tile, A, dyb, dxv, lane);
+    if (dx && sample < n) {
+      for (int t = 0; t < 5; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dx[sample * 80 + 16 * t + 4 * g + j] = t < 2 ? dxv[t][j] : 0.f;
+    }
+  }
 }
 
 // Phase 2: workgroup b takes record tiles [b T, (b+1) T) and writes its
@@ -818,7 +714,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_dw(const bf16x4* __restrict__ w
                                                    const int* __restrict__ count, int64_t n,
                                                    float* __restrict__ part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t n_tiles = (min((int64_t)*count, n) + 15) / 16;   // tiles phase 1 wrote
+  const int64_t n_tiles = ((count ? min((int64_t)*count, n) : n) + 15) / 16;  // tiles phase 1 wrote
   const int64_t t0 = (int64_t)blockIdx.x * kDwBlockTiles;
   const int64_t t1 = min(n_tiles, t0 + kDwBlockTiles);
   float* p = part + (size_t)blockIdx.x * (kW4 + 3 * 64);
@@ -898,12 +794,7 @@ hipError_t launch_nrc_forward(const float* W, const float* x, int64_t n, float* 
   hipLaunchKernelGGL(k_nrc_forward, dim3(grid_for(n, 4096)), dim3(kBlockN), 0, st, W, x, n, y);
   return hipGetLastError();
 }
-hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n,
-                               float* dW, float* dx, hipStream_t st) {
-  hipLaunchKernelGGL(k_nrc_backward, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, W, x, dy, n,
-                     dW, dx);
-  return hipGetLastError();
-}
+
 hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_nrc_encode, dim3(grid_for(n, 4096)), dim3(kBlockN), 0, st, net, rec, n, x);
@@ -932,6 +823,23 @@ static int64_t ws_chunk_bytes(int64_t n) { return ((n + 15) / 16) * kChunks * 64
 static int64_t ws_part_bytes(int64_t n) { return dw_blocks(n) * (kW4 + 3 * 64) * 4; }
 int64_t nrc_train_workspace_bytes(int64_t n) {
   return ws_chunk_bytes(n) + ws_part_bytes(n) + n * 4 + kQueryBins * 4;
+}
+
+hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n, void* ws,
+                               float* dW, float* dx, hipStream_t st) {
+  const int64_t n_tiles = (n + 15) / 16;
+  if (n_tiles == 0) return hipSuccess;
+  float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + ws_chunk_bytes(n));
+  hipLaunchKernelGGL(k_nrc_backward, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, W, x, dy, n,
+                     reinterpret_cast<bf16x4*>(ws), dx);
+  const int64_t blocks = dw_blocks(n);
+  hipLaunchKernelGGL(k_nrc_dw, dim3((unsigned)blocks), dim3(kBlockN), 0, st,
+                     reinterpret_cast<const bf16x4*>(ws), (const int*)nullptr, n, part);
+  hipLaunchKernelGGL(k_nrc_dw_reduce,
+                     dim3((kW4 + 3 * 64 + kBlockN - 1) / kBlockN,
+                          (unsigned)((blocks + kReduceSlice - 1) / kReduceSlice)),
+                     dim3(kBlockN), 0, st, part, (int)blocks, dW);
+  return hipGetLastError();
 }
 
 hipError_t launch_nrc_train2(const DNrcNet& net, const float* W, const float* rec, const int* valid,
