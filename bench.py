@@ -119,6 +119,27 @@ def main():
     value = samples / (ms * 1e-3) / 1e6
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
+    # the primal of the same step by the wavefront variant (comparison only)
+    ws = torch.empty(int(drt.lib.drt_render_wavefront_workspace_bytes(R * R * SPP)), dtype=torch.uint8,
+                     device=dev)
+    wf_img = torch.empty_like(img)
+    drt.render_wavefront(gs, [tex], rough, cams, SPP, D, seed=1, out=wf_img, workspace=ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(3):
+        drt.render_forward(gs, [tex], rough, cams, SPP, D, seed=3 + k, out=wf_img)
+    e1.record()
+    torch.cuda.synchronize()
+    mk_ms = e0.elapsed_time(e1) / 3
+    e0.record()
+    for k in range(3):
+        drt.render_wavefront(gs, [tex], rough, cams, SPP, D, seed=3 + k, out=wf_img, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wavefront = {"primal_ms_megakernel": round(mk_ms, 3), "primal_ms_wavefront": round(e0.elapsed_time(e1) / 3, 3),
+                 "wavefront_over_megakernel_time": round(e0.elapsed_time(e1) / 3 / mk_ms, 3)}
+    del ws, wf_img
+
     # algorithmic work of one adjoint launch (stats run, not timed)
     stats = drt.new_stats()
     drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * args.warmup + 2,
@@ -169,6 +190,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cache": cache,
+        "wavefront": wavefront,
         "aux": aux,
     }
     print(json.dumps(line), flush=True)
@@ -213,9 +235,21 @@ def aux_primal_1m(drt, scenes, torch):
     drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=2, out=img, stats=stats)
     st = drt.read_stats(stats)
     rays = st["rays"] + st["shadow_rays"]
+    # the same image by the wavefront variant (state through HBM between kernels)
+    ws = torch.empty(int(drt.lib.drt_render_wavefront_workspace_bytes(1024 * 1024 * 64)),
+                     dtype=torch.uint8, device="cuda")
+    drt.render_wavefront(gs, tex, rough, sc.cameras, 64, 6, 3, seed=1, out=img, workspace=ws)
+    e0.record()
+    for k in range(reps):
+        drt.render_wavefront(gs, tex, rough, sc.cameras, 64, 6, 3, seed=2 + k, out=img, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wf_ms = e0.elapsed_time(e1) / reps
+    del ws
     return {"workload": "procedural ~1M triangles, 8 BSDFs, env + 16 quad lights, 1024^2 64spp D6 RR3",
             "triangles": sc.n_triangles, "primal_msamples_s": round(1024 * 1024 * 64 / ms / 1e3, 2),
-            "primal_ms": round(ms, 2), "mrays_s": round(rays / ms / 1e3, 1),
+            "primal_ms": round(ms, 2), "wavefront_primal_ms": round(wf_ms, 2),
+            "wavefront_over_megakernel_time": round(wf_ms / ms, 3), "mrays_s": round(rays / ms / 1e3, 1),
             "nodes_per_ray": round(st["nodes"] / max(rays, 1), 2),
             "tris_per_ray": round(st["tris"] / max(rays, 1), 2),
             "bvh": {k: gs.info[k] for k in ("n_nodes", "max_depth", "forced_leaves")},

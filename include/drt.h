@@ -215,6 +215,20 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
                               const float* adj_image, const drt_grads* grads, void* hip_stream);
 
+/* The primal image by the wavefront variant of the same estimator (same
+ * sample streams and conventions as drt_render_forward): per bounce, a
+ * closest-hit kernel, a shading kernel and a shadow-ray kernel exchange the
+ * path state through the workspace (the execution model the paper's
+ * megakernels are compared with, Sec. "Evaluation").  For the comparison;
+ * opts->stats is ignored.  workspace: device scratch of at least
+ * drt_render_wavefront_workspace_bytes(n_cams*W*H*spp) bytes, 16-byte
+ * aligned. */
+int64_t drt_render_wavefront_workspace_bytes(int64_t n_paths);
+drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params,
+                                const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                                void* workspace, int64_t workspace_bytes, float* image,
+                                void* hip_stream);
+
 /* Forward-mode derivative of the primal image along a parameter direction
  * (Sec. "Physically Based Differentiable Rendering" describes the forward
  * mode used to check and visualise derivatives): image_tangent = d I / d params

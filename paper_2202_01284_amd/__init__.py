@@ -113,6 +113,9 @@ _SIGS = {
     "drt_scene_destroy": (_c_i32, [_vp]),
     "drt_render_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                     _c_i32, ctypes.POINTER(drt_render_opts), _vp, _vp]),
+    "drt_render_wavefront_workspace_bytes": (_c_i64, [_c_i64]),
+    "drt_render_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                      _c_i32, ctypes.POINTER(drt_render_opts), _vp, _c_i64, _vp, _vp]),
     "drt_render_jvp": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                 ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_grads), _vp, _vp]),
     "drt_render_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
@@ -419,6 +422,29 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
                                   adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
            "drt_render_adjoint")
     return grad_textures, grad_roughness
+
+
+def render_wavefront(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,
+                     rr_depth: int = NO_RR, seed: int = 1, flags: int = 0, out=None, workspace=None,
+                     stream=None):
+    """Primal image [n_cams, H, W, 3] by the wavefront variant (for the
+    megakernel-versus-wavefront comparison)."""
+    torch = _torch()
+    W, H = cams[0].width, cams[0].height
+    dev = scene.buffer.device
+    if out is None:
+        out = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=dev)
+    _expect(out, "out", _image_shape(cams))
+    need = int(lib.drt_render_wavefront_workspace_bytes(len(cams) * W * H * spp))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    _check(lib.drt_render_wavefront(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                    workspace.data_ptr(), workspace.numel(), out.data_ptr(),
+                                    _stream(stream)), "drt_render_wavefront")
+    return out
 
 
 def render_jvp(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,

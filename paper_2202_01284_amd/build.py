@@ -8,11 +8,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdrt.so")
-SOURCES = ["drt_kernels.hip", "drt_nrc.hip", "drt_host.cpp"]
+SOURCES = ["drt_kernels.hip", "drt_nrc.hip", "drt_wavefront.hip", "drt_host.cpp"]
 # per-source extra flags: the kernels use the hardware's approximate (about
 # 1 ulp) float division and square root instead of correctly rounded sequences
 EXTRA = {"drt_kernels.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"],
-         "drt_nrc.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+         "drt_nrc.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"],
+         "drt_wavefront.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

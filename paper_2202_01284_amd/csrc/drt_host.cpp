@@ -743,6 +743,31 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
   return ok();
 }
 
+int64_t drt_render_wavefront_workspace_bytes(int64_t n_paths) {
+  return n_paths < 0 ? 0 : wavefront_workspace_bytes(n_paths);
+}
+
+drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params,
+                                const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                                void* workspace, int64_t workspace_bytes, float* image,
+                                void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!image || !workspace) return fail(DRT_EINVAL, "image and workspace are required");
+  const int64_t n = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
+  if (workspace_bytes < wavefront_workspace_bytes(n))
+    return fail(DRT_EINVAL, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                (long long)wavefront_workspace_bytes(n));
+  if (((uintptr_t)workspace & 15) != 0) return fail(DRT_EINVAL, "workspace is not 16-byte aligned");
+  dr.stats = nullptr;
+  hipError_t e = launch_render_wavefront(scene->dev, dp, dc, dr, workspace, image, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "render_wavefront launch");
+  return ok();
+}
+
 drt_status drt_render_jvp(const drt_scene* scene, const drt_params* params, const drt_camera* cams,
                           int32_t n_cams, const drt_render_opts* opts, const drt_grads* direction,
                           float* image_tangent, void* hip_stream) {

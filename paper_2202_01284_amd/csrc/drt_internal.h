@@ -176,6 +176,9 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
                                         const DNrcIO& io, hipStream_t st);
 hipError_t launch_render_jvp(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                              const DGrads& t, float* image, hipStream_t st);
+int64_t wavefront_workspace_bytes(int64_t n_paths);
+hipError_t launch_render_wavefront(const DScene& s, const DParams& p, const DCams& c,
+                                   const DRender& r, void* ws, float* image, hipStream_t st);
 hipError_t launch_trace(const DScene& s, const float* rays, int64_t n, int mode, drt_hit* hits,
                         hipStream_t st);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,
