@@ -45,7 +45,7 @@ typedef enum {
   DRT_ENOMEM = -2,      /* host allocation failed */
   DRT_EHIP = -3,        /* a HIP call or kernel launch failed */
   DRT_ESTATE = -4,      /* object in the wrong state */
-  DRT_EUNSUPPORTED = -5 /* valid request beyond this build's limits */
+  DRT_EUNSUPPORTED = -5 /* valid request beyond the library's limits */
 } drt_status;
 
 /* Message of the last failure on the calling thread ("" if none). */
@@ -282,7 +282,7 @@ drt_status drt_adam_step(float* param, float* grad, float* m, float* v, int64_t 
                          const drt_adam_opts* opts, void* hip_stream);
 
 /* ------------------------------------------------------------------------
- * Neural radiance cache.  The paper does not cover it; this build adds it as
+ * Neural radiance cache.  The paper does not cover it; the library adds it as
  * a learned replacement of path tails: paths stop at their record vertex --
  * the first scattering vertex with index >= K, after that vertex's emission
  * -- and add beta * max(C, 0), where C is a small network evaluated on an
@@ -307,8 +307,8 @@ drt_status drt_adam_step(float* param, float* grad, float* m, float* v, int64_t 
 enum { DRT_NRC_INPUTS = 80, DRT_NRC_WEIGHTS = 17600, DRT_NRC_RECORD = 16, DRT_NRC_LEVELS = 16 };
 
 typedef struct {
-  int32_t levels;        /* 16 in this build */
-  int32_t features;      /* 2 in this build */
+  int32_t levels;        /* must be 16 */
+  int32_t features;      /* must be 2 */
   int32_t log2_table;    /* entries per level = 2^log2_table, 10..24 */
   int32_t base_res, max_res;
   int32_t trunc_vertex;  /* K >= 2 */

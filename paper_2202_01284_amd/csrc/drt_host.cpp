@@ -615,7 +615,7 @@ static hipError_t answer_queries(const DNrcNet& net, const float* weights, const
 drt_status nrc_net(const drt_nrc_config* c, const uint16_t* grid, DNrcNet* net) {
   if (!c) return fail(DRT_EINVAL, "cache config is NULL");
   if (c->levels != DRT_NRC_LEVELS || c->features != 2)
-    return fail(DRT_EUNSUPPORTED, "this build has 16 levels of 2 features");
+    return fail(DRT_EUNSUPPORTED, "the cache has 16 levels of 2 features");
   if (c->log2_table < 10 || c->log2_table > 24) return fail(DRT_EINVAL, "log2_table must be in [10, 24]");
   if (c->base_res < 1 || c->max_res < c->base_res) return fail(DRT_EINVAL, "bad grid resolutions");
   if (c->trunc_vertex < 2) return fail(DRT_EINVAL, "trunc_vertex must be >= 2");
