@@ -136,9 +136,33 @@ def main():
         drt.render_wavefront(gs, [tex], rough, cams, SPP, D, seed=3 + k, out=wf_img, workspace=ws)
     e1.record()
     torch.cuda.synchronize()
-    wavefront = {"primal_ms_megakernel": round(mk_ms, 3), "primal_ms_wavefront": round(e0.elapsed_time(e1) / 3, 3),
-                 "wavefront_over_megakernel_time": round(e0.elapsed_time(e1) / 3 / mk_ms, 3)}
+    wf_ms = e0.elapsed_time(e1) / 3
     del ws, wf_img
+    # and the replayed adjoint (gradients into scratch tensors)
+    ws = torch.empty(int(drt.lib.drt_render_adjoint_wavefront_workspace_bytes(R * R * SPP)),
+                     dtype=torch.uint8, device=dev)
+    g_t, g_r = torch.zeros_like(tex), torch.zeros_like(rough)
+    drt.render_adjoint_wavefront(gs, [tex], rough, cams, adj, SPP, D, seed=2, grad_textures=[g_t],
+                                 grad_roughness=g_r, workspace=ws)
+    e0.record()
+    for k in range(2):
+        drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=4 + k, grad_textures=[g_t],
+                           grad_roughness=g_r)
+    e1.record()
+    torch.cuda.synchronize()
+    mk_adj = e0.elapsed_time(e1) / 2
+    e0.record()
+    for k in range(2):
+        drt.render_adjoint_wavefront(gs, [tex], rough, cams, adj, SPP, D, seed=4 + k, grad_textures=[g_t],
+                                     grad_roughness=g_r, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wf_adj = e0.elapsed_time(e1) / 2
+    del ws, g_t, g_r
+    wavefront = {"primal_ms_megakernel": round(mk_ms, 3), "primal_ms_wavefront": round(wf_ms, 3),
+                 "adjoint_ms_megakernel": round(mk_adj, 3), "adjoint_ms_wavefront": round(wf_adj, 3),
+                 "wavefront_over_megakernel_time": {"primal": round(wf_ms / mk_ms, 3),
+                                                    "adjoint": round(wf_adj / mk_adj, 3)}}
 
     # algorithmic work of one adjoint launch (stats run, not timed)
     stats = drt.new_stats()
@@ -246,10 +270,32 @@ def aux_primal_1m(drt, scenes, torch):
     torch.cuda.synchronize()
     wf_ms = e0.elapsed_time(e1) / reps
     del ws
+    # replayed adjoint at 16 spp (random image adjoint), megakernel vs wavefront
+    adj = torch.randn((1, 1024, 1024, 3), device="cuda") * 1e-3
+    gt = [torch.zeros_like(x) for x in tex]
+    gr = torch.zeros_like(rough)
+    ws = torch.empty(int(drt.lib.drt_render_adjoint_wavefront_workspace_bytes(1024 * 1024 * 16)),
+                     dtype=torch.uint8, device="cuda")
+    drt.render_adjoint_wavefront(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=5, grad_textures=gt,
+                                 grad_roughness=gr, workspace=ws)
+    e0.record()
+    drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=6, grad_textures=gt, grad_roughness=gr)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_mk = e0.elapsed_time(e1)
+    e0.record()
+    drt.render_adjoint_wavefront(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=6, grad_textures=gt,
+                                 grad_roughness=gr, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_wf = e0.elapsed_time(e1)
+    del ws, gt, gr, adj
     return {"workload": "procedural ~1M triangles, 8 BSDFs, env + 16 quad lights, 1024^2 64spp D6 RR3",
             "triangles": sc.n_triangles, "primal_msamples_s": round(1024 * 1024 * 64 / ms / 1e3, 2),
             "primal_ms": round(ms, 2), "wavefront_primal_ms": round(wf_ms, 2),
-            "wavefront_over_megakernel_time": round(wf_ms / ms, 3), "mrays_s": round(rays / ms / 1e3, 1),
+            "wavefront_over_megakernel_time": round(wf_ms / ms, 3),
+            "adjoint_16spp_ms": {"megakernel": round(adj_mk, 2), "wavefront": round(adj_wf, 2)},
+            "mrays_s": round(rays / ms / 1e3, 1),
             "nodes_per_ray": round(st["nodes"] / max(rays, 1), 2),
             "tris_per_ray": round(st["tris"] / max(rays, 1), 2),
             "bvh": {k: gs.info[k] for k in ("n_nodes", "max_depth", "forced_leaves")},

@@ -229,6 +229,20 @@ drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params
                                 void* workspace, int64_t workspace_bytes, float* image,
                                 void* hip_stream);
 
+/* The replayed adjoint by the wavefront variant: pass A (the primal with
+ * opts->seed, radiance per path) and pass B (the replay with the
+ * subtractions and the gradient scatter) as per-bounce kernels exchanging
+ * the path state through the workspace.  Same gradients as
+ * drt_render_adjoint (ADDED to grads) up to float rounding and atomic order.
+ * workspace: at least drt_render_adjoint_wavefront_workspace_bytes(
+ * n_cams*W*H*spp) bytes, 16-byte aligned. */
+int64_t drt_render_adjoint_wavefront_workspace_bytes(int64_t n_paths);
+drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params* params,
+                                        const drt_camera* cams, int32_t n_cams,
+                                        const drt_render_opts* opts, const float* adj_image,
+                                        const drt_grads* grads, void* workspace,
+                                        int64_t workspace_bytes, void* hip_stream);
+
 /* Forward-mode derivative of the primal image along a parameter direction
  * (Sec. "Physically Based Differentiable Rendering" describes the forward
  * mode used to check and visualise derivatives): image_tangent = d I / d params

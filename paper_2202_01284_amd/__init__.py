@@ -116,6 +116,10 @@ _SIGS = {
     "drt_render_wavefront_workspace_bytes": (_c_i64, [_c_i64]),
     "drt_render_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                       _c_i32, ctypes.POINTER(drt_render_opts), _vp, _c_i64, _vp, _vp]),
+    "drt_render_adjoint_wavefront_workspace_bytes": (_c_i64, [_c_i64]),
+    "drt_render_adjoint_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                              _c_i32, ctypes.POINTER(drt_render_opts), _vp,
+                                              ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
     "drt_render_jvp": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                 ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_grads), _vp, _vp]),
     "drt_render_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
@@ -445,6 +449,41 @@ def render_wavefront(scene: Scene, textures: Sequence, roughness, cams, spp: int
                                     workspace.data_ptr(), workspace.numel(), out.data_ptr(),
                                     _stream(stream)), "drt_render_wavefront")
     return out
+
+
+def render_adjoint_wavefront(scene: Scene, textures: Sequence, roughness, cams, adj_image, spp: int,
+                             max_depth: int, rr_depth: int = NO_RR, seed: int = 2, flags: int = 0,
+                             grad_textures=None, grad_roughness=None, workspace=None, stream=None):
+    """The replayed adjoint by the wavefront variant: adds the gradient of
+    <adj, I> into grad_textures / grad_roughness and returns them."""
+    torch = _torch()
+    _expect(adj_image, "adj_image", _image_shape(cams))
+    if grad_textures is None:
+        grad_textures = [torch.zeros_like(t) for t in textures]
+    if grad_roughness is None and roughness is not None and roughness.numel() > 0:
+        grad_roughness = torch.zeros_like(roughness)
+    g = drt_grads()
+    for i, t in enumerate(grad_textures):
+        if t is not None:
+            _expect(t, f"grad texture {i}", scene.tex_shapes[i])
+            g.textures[i] = t.data_ptr()
+    if grad_roughness is not None:
+        _expect(grad_roughness, "grad roughness")
+        if grad_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
+        g.roughness = grad_roughness.data_ptr()
+    n = len(cams) * cams[0].width * cams[0].height * spp
+    if workspace is None:
+        workspace = torch.empty(int(lib.drt_render_adjoint_wavefront_workspace_bytes(n)), dtype=torch.uint8,
+                                device=scene.buffer.device)
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    _check(lib.drt_render_adjoint_wavefront(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                            adj_image.data_ptr(), ctypes.byref(g), workspace.data_ptr(),
+                                            workspace.numel(), _stream(stream)),
+           "drt_render_adjoint_wavefront")
+    return grad_textures, grad_roughness
 
 
 def render_jvp(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,

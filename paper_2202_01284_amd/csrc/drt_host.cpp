@@ -768,6 +768,38 @@ drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params
   return ok();
 }
 
+int64_t drt_render_adjoint_wavefront_workspace_bytes(int64_t n_paths) {
+  return n_paths < 0 ? 0 : wavefront_adjoint_workspace_bytes(n_paths);
+}
+
+drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params* params,
+                                        const drt_camera* cams, int32_t n_cams,
+                                        const drt_render_opts* opts, const float* adj_image,
+                                        const drt_grads* grads, void* workspace,
+                                        int64_t workspace_bytes, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!adj_image || !grads || !workspace)
+    return fail(DRT_EINVAL, "adj_image, grads and workspace are required");
+  const int64_t n = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
+  if (workspace_bytes < wavefront_adjoint_workspace_bytes(n))
+    return fail(DRT_EINVAL, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                (long long)wavefront_adjoint_workspace_bytes(n));
+  if (((uintptr_t)workspace & 15) != 0) return fail(DRT_EINVAL, "workspace is not 16-byte aligned");
+  DGrads dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
+  dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  dr.stats = nullptr;
+  hipError_t e = launch_render_adjoint_wavefront(scene->dev, dp, dc, dr, adj_image, dg, workspace,
+                                                 (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "render_adjoint_wavefront launch");
+  return ok();
+}
+
 drt_status drt_render_jvp(const drt_scene* scene, const drt_params* params, const drt_camera* cams,
                           int32_t n_cams, const drt_render_opts* opts, const drt_grads* direction,
                           float* image_tangent, void* hip_stream) {

@@ -177,6 +177,10 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
 hipError_t launch_render_jvp(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                              const DGrads& t, float* image, hipStream_t st);
 int64_t wavefront_workspace_bytes(int64_t n_paths);
+int64_t wavefront_adjoint_workspace_bytes(int64_t n_paths);
+hipError_t launch_render_adjoint_wavefront(const DScene& s, const DParams& p, const DCams& c,
+                                           const DRender& r, const float* adj, const DGrads& G,
+                                           void* ws, hipStream_t st);
 hipError_t launch_render_wavefront(const DScene& s, const DParams& p, const DCams& c,
                                    const DRender& r, void* ws, float* image, hipStream_t st);
 hipError_t launch_trace(const DScene& s, const float* rays, int64_t n, int mode, drt_hit* hits,

@@ -1,35 +1,57 @@
-// Wavefront variant of the primal renderer: the same estimator as the
-// megakernel (identical Philox counters, conventions and device functions),
-// but every bounce is split into separate kernels that pass the path state
-// through HBM -- closest hit, shading, shadow ray -- the execution model the
-// paper compares its megakernels against (Sec. "Evaluation": wavefront
-// versus megakernel).  One lane per path g = ((cam H + y) W + x) spp + s;
-// paths that have ended return at once (no compaction).
+// Wavefront variants of the primal renderer and of the replayed adjoint:
+// the same estimators as the megakernels (identical Philox counters,
+// conventions, device functions and arithmetic order), but every bounce is
+// split into separate kernels that pass the path state through HBM --
+// closest hit, shading, shadow ray (in the replay: resolving the vertex and
+// scattering its gradient) -- the execution model the paper compares its
+// megakernels against (Sec. "Evaluation": wavefront versus megakernel).
+// One lane per path g = ((cam H + y) W + x) spp + s; paths that have ended
+// return at once (no compaction).  The adjoint runs pass A (the primal with
+// the replay seed, for each path's radiance L) and then pass B, the replay
+// from L_rem = L with the subtractions and the gradient scatter of Path
+// Replay Backpropagation (Sec. "Physically Based Differentiable Rendering").
 //
 // Path state (structure of arrays, float4 each, in a caller workspace):
 //   o4  = (origin, prev_pdf)        d4  = (direction, k as int bits)
-//   b4  = (beta, alive as int bits) L4  = (radiance, unused)
+//   b4  = (beta, alive as int bits) L4  = (radiance, or L_rem in the replay)
 //   pp4 = (prev_p, unused)          h4  = (t, b1, b2, triangle as int bits)
 //   so4 = (shadow origin, tmax)     sd4 = (shadow direction, pending flag)
 //   sc4 = (next-event contribution, unused)
+// and, for the replay, the vertex's pending derivative terms:
+//   pa4 = ((d f/d albedo)/f, unused) pr4 = ((d f/d alpha)/f, unused)
+//   pn4 = (next-event albedo gradient, next-event roughness gradient)
+//   pv4 = (texture, texel, roughness slot, BSDF sample pending) as int bits
 #include "drt_device.h"
 
 namespace drt {
 
 struct WState {
   float4 *o4, *d4, *b4, *L4, *pp4, *h4, *so4, *sd4, *sc4;
+  float4 *pa4, *pr4, *pn4, *pv4;
 };
 
 constexpr int kWfBlock = 64;    // one wave per workgroup (LDS traversal stack per lane)
-constexpr int kWfArrays = 9;
+constexpr int kWfArrays = 9;    // primal state
+constexpr int kWfArraysAdj = 13;  // with the replay's pending terms
+
+// the path's share of the image adjoint (zero: the path is not traced)
+DEV f3 path_dL(const float* adj, int64_t g, int spp) {
+  const int64_t pix = g / spp;
+  const float inv = 1.0f / (float)spp;
+  return mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
+}
 
 DEV f3 xyz(float4 v) { return mk(v.x, v.y, v.z); }
 DEV float4 f4(f3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
 
-// camera rays of all paths
-__global__ __launch_bounds__(kWfBlock) void k_wf_camera(DCams C, DRender R, int64_t n, WState S) {
+// camera rays of all paths.  ADJ: paths whose pixel has a zero adjoint are
+// not traced; REPLAY: L4 keeps pass A's radiance as L_rem.
+template <bool ADJ, bool REPLAY>
+__global__ __launch_bounds__(kWfBlock) void k_wf_camera(DCams C, DRender R, int64_t n,
+                                                        const float* __restrict__ adj, WState S) {
   const int64_t g = (int64_t)blockIdx.x * kWfBlock + threadIdx.x;
   if (g >= n) return;
+  const bool live = !ADJ || nonzero(path_dL(adj, g, R.spp));
   const int64_t pix = g / R.spp;
   const int W = C.width, H = C.height;
   const int cam = (int)(pix / ((int64_t)W * H));
@@ -38,10 +60,11 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_camera(DCams C, DRender R, int6
   camera_ray(C.cam[cam], W, H, x, y, (uint32_t)g, (uint32_t)((uint64_t)g >> 32), R, o, d);
   S.o4[g] = f4(o, 0.f);  // prev_pdf 0: the first emitter hit takes no MIS weight
   S.d4[g] = f4(d, __int_as_float(1));
-  S.b4[g] = f4(mk(1, 1, 1), __int_as_float(1));
-  S.L4[g] = f4(mk(0, 0, 0), 0.f);
+  S.b4[g] = f4(mk(1, 1, 1), __int_as_float(live ? 1 : 0));
+  if (!REPLAY) S.L4[g] = f4(mk(0, 0, 0), 0.f);
   S.pp4[g] = f4(o, 0.f);
   S.sd4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (REPLAY) S.pv4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // closest hit of every live path
@@ -59,9 +82,12 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_trace(DScene s, int64_t n, WSta
 
 // the vertex found by the closest hit: emission (MIS), then, below the
 // maximum depth, a pass-through or the next-event candidate (its shadow ray
-// left pending) and the BSDF sample with Russian roulette
+// left pending) and the BSDF sample with Russian roulette.  RB (the replay):
+// the collected terms are subtracted from L_rem in L4 and the vertex's
+// derivative terms are left pending for k_wf_resolve.
+template <bool RB>
 __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRender R, int64_t n,
-                                                       WState S) {
+                                                       const float* __restrict__ adj, WState S) {
   __shared__ LdsTables tab;
   load_tables(tab, s, P, nullptr);
   __syncthreads();
@@ -83,6 +109,12 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
   bool nee = false;
   f3 nee_c = mk(0, 0, 0), so = o, sd = d;
   float stmax = 0.f;
+  // replay: the vertex's derivative terms
+  const f3 dL = RB ? path_dL(adj, g, R.spp) : mk(0, 0, 0);
+  f3 nee_gt = mk(0, 0, 0), rat_alb = mk(0, 0, 0), rat_alpha = mk(0, 0, 0);
+  float nee_gr = 0.f;
+  int vtex = -1, vtexel = 0, vrslot = -1;
+  bool bsdf_pend = false, shaded = false;
   if (tri < 0) {
     if (s.env_emitter >= 0) {
       int row, col;
@@ -90,7 +122,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
       env_cell(s, d, row, col, st);
       float w = 1.0f;
       if (!(prev_pdf == 0.f || no_nee)) w = power_heuristic(prev_pdf, p_sel * env_pdf(s, row, col, st));
-      L = L + beta * env_lookup(s, row, col) * w;
+      f3 c = beta * env_lookup(s, row, col) * w;
+      L = RB ? L - c : L + c;
     }
     done = true;
   } else {
@@ -110,7 +143,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         f3 dv = p - prev_p;
         w = power_heuristic(prev_pdf, p_sel * dot(dv, dv) / (E.area * cos_y));
       }
-      L = L + beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
+      f3 c = beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
+      L = RB ? L - c : L + c;
     }
     if (k == R.max_depth) {
       done = true;
@@ -124,6 +158,7 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         o = spawn(s, p, n_g, d);
         ++k;
       } else {
+        shaded = true;
         Frame fr = make_frame(n_g);
         f3 wi = to_local(fr, -d);
         Shade sh;
@@ -133,7 +168,7 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         sh.alpha = M.alpha;
         sh.eta = M.eta;
         sh.opacity = M.opacity;
-        const int vtex = M.texture;
+        vtex = M.texture;
         if (vtex >= 0) {
           float4 sa = shp[0];
           float u = sa.x * b0 + sa.z * hv.y + sb.x * hv.z;
@@ -141,10 +176,12 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
           int TW = tab.tw[vtex], TH = tab.th[vtex];
           int tx = (int)fminf(floorf(fmaxf(u, 0.f) * (float)TW), (float)(TW - 1));
           int ty = (int)fminf(floorf(fmaxf(v, 0.f) * (float)TH), (float)(TH - 1));
-          const float* tp = tab.tex[vtex] + 3 * (size_t)(ty * TW + tx);
+          vtexel = ty * TW + tx;
+          const float* tp = tab.tex[vtex] + 3 * (size_t)vtexel;
           sh.albedo = mk(tp[0], tp[1], tp[2]);
         }
-        if (M.rough_slot >= 0) sh.alpha = P.rough[M.rough_slot];
+        vrslot = M.rough_slot;
+        if (vrslot >= 0) sh.alpha = P.rough[vrslot];
         if (!no_nee && n_em > 0) {
           const DEmitter& E = s.ems[pick(r0.x, (uint32_t)n_em)];
           float lu = u01(r0.y), lv = u01(r0.z);
@@ -183,10 +220,16 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
             valid = true;
           }
           if (valid) {
-            BEval fe = bsdf_eval<false>(sh, wi, to_local(fr, wl));
+            BEval fe = bsdf_eval<RB>(sh, wi, to_local(fr, wl));
             if (nonzero(fe.f)) {
               float w = delta ? 1.0f : power_heuristic(p_sel * pdf_l, fe.pdf);
-              nee_c = beta * Le * (w / (p_sel * pdf_l)) * fe.f;
+              f3 coef = beta * Le * (w / (p_sel * pdf_l));
+              nee_c = coef * fe.f;
+              if (RB) {
+                nee_gt = dL * coef * fe.dalb;
+                f3 gr = dL * coef * fe.dalpha;
+                nee_gr = gr.x + gr.y + gr.z;
+              }
               so = spawn(s, p, n_g, wl);
               sd = wl;
               stmax = INFINITY;
@@ -202,7 +245,16 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         }
         f3 wo;
         BEval be;
-        if (bsdf_sample<false>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be)) {
+        const bool ok = bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
+        if (RB && ok) {
+          bsdf_pend = true;
+          rat_alb = mk(be.f.x != 0.f ? be.dalb.x / be.f.x : 0.f, be.f.y != 0.f ? be.dalb.y / be.f.y : 0.f,
+                       be.f.z != 0.f ? be.dalb.z / be.f.z : 0.f);
+          rat_alpha = mk(be.f.x != 0.f ? be.dalpha.x / be.f.x : 0.f,
+                         be.f.y != 0.f ? be.dalpha.y / be.f.y : 0.f,
+                         be.f.z != 0.f ? be.dalpha.z / be.f.z : 0.f);
+        }
+        if (ok) {
           beta = beta * be.f * (1.0f / be.pdf);
           prev_pdf = be.pdf;
           prev_p = p;
@@ -231,6 +283,15 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
     S.sc4[g] = f4(nee_c, 0.f);
   }
   S.sd4[g] = f4(sd, __int_as_float(nee ? 1 : 0));
+  if (RB) {
+    if (shaded) {
+      S.pa4[g] = f4(rat_alb, 0.f);
+      S.pr4[g] = f4(rat_alpha, 0.f);
+      S.pn4[g] = f4(nee_gt, nee_gr);
+    }
+    S.pv4[g] = make_float4(__int_as_float(shaded ? vtex : -1), __int_as_float(vtexel),
+                           __int_as_float(shaded ? vrslot : -1), __int_as_float(bsdf_pend ? 1 : 0));
+  }
 }
 
 // pending shadow rays: an unoccluded one adds its next-event contribution
@@ -251,6 +312,63 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shadow(DScene s, int64_t n, WSt
   S.sd4[g] = make_float4(sd4.x, sd4.y, sd4.z, 0.f);  // resolved (the path may have ended)
 }
 
+// replay: the vertex's shadow ray, then its gradient as the megakernel forms
+// it -- the next-event term if visible (L_rem loses it first), plus dL L_rem
+// (d f/f) for the sampled continuation -- scattered into its texel and
+// roughness slot (roughness pre-reduced in LDS per workgroup)
+__global__ __launch_bounds__(kWfBlock) void k_wf_resolve(DScene s, DParams P, DGrads G, DRender R,
+                                                         int64_t n, const float* __restrict__ adj,
+                                                         WState S) {
+  __shared__ int stack[kStackDepth * kWfBlock];
+  __shared__ LdsTables tab;
+  __shared__ float rough_acc[kMaxRoughLds];
+  const bool lds_rough = G.rough && s.n_rough <= kMaxRoughLds;
+  load_tables(tab, s, P, &G);
+  if (threadIdx.x < kMaxRoughLds) rough_acc[threadIdx.x] = 0.f;
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * kWfBlock + threadIdx.x;
+  Counters cnt = {};
+  if (g < n) {
+    const float4 sd4 = S.sd4[g], pv = S.pv4[g];
+    const bool nee = __float_as_int(sd4.w) != 0;
+    const int vtex = __float_as_int(pv.x), vtexel = __float_as_int(pv.y), vrslot = __float_as_int(pv.z);
+    const bool bsdf_pend = __float_as_int(pv.w) != 0;
+    if (nee || bsdf_pend) {
+      f3 Lrem = xyz(S.L4[g]);
+      f3 gtex = mk(0, 0, 0);
+      float grough = 0.f;
+      if (nee) {
+        const float4 so4 = S.so4[g];
+        Hit h;
+        RayPre rp = ray_pre(xyz(so4), xyz(sd4));
+        if (!traverse(s, rp, 0.f, so4.w, true, h, stack + threadIdx.x, cnt)) {
+          Lrem = Lrem - xyz(S.sc4[g]);
+          const float4 pn = S.pn4[g];
+          gtex = xyz(pn);
+          grough = pn.w;
+        }
+      }
+      if (bsdf_pend) {
+        const f3 dL = path_dL(adj, g, R.spp);
+        gtex = gtex + dL * Lrem * xyz(S.pa4[g]);
+        f3 gr = dL * Lrem * xyz(S.pr4[g]);
+        grough += gr.x + gr.y + gr.z;
+      }
+      Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
+      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
+      if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
+      S.L4[g] = f4(Lrem, 0.f);
+      S.sd4[g] = make_float4(sd4.x, sd4.y, sd4.z, 0.f);
+      S.pv4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  if (lds_rough && threadIdx.x < s.n_rough) {
+    const float v = rough_acc[threadIdx.x];
+    if (v != 0.f) atomicAdd(G.rough + threadIdx.x, v);
+  }
+}
+
 // image = mean over each pixel's samples (in sample order, as the megakernel sums)
 __global__ __launch_bounds__(256) void k_wf_accumulate(int64_t n_pix, int spp, WState S,
                                                        float* __restrict__ image) {
@@ -265,24 +383,56 @@ __global__ __launch_bounds__(256) void k_wf_accumulate(int64_t n_pix, int spp, W
 }
 
 int64_t wavefront_workspace_bytes(int64_t n_paths) { return n_paths * kWfArrays * 16; }
+int64_t wavefront_adjoint_workspace_bytes(int64_t n_paths) { return n_paths * kWfArraysAdj * 16; }
+
+static WState state_in(void* ws, int64_t n, int n_arrays) {
+  float4* base = static_cast<float4*>(ws);
+  WState S = {};
+  float4** arrays[kWfArraysAdj] = {&S.o4, &S.d4, &S.b4, &S.L4, &S.pp4, &S.h4, &S.so4,
+                                   &S.sd4, &S.sc4, &S.pa4, &S.pr4, &S.pn4, &S.pv4};
+  for (int a = 0; a < n_arrays; ++a) *arrays[a] = base + (size_t)a * n;
+  return S;
+}
+
+// one full primal pass over all paths (radiance per path in L4)
+static void primal_passes(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
+                          int64_t n, const float* adj, const WState& S, hipStream_t st) {
+  const unsigned blocks = (unsigned)((n + kWfBlock - 1) / kWfBlock);
+  if (adj)
+    hipLaunchKernelGGL((k_wf_camera<true, false>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, adj, S);
+  else
+    hipLaunchKernelGGL((k_wf_camera<false, false>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, adj, S);
+  for (int depth = 1; depth <= r.max_depth; ++depth) {
+    hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+    hipLaunchKernelGGL(k_wf_shade<false>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
+    hipLaunchKernelGGL(k_wf_shadow, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+  }
+}
 
 hipError_t launch_render_wavefront(const DScene& s, const DParams& p, const DCams& c,
                                    const DRender& r, void* ws, float* image, hipStream_t st) {
   const int64_t n_pix = (int64_t)c.n * c.width * c.height;
   const int64_t n = n_pix * r.spp;
-  float4* base = static_cast<float4*>(ws);
-  WState S;
-  float4** arrays[kWfArrays] = {&S.o4, &S.d4, &S.b4, &S.L4, &S.pp4, &S.h4, &S.so4, &S.sd4, &S.sc4};
-  for (int a = 0; a < kWfArrays; ++a) *arrays[a] = base + (size_t)a * n;
-  const unsigned blocks = (unsigned)((n + kWfBlock - 1) / kWfBlock);
-  hipLaunchKernelGGL(k_wf_camera, dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, S);
-  for (int depth = 1; depth <= r.max_depth; ++depth) {
-    hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
-    hipLaunchKernelGGL(k_wf_shade, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, S);
-    hipLaunchKernelGGL(k_wf_shadow, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
-  }
+  const WState S = state_in(ws, n, kWfArrays);
+  primal_passes(s, p, c, r, n, nullptr, S, st);
   hipLaunchKernelGGL(k_wf_accumulate, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, st, n_pix,
                      r.spp, S, image);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_adjoint_wavefront(const DScene& s, const DParams& p, const DCams& c,
+                                           const DRender& r, const float* adj, const DGrads& G,
+                                           void* ws, hipStream_t st) {
+  const int64_t n = (int64_t)c.n * c.width * c.height * r.spp;
+  const WState S = state_in(ws, n, kWfArraysAdj);
+  const unsigned blocks = (unsigned)((n + kWfBlock - 1) / kWfBlock);
+  primal_passes(s, p, c, r, n, adj, S, st);  // pass A: L per path
+  hipLaunchKernelGGL((k_wf_camera<true, true>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, adj, S);
+  for (int depth = 1; depth <= r.max_depth; ++depth) {
+    hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+    hipLaunchKernelGGL(k_wf_shade<true>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
+    hipLaunchKernelGGL(k_wf_resolve, dim3(blocks), dim3(kWfBlock), 0, st, s, p, G, r, n, adj, S);
+  }
   return hipGetLastError();
 }
 

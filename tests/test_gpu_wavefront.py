@@ -51,3 +51,38 @@ def test_wavefront_multi_camera_and_workspace_check():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(RuntimeError, match="workspace"):
         drt.render_wavefront(gs, tex, rough, sc.cameras, 3, 3, seed=7, workspace=small)
+
+
+@pytest.mark.parametrize("case", ["cornell_c1", "cornell_conductor", "zoo"])
+def test_wavefront_adjoint_equals_megakernel_and_oracle(case):
+    """The wavefront replay against the megakernel's (same seed: equal up to
+    float rounding and atomic order, relative L2 <= 1e-5) and the oracle
+    (gradient tolerance, pixels with FP32-reach decisions set aside)."""
+    from test_gpu_parity import ADJ_CASES, check_grad, unambiguous_adjoint
+    drt = _drt()
+    make, kw = ADJ_CASES[case]
+    sc = make()
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    c = sc.cameras[0]
+    rr = kw.get("rr_depth", drt.NO_RR)
+    orc = oracle.OracleScene(sc)
+    _, amb = orc.render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr, seed=2, ambiguity=True)
+    adj = unambiguous_adjoint(orc, np.random.default_rng(5).normal(size=(1, c.height, c.width, 3))
+                              .astype(np.float32), amb)
+    a = torch.from_numpy(adj).cuda()
+    wt, wr = drt.render_adjoint_wavefront(gs, tex, rough, sc.cameras, a, kw["spp"], kw["max_depth"], rr, seed=2)
+    mt, mr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, kw["spp"], kw["max_depth"], rr, seed=2)
+    for i, (w, m) in enumerate(zip(wt, mt)):
+        w, m = w.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+        r = np.linalg.norm(w - m) / np.linalg.norm(m)
+        print(case, f"texture {i}: wavefront vs megakernel rel {r:.3g}", flush=True)
+        assert r <= 1e-5
+    if len(sc.roughness):
+        assert np.allclose(wr.cpu().numpy(), mr.cpu().numpy(), rtol=1e-5, atol=1e-9)
+    ot, orr = orc.adjoint(adj.astype(np.float64), spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
+                          seed=2)
+    for i, (g, o) in enumerate(zip(wt, ot)):
+        check_grad(g.cpu().numpy(), o, f"{case} wavefront texture {i}")
+    if len(sc.roughness):
+        check_grad(wr.cpu().numpy(), orr, f"{case} wavefront roughness")
