@@ -227,10 +227,12 @@ def measured_traffic():
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "adjoint_traffic.json")))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        h = hashlib.sha256()
+        for f in rec["sources"]:  # every file the kernel is compiled from, in order
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if h.hexdigest() != rec.get("source_sha256"):
         return None
     return int(rec["hbm_bytes"])
 

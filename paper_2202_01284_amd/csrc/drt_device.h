@@ -216,15 +216,19 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
     cnt.nodes++;
     float t0, t1, t2, t3;
     bool h0, h1, h2, h3;
+    // The slab tests run whatever the counts say and are masked afterwards:
+    // a short-circuit on the count would put the box loads behind the count
+    // load and cost every node a second memory round trip.  Empty slots hold
+    // a zero box, so the test on them is harmless.
     {  // children 0 and 1: three float4 (fewer live registers than all four boxes)
       const float4 a = np[0], b = np[1], c = np[2];
-      h0 = cn.x >= 0 && slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0);
-      h1 = cn.y >= 0 && slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1);
+      h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0) & (cn.x >= 0);
+      h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1) & (cn.y >= 0);
     }
     {  // children 2 and 3
       const float4 a = np[3], b = np[4], c = np[5];
-      h2 = cn.z >= 0 && slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2);
-      h3 = cn.w >= 0 && slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3);
+      h2 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2) & (cn.z >= 0);
+      h3 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3) & (cn.w >= 0);
     }
     // leaf children: test their triangles now (one loop over the ranges)
     const int e0 = (h0 && cn.x > 0) ? cn.x : 0;
