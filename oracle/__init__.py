@@ -468,9 +468,10 @@ def _train_records(self, n_paths, K=3, cams=None, max_depth=6, rr_depth=3, flags
 
 def _adjoint_cached(self, cfg, grid, W, adj, K=3, cams=None, spp=4, max_depth=6, rr_depth=3,
                     flags=0, seed=2, pixel_ids=None, emu=True, textures=None, roughness=None,
-                    threads=None):
-    """Gradient of sum_p <adj_p, I_p> for the cached estimator (cache output
-    detached): (list of texture grads, roughness grad)."""
+                    threads=None, input_grad=False):
+    """Gradient of sum_p <adj_p, I_p> for the cached estimator: (list of
+    texture grads, roughness grad).  input_grad=False: cache output detached;
+    True: also through the network's albedo and roughness inputs."""
     cams = self.sc.cameras if cams is None else cams
     ca = cam_array(cams)
     Wd, H = cams[0].width, cams[0].height
@@ -489,7 +490,8 @@ def _adjoint_cached(self, cfg, grid, W, adj, K=3, cams=None, spp=4, max_depth=6,
     lib().oracle_adjoint_cached(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)), _c_int(spp),
                                 _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
                                 _c_int(K), _p(nrc_cfg_array(cfg)), _p(g), _p(Wv),
-                                _c_int(1 if emu else 0), _c_i64(pixel_ids.size), _p(pixel_ids),
+                                _c_int(1 if emu else 0), _c_int(1 if input_grad else 0),
+                                _c_i64(pixel_ids.size), _p(pixel_ids),
                                 _p(adj), _c_int(threads or n_threads_default()), gptr, _p(grough))
     return gtex, grough[:len(self.sc.roughness)]
 

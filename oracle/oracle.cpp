@@ -797,7 +797,10 @@ static V3 cam_dir(const Cam& k, int x, int y, double jx, double jy) {
 // conductor, 1 for a dielectric).  mode 0 (cached estimator): the path stops
 // there and the caller adds beta * max(C(features), 0).  mode 1 (training
 // record): the plain path continues; the target is the radiance collected
-// after the record point divided by beta at it.
+// after the record point divided by beta at it.  The hook also notes which
+// scene parameter each of the last four features is (the roughness slot for
+// a microfacet type, the albedo texel for a type whose albedo feature is its
+// albedo), for the derivative through the network's inputs.
 // ---------------------------------------------------------------------------
 struct CacheHook {
   int K = 3;
@@ -806,6 +809,8 @@ struct CacheHook {
   double feat[13];   // p[3], w[3], n[3], alpha, albedo[3]
   RGB beta;          // throughput at the record vertex
   RGB L_at;          // radiance collected up to and including its emission
+  bool tex_in = false, rough_in = false;  // features 10..12 / 9 are parameters
+  Key k_tex = 0, k_rough = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -893,6 +898,10 @@ static RGB trace_sample(const Scene& s, const Params& P, const Opts& opt, const 
       RGB alb = t == BSDF_CONDUCTOR ? mat.f0 : (t == BSDF_DIELECTRIC ? RGB(1, 1, 1) : sc.sh.albedo);
       f[10] = alb[0]; f[11] = alb[1]; f[12] = alb[2];
       std::memcpy(ch->feat, f, sizeof(f));
+      ch->tex_in = sc.has_tex && t != BSDF_CONDUCTOR && t != BSDF_DIELECTRIC;
+      ch->k_tex = sc.k_tex;
+      ch->rough_in = sc.has_rough && ggx;
+      ch->k_rough = sc.k_rough;
       ch->has = true;
       ch->beta = beta;
       ch->L_at = L;
@@ -1831,16 +1840,22 @@ void oracle_render_cached(void* h, const float* const* textures, const float* ro
 }
 
 // Reverse-mode gradient of the cached estimator (same adjoint convention as
-// oracle_adjoint, reverse sweep).  The cache output is detached: the term
-// beta * max(C, 0) at the record vertex enters the sweep like emission found
-// there, so it reaches earlier vertices' BSDF derivatives through beta, and
-// nothing flows through the network or its inputs.
+// oracle_adjoint, reverse sweep).  The term beta * max(C, 0) at the record
+// vertex enters the sweep like emission found there, so it reaches earlier
+// vertices' BSDF derivatives through beta.  input_grad = 0: that is all (the
+// cache output is detached).  input_grad = 1: the network is differentiated
+// too, through the inputs that are scene parameters -- the chain rule on
+// dL . beta * max(C(x), 0): output gradient dy_c = dL_c beta_c [C_c > 0],
+// back through the network to x, and d/dx of the albedo features (10..12)
+// and the roughness feature (9) added to the texel / roughness slot they
+// were read from.  With it the result is the derivative of the cached
+// estimator itself, not of its detached form.
 void oracle_adjoint_cached(void* h, const float* const* textures, const float* roughness,
                            const double* cams, int n_cams, int spp, int max_depth, int rr_depth,
                            uint32_t flags, uint64_t seed, int K, const double* cfg,
-                           const float* grid, const double* W, int emu, int64_t n_pix,
-                           const int64_t* pixel_ids, const double* adj, int n_threads,
-                           double* const* grad_tex, double* grad_rough) {
+                           const float* grid, const double* W, int emu, int input_grad,
+                           int64_t n_pix, const int64_t* pixel_ids, const double* adj,
+                           int n_threads, double* const* grad_tex, double* grad_rough) {
   const Scene& s = *(Scene*)h;
   Params P{textures, roughness};
   Opts opt{spp, max_depth, rr_depth, flags, seed};
@@ -1850,6 +1865,7 @@ void oracle_adjoint_cached(void* h, const float* const* textures, const float* r
   const int Wd = cs[0].W, Ht = cs[0].H;
   int nth = std::max(1, n_threads);
   std::vector<GradAcc> accs(nth);
+  std::vector<std::vector<double>> dWs(nth);  // weight gradient of mlp_backward, unused
   parallel_for(n_pix, nth, [&](int t, int64_t i) {
     int64_t pid = pixel_ids[i];
     int cam = (int)(pid / ((int64_t)Wd * Ht));
@@ -1873,6 +1889,16 @@ void oracle_adjoint_cached(void* h, const float* const* textures, const float* r
         RGB c;
         for (int ci = 0; ci < 3; ++ci) c[ci] = ch.beta[ci] * std::max(yv[ci], 0.0);
         recs.back().emit = recs.back().emit + c;
+        if (input_grad && (ch.tex_in || ch.rough_in)) {
+          double dy[3], dx[80];
+          for (int ci = 0; ci < 3; ++ci) dy[ci] = yv[ci] > 0 ? dL[ci] * ch.beta[ci] : 0.0;
+          if (dy[0] != 0 || dy[1] != 0 || dy[2] != 0) {
+            if (dWs[t].empty()) dWs[t].assign(kNumWeights, 0.0);
+            mlp_backward(W, enc, dy, emu != 0, dWs[t].data(), dx);
+            if (ch.tex_in) accs[t].add(ch.k_tex, RGB(dx[65], dx[66], dx[67]));
+            if (ch.rough_in) accs[t].add(ch.k_rough, RGB(dx[64], 0, 0));
+          }
+        }
       }
       reverse_sweep(recs, dL, &accs[t]);
     }

@@ -269,3 +269,125 @@ def test_cached_adjoint_matches_central_differences():
         fd = float(((ip - im) * adj).sum() / (2 * h))
         an = float((g * v).sum())
         assert math.isclose(an, fd, rel_tol=1e-9, abs_tol=1e-12), (trial, an, fd)
+
+
+def _linear_network(c=(0.5, 0.4, 0.3), a=(0.8, 1.1, 0.6), b=(0.7, 0.2, 0.9)):
+    """Weights whose output is c * Y_00 + a * albedo + b * roughness, per
+    channel: hidden units 0..4 carry the band-0 SH input (32), the three
+    albedo inputs (65..67) and the roughness input (64) unchanged through the
+    ReLU layers (all of them are >= 0)."""
+    W = np.zeros(oracle.mlp_num_weights())
+    W[0 * 80 + 32] = 1.0
+    for ch in range(3):
+        W[(1 + ch) * 80 + 65 + ch] = 1.0
+    W[4 * 80 + 64] = 1.0
+    for layer in range(3):
+        off = 64 * 80 + layer * 4096
+        for r in range(5):
+            W[off + r * 64 + r] = 1.0
+    off = 64 * 80 + 3 * 4096
+    for ch in range(3):
+        W[off + ch * 64 + 0] = c[ch]
+        W[off + ch * 64 + 1 + ch] = a[ch]
+        W[off + ch * 64 + 4] = b[ch]
+    return W
+
+
+def test_linear_network_output():
+    W = _linear_network()
+    x = np.random.default_rng(4).uniform(0.0, 1.0, size=(6, 80))
+    y = oracle.mlp_forward(x, W)
+    want = (np.array([0.5, 0.4, 0.3]) * x[:, 32:33] + np.array([0.8, 1.1, 0.6]) * x[:, 65:68]
+            + np.array([0.7, 0.2, 0.9]) * x[:, 64:65])
+    np.testing.assert_allclose(y, want, rtol=1e-14)
+
+
+def test_cached_adjoint_through_inputs_matches_differences_of_the_estimator():
+    """With a network linear in the albedo input, the cached estimator at
+    K = 3 is a polynomial of degree <= 3 in the texels (albedo at the two
+    scattering vertices before the record vertex and at the record vertex),
+    so the Richardson combination of central differences at h and 2h is
+    exact up to rounding.  The gradient through the network's inputs must
+    match it; the detached gradient must not."""
+    sc = scenes.cornell(texture=scenes.random_texture(8), width=16, height=16)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    W = _linear_network()
+    orc = oracle.OracleScene(sc)
+    rng = np.random.default_rng(12)
+    adj = rng.normal(size=(1, 16, 16, 3))
+    kw = dict(K=3, spp=2, max_depth=6, rr_depth=3, seed=9, emu=False)
+    # texels on a 2^-10 grid inside [0.1, 0.9], steps of 2^-6 and 2^-5: exact in float32
+    t0 = np.clip(sc.textures[0].astype(np.float64), 0.1, 0.9)
+    tex = (np.round(t0 * 1024) / 1024).astype(np.float32)
+    (g,), _ = orc.adjoint_cached(cfg, grid, W, adj, textures=[tex], input_grad=True, **kw)
+    (g0,), _ = orc.adjoint_cached(cfg, grid, W, adj, textures=[tex], **kw)
+
+    def fd(v, h):
+        ip = orc.render_cached(cfg, grid, W, textures=[tex + h * v], **kw)
+        im = orc.render_cached(cfg, grid, W, textures=[tex - h * v], **kw)
+        return float(((ip - im) * adj).sum() / (2 * h))
+
+    for trial in range(4):
+        v = np.zeros_like(tex)
+        sel = rng.choice(tex.size, 16, replace=False)
+        v.reshape(-1)[sel] = rng.choice([-1.0, 1.0], 16)
+        if trial == 0:
+            v = rng.choice([-1.0, 1.0], tex.shape).astype(np.float32)
+        h = 1.0 / 64
+        ref = (4.0 * fd(v, h) - fd(v, 2 * h)) / 3.0
+        an, an0 = float((g * v).sum()), float((g0 * v).sum())
+        assert math.isclose(an, ref, rel_tol=1e-8, abs_tol=1e-12), (trial, an, ref)
+        if trial == 0:
+            assert abs(an - an0) > 1e-3 * abs(an), (an, an0)
+
+
+def test_cached_adjoint_through_roughness_input_at_the_first_vertex():
+    """Record vertex K = 1: the cached estimator is the emission seen by the
+    camera ray plus C(features of its hit), linear in the roughness of the
+    GGX conductor and in the texels through this network, so central
+    differences are exact.  This pins the roughness feature's slot and the
+    texel lookup of the albedo feature."""
+    sc = scenes.cornell(texture=scenes.random_texture(8), width=16, height=16, conductor=True,
+                        roughness=0.25)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    W = _linear_network()
+    orc = oracle.OracleScene(sc)
+    rng = np.random.default_rng(13)
+    adj = rng.normal(size=(1, 16, 16, 3))
+    kw = dict(K=1, spp=2, max_depth=6, rr_depth=3, seed=10, emu=False)
+    tex = (np.round(sc.textures[0].astype(np.float64) * 1024) / 1024).astype(np.float32)
+    rough = np.array([0.25], np.float32)
+    (g,), gr = orc.adjoint_cached(cfg, grid, W, adj, textures=[tex], roughness=rough,
+                                  input_grad=True, **kw)
+    (g0,), gr0 = orc.adjoint_cached(cfg, grid, W, adj, textures=[tex], roughness=rough, **kw)
+    assert np.all(g0 == 0) and np.all(gr0 == 0)   # nothing before the record vertex
+    h = 1.0 / 64
+    ip = orc.render_cached(cfg, grid, W, textures=[tex], roughness=rough + h, **kw)
+    im = orc.render_cached(cfg, grid, W, textures=[tex], roughness=rough - h, **kw)
+    fd = float(((ip - im) * adj).sum() / (2 * h))
+    assert abs(gr[0]) > 1e-6
+    assert math.isclose(float(gr[0]), fd, rel_tol=1e-9, abs_tol=1e-13), (gr[0], fd)
+    v = rng.choice([-1.0, 1.0], tex.shape).astype(np.float32)
+    ip = orc.render_cached(cfg, grid, W, textures=[tex + h * v], roughness=rough, **kw)
+    im = orc.render_cached(cfg, grid, W, textures=[tex - h * v], roughness=rough, **kw)
+    fd = float(((ip - im) * adj).sum() / (2 * h))
+    assert math.isclose(float((g * v).sum()), fd, rel_tol=1e-9, abs_tol=1e-13)
+
+
+def test_cached_adjoint_input_term_vanishes_without_input_weights():
+    """A network that ignores its albedo and roughness inputs adds nothing
+    through them."""
+    sc = scenes.cornell(texture=scenes.random_texture(8), width=16, height=16, conductor=True)
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg)
+    W = np.array(W, np.float64)
+    W[np.arange(64)[:, None] * 80 + np.arange(64, 68)[None, :]] = 0.0
+    orc = oracle.OracleScene(sc)
+    adj = np.random.default_rng(14).normal(size=(1, 16, 16, 3))
+    kw = dict(K=3, spp=2, max_depth=6, rr_depth=3, seed=11, threads=1)  # one summation order
+    (g,), gr = orc.adjoint_cached(cfg, grid, W, adj, input_grad=True, **kw)
+    (g0,), gr0 = orc.adjoint_cached(cfg, grid, W, adj, **kw)
+    np.testing.assert_array_equal(g, g0)
+    np.testing.assert_array_equal(gr, gr0)
