@@ -408,7 +408,7 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
     work = drt.cached_work(n, dev, sample_radiance=True)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
-    def step(k, cached):
+    def step(k, cached, input_grad=False):
         if cached:
             cache.render(gs, [tex], rough, cams, SPP, seed=2 * k + 1, out=img, work=work[:3])
         else:
@@ -416,7 +416,7 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
         drt.loss_l2(img, target, adj=adj)
         if cached:
             cache.adjoint(gs, [tex], rough, cams, adj, SPP, seed=2 * k + 2, grad_textures=[gtex],
-                          grad_roughness=grough, work=work)
+                          grad_roughness=grough, work=work, input_grad=input_grad)
             cache.train_frame(gs, [tex], rough, cams, seed=20000 + k)
         else:
             drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, RR, seed=2 * k + 2,
@@ -425,17 +425,17 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
         drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=1e-2, lo=0.01, hi=1.0, zero_grad=True)
 
     out = {}
-    for cached in (False, True):
-        step(0, cached)
+    for name, cached, ig in (("plain", False, False), ("cache", True, False),
+                             ("cache_input_grad", True, True)):
+        step(0, cached, ig)
         a, b = ev(), ev()
         a.record()
         for k in range(1, 1 + steps):
-            step(k, cached)
+            step(k, cached, ig)
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
-        out["cache" if cached else "plain"] = {"ms_per_step": round(ms, 3),
-                                               "msamples_s": round(n / ms / 1e3, 2)}
+        out[name] = {"ms_per_step": round(ms, 3), "msamples_s": round(n / ms / 1e3, 2)}
     return {"workload": f"cornell-box + GGX conductor, {tex_size}^2x3 texture, {R}^2 {SPP}spp D{D} "
                         f"RR{RR}, cache at v3 (one 65,536-path training frame per step)", **out}
 
@@ -446,9 +446,10 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
     512^2 in one launch, depth 6, RR from 3, 4096^2x3 texture + roughness):
     the image adjoint is 2 (I - T) / N of a 32-spp primal against a 256-spp
     target; the reference gradient is the plain replayed adjoint at ref_spp;
-    the cached gradient (32 spp, cache trained for train_frames frames) is
-    timed, and the plain gradient is taken at the spp that costs the same
-    time.  Errors are ||g - g_ref|| / ||g_ref|| per texel and on the means of
+    the cached gradient (32 spp, cache trained for train_frames frames; output
+    detached, and through the network's albedo/roughness inputs) is timed,
+    and the plain gradient is taken at the spp that costs the same time as
+    the detached one.  Errors are ||g - g_ref|| / ||g_ref|| per texel and on the means of
     64x64-texel blocks (where sampling noise averages out and bias remains)."""
     D, RR = 6, 3
     sc = scenes.cornell(tex_size=tex_size, width=R, height=R, conductor=True)
@@ -488,6 +489,9 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
     work = drt.cached_work(n_cams * R * R * spp, dev, sample_radiance=True)
     g_c, _, t_c = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
                                                     grad_textures=[gt], grad_roughness=gr, work=work))
+    g_ci, _, t_ci = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
+                                                      grad_textures=[gt], grad_roughness=gr, work=work,
+                                                      input_grad=True))
     _, _, t_p32 = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, spp, D, RR, seed=105,
                                                          grad_textures=[gt], grad_roughness=gr))
     spp_p = max(1, int(round(spp * t_c / t_p32)))
@@ -502,10 +506,12 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
         block = float((blk(g) - blk(g_ref)).norm() / blk(g_ref).norm())
         return round(full, 4), round(block, 4)
 
-    ec, ep = err(g_c), err(g_p)
+    ec, ep, eci = err(g_c), err(g_p), err(g_ci)
     return {"workload": f"{n_cams} views x {R}^2, depth {D} RR{RR}, {tex_size}^2x3 texture, "
                         f"reference: plain adjoint at {ref_spp} spp",
             "cache": {"spp": spp, "ms": round(t_c, 2), "rel_err_texel": ec[0], "rel_err_64x64_blocks": ec[1]},
+            "cache_input_grad": {"spp": spp, "ms": round(t_ci, 2), "rel_err_texel": eci[0],
+                                 "rel_err_64x64_blocks": eci[1]},
             "plain_matched_time": {"spp": spp_p, "ms": round(t_p, 2), "rel_err_texel": ep[0],
                                    "rel_err_64x64_blocks": ep[1]},
             "train_frames": train_frames}

@@ -78,7 +78,9 @@ enum {
 
 /* Render flags. */
 enum {
-  DRT_FLAG_NO_NEE = 1 /* BSDF sampling only (no next-event estimation, no MIS) */
+  DRT_FLAG_NO_NEE = 1,         /* BSDF sampling only (no next-event estimation, no MIS) */
+  DRT_FLAG_CACHE_INPUT_GRAD = 2 /* drt_render_adjoint_cached: differentiate the cache's
+                                   output through its albedo and roughness inputs too */
 };
 
 typedef struct {
@@ -379,7 +381,7 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
 
 /* Entries of the int32 query scratch of the cached calls for `capacity`
  * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
- * bin histogram [4096]. */
+ * parameter references [capacity][2] | bin histogram [4096]. */
 int64_t drt_nrc_query_ints(int64_t capacity);
 
 /* Primal render with the cache: image = (1/spp) sum over samples of the
@@ -397,18 +399,27 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
                                      int32_t* query_ints, int32_t* query_count,
                                      int64_t capacity, float* image, void* hip_stream);
 
-/* Reverse-mode gradient of the cached estimator (cache output detached:
- * the network and its inputs receive no gradient; the term beta * max(C, 0)
+/* Reverse-mode gradient of the cached estimator.  The term beta * max(C, 0)
  * at the record vertex reaches earlier vertices' BSDF derivatives through
  * beta, as in the PRB replay of Sec. "Physically Based Differentiable
- * Rendering").  Three launches on the stream: a cached pass with seed
- * opts->seed that writes each sample's truncated radiance to
- * sample_radiance and its query (with the sample index) to queries /
- * query_ids; the network answers the queries into sample_radiance; the
- * replay then starts every sample from its stored estimate (no second
- * forward pass).  Gradients are ADDED to grads as in drt_render_adjoint.
- * sample_radiance: device float [n_cams*W*H*spp][3] (scratch); queries,
- * query_ints, query_count and capacity as for drt_render_forward_cached. */
+ * Rendering".  Without DRT_FLAG_CACHE_INPUT_GRAD in opts->flags that is all
+ * (cache output detached).  With it, the network is differentiated as well,
+ * through the inputs that are scene parameters: each query's output
+ * gradient dL * beta * [C > 0] (dL = adj of its pixel / spp) is propagated
+ * back through the network (BF16 operands, FP32 accumulation) to the albedo
+ * and roughness inputs, which are added to the texel and roughness slot the
+ * record vertex read them from (albedo of a conductor or dielectric and
+ * roughness of a non-microfacet type are constants: nothing is added);
+ * the network weights and the hash grid receive nothing.  Launches on the
+ * stream: a cached pass with seed opts->seed that writes each sample's
+ * truncated radiance to sample_radiance and its query (with the sample
+ * index) to queries / query_ints; the network answers the queries into
+ * sample_radiance; with the flag, one more network pass over the queries
+ * adds the input term; the replay then starts every sample from its stored
+ * estimate (no second forward pass).  Gradients are ADDED to grads as in
+ * drt_render_adjoint.  sample_radiance: device float [n_cams*W*H*spp][3]
+ * (scratch); queries, query_ints, query_count and capacity as for
+ * drt_render_forward_cached. */
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,

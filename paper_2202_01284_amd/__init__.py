@@ -26,6 +26,7 @@ LIB_PATH = os.environ.get("DRT_LIBRARY") or os.path.join(_HERE, "libdrt.so")
 MAX_TEXTURES = 8
 MAX_CAMERAS = 32
 FLAG_NO_NEE = 1
+FLAG_CACHE_INPUT_GRAD = 2   # cached adjoint: also through the cache's albedo/roughness inputs
 STAT_NAMES = ["rays", "shadow_rays", "nodes", "tris", "vertices", "scatter", "lrem_max", "samples"]
 
 _c_i32 = ctypes.c_int32
@@ -785,8 +786,10 @@ def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
                           adj_image, spp: int, max_depth: int = 6, rr_depth: int = 3, seed: int = 2,
                           flags: int = 0, grad_textures=None, grad_roughness=None, work=None,
                           stats=None, stream=None):
-    """Adds the gradient of <adj, I_cached> (cache output detached) into
-    grad_textures / grad_roughness and returns them."""
+    """Adds the gradient of <adj, I_cached> into grad_textures /
+    grad_roughness and returns them: with the cache output detached, or,
+    with FLAG_CACHE_INPUT_GRAD in flags, also through the network's albedo
+    and roughness inputs."""
     torch = _torch()
     _expect(adj_image, "adj_image", _image_shape(cams))
     if grad_textures is None:
@@ -871,9 +874,11 @@ class NrcCache:
         return self.loss
 
     def adjoint(self, scene: Scene, textures, roughness, cams, adj_image, spp: int, seed: int,
-                max_depth=6, rr_depth=3, grad_textures=None, grad_roughness=None, work=None):
+                max_depth=6, rr_depth=3, grad_textures=None, grad_roughness=None, work=None,
+                input_grad=False):
         return render_adjoint_cached(scene, textures, roughness, cams, self.cfg, self.W,
                                      self.grid16, adj_image, spp, max_depth, rr_depth, seed,
+                                     flags=FLAG_CACHE_INPUT_GRAD if input_grad else 0,
                                      grad_textures=grad_textures, grad_roughness=grad_roughness,
                                      work=work)
 

@@ -585,7 +585,8 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
 }
 
 // Query buffers of the cached calls: the int32 scratch holds ids | order |
-// bins | histogram (drt_nrc_query_ints).
+// bins | parameter references (2 per query) | histogram (drt_nrc_query_ints).
+// The references are written only when io.qref is set.
 static DNrcIO query_io(const DNrcNet& net, const drt_nrc_config* cfg, float* queries,
                        int32_t* ints, int32_t* count, int64_t capacity) {
   DNrcIO io = {};
@@ -606,7 +607,7 @@ static DNrcIO query_io(const DNrcNet& net, const drt_nrc_config* cfg, float* que
 static hipError_t answer_queries(const DNrcNet& net, const float* weights, const DNrcIO& io,
                                  int64_t need, float scale, float* out, hipStream_t st) {
   int* order = io.qpix + io.capacity;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(io.qpix + 3 * io.capacity);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(io.qpix + 5 * io.capacity);
   hipError_t e = launch_query_sort(io.qbin, io.count, need, hist, order, st);
   if (e != hipSuccess) return e;
   return launch_nrc_infer(net, weights, io.rec, io.qpix, order, io.count, need, scale, out, st);
@@ -972,7 +973,7 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
 }
 
 int64_t drt_nrc_query_ints(int64_t capacity) {
-  return capacity < 0 ? 0 : 3 * capacity + kQueryBins;
+  return capacity < 0 ? 0 : 5 * capacity + kQueryBins;
 }
 
 drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
@@ -1033,12 +1034,20 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   hipStream_t stream = (hipStream_t)hip_stream;
   DNrcIO io = query_io(net, cfg, queries, query_ints, query_count, capacity);
   io.lsamp = sample_radiance;
+  const bool input_grad = (opts->flags & DRT_FLAG_CACHE_INPUT_GRAD) != 0;
+  if (input_grad) io.qref = query_ints + 3 * capacity;
   hipError_t e = launch_zero(query_count, 1, stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
   e = launch_render_cached(scene->dev, dp, dc, dr, nullptr, io, stream);
   if (e != hipSuccess) return hip_fail(e, "render_cached launch");
   e = answer_queries(net, weights, io, need, 1.0f, sample_radiance, stream);
   if (e != hipSuccess) return hip_fail(e, "cache query launch");
+  if (input_grad) {
+    // the queries are in bin order now (answer_queries sorted them)
+    e = launch_nrc_input_grad(net, weights, io.rec, io.qpix, io.qref, io.qpix + capacity, io.count,
+                              need, opts->spp, adj_image, dg, stream);
+    if (e != hipSuccess) return hip_fail(e, "cache input-gradient launch");
+  }
   e = launch_render_adjoint_cached(scene->dev, dp, dc, dr, adj_image, dg, io, stream);
   if (e != hipSuccess) return hip_fail(e, "render_adjoint_cached launch");
   return ok();

@@ -140,8 +140,18 @@ struct DNrcIO {
   int K;            // record vertex index
   float* lsamp;     // per-sample radiance [n_samples][3] (cached adjoint), else null
   uint32_t* qbin;   // queries: spatial bin of each query (null: not binned)
+  int* qref;        // queries: [2] per query, the parameters its inputs were read
+                    // from (QueryRef), or null (not recorded)
   float lo[3], inv_ext[3];  // scene box of the cache (query binning)
 };
+
+// Scene parameters behind a query's inputs, two ints per query: the albedo
+// texel (-1: the albedo input is a constant) and texture | (roughness slot +
+// 1) << 8 (slot + 1 = 0: the roughness input is a constant).
+__host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int rough_slot) {
+  q[0] = texel;
+  q[1] = (tex & 0xff) | ((rough_slot + 1) << 8);
+}
 
 // Spatial binning of cache queries: 16 cells per axis of the cache's box,
 // Morton order (12 bits), so that bin-sorted queries gather nearby table entries.
@@ -206,6 +216,13 @@ hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t cap
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
                             const int* order, const int* count, int64_t capacity, float inv_spp,
                             float* image, hipStream_t st);
+// Gradient of the cache term through the network's albedo and roughness
+// inputs: queries q with sample ids qsample (pixel = id / spp), references
+// qref, in the bin order of launch_query_sort; adj: image adjoint.
+hipError_t launch_nrc_input_grad(const DNrcNet& net, const float* W, const float* q,
+                                 const int* qsample, const int* qref, const int* order,
+                                 const int* count, int64_t capacity, int spp, const float* adj,
+                                 const DGrads& g, hipStream_t st);
 hipError_t launch_nrc_grid_backward(const DNrcNet& net, const float* rec, const float* dx,
                                     int64_t n, float* dgrid, hipStream_t st);
 int64_t nrc_train_workspace_bytes(int64_t n);

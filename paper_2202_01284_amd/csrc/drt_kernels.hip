@@ -231,6 +231,12 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                   rec = io.rec + (size_t)NRC_REC * slot;
                   io.qpix[slot] = MODE == MODE_CACHED_SAMPLES ? (int)glo : (int)pix;
                   if (io.qbin) io.qbin[slot] = query_bin(p.x, p.y, p.z, io.lo, io.inv_ext);
+                  if (io.qref) {
+                    const bool tex_in = vtex >= 0 && type != DRT_BSDF_CONDUCTOR &&
+                                        type != DRT_BSDF_DIELECTRIC;
+                    query_ref_put(io.qref + 2 * (size_t)slot, tex_in ? vtexel : -1, vtex,
+                                  ggx ? vrslot : -1);
+                  }
                   rec[13] = beta.x;
                   rec[14] = beta.y;
                   rec[15] = beta.z;

@@ -420,10 +420,28 @@ static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hip
   return hipGetLastError();
 }
 
+// Tiles of this wave when the workgroups of a grid are dealt round-robin to
+// the 8 XCDs: XCD x walks its own contiguous tile range [x per, (x + 1) per),
+// so with spatially sorted queries its L2 holds the table entries of one
+// region at a time.
+struct TileRange {
+  int64_t first, end, step;
+};
+DEV TileRange xcd_tiles(int64_t n_tiles) {
+  const int n_x = min(8, (int)gridDim.x);
+  const int xcd = blockIdx.x % n_x;
+  const int64_t blocks_x = (gridDim.x - 1 - xcd) / n_x + 1;
+  const int64_t per = (n_tiles + n_x - 1) / n_x;
+  TileRange r;
+  r.first = (int64_t)xcd * per + (blockIdx.x / n_x) * (kBlockN / 64) + (threadIdx.x >> 6);
+  r.end = min(n_tiles, (int64_t)(xcd + 1) * per);
+  r.step = blocks_x * (kBlockN / 64);
+  return r;
+}
+
 // Cache queries: image[qpix] += beta * max(C(record), 0) * inv_spp, for the
-// queries in `order` (spatially sorted; null: in slot order).  Each XCD
-// (workgroups are dealt to the 8 XCDs round-robin) walks its own contiguous
-// range of tiles, so its L2 holds the table entries of one region at a time.
+// queries in `order` (spatially sorted; null: in slot order), tiles as in
+// xcd_tiles.
 __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float* __restrict__ W,
                                                       const float* __restrict__ q,
                                                       const int* __restrict__ qpix,
@@ -438,15 +456,8 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float*
   __syncthreads();
   const int64_t n = min((int64_t)*count, capacity);
   const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int64_t n_tiles = (n + 15) / 16;
-  const int n_x = min(8, (int)gridDim.x);
-  const int xcd = blockIdx.x % n_x;
-  const int64_t blocks_x = (gridDim.x - 1 - xcd) / n_x + 1;
-  const int64_t waves_x = blocks_x * (kBlockN / 64);
-  const int64_t per = (n_tiles + n_x - 1) / n_x;
-  const int64_t t1 = min(n_tiles, (int64_t)(xcd + 1) * per);
-  for (int64_t tile = (int64_t)xcd * per + (blockIdx.x / n_x) * (kBlockN / 64) + (threadIdx.x >> 6);
-       tile < t1; tile += waves_x) {
+  const TileRange tr = xcd_tiles((n + 15) / 16);
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
     int64_t slot = tile * 16 + (lane & 15);
     bool valid = slot < n;
     int64_t qi = valid ? (order ? (int64_t)order[slot] : slot) : 0;
@@ -497,13 +508,16 @@ DEV void put_chunk(bf16x4* ws, uint16_t* tb, int64_t tile, int c, bf16x4 v, int 
   ws[((size_t)tile * kChunks + c) * 64 + lane] = *reinterpret_cast<const bf16x4*>(tb + r * 16 + 4 * g);
 }
 
-// Backward propagation of one tile without the weight gradient: the masked
-// deltas of every layer (from the output gradient dyb, B layout), dx of
-// inputs 0..31, and the weight-gradient operands written to the workspace
-// (chunk map above).
-DEV void backprop_tile(const uint16_t* wl, uint16_t* tb, bf16x4* ws, int64_t tile, const Acts& A,
-                       bf16x4 dyb, f32x4 dx[2], int lane) {
-  bf16x4 g4[4], g3[4], g2[4], g1[4];
+// Masked deltas of one tile from the output gradient dyb (B layout): gl is
+// the gradient at hidden layer l's output, zero where its ReLU was off.
+struct Deltas {
+  bf16x4 g1[4], g2[4], g3[4], g4[4];
+};
+DEV void backprop_deltas(const uint16_t* wl, const Acts& A, bf16x4 dyb, Deltas& D, int lane) {
+  bf16x4(&g4)[4] = D.g4;
+  bf16x4(&g3)[4] = D.g3;
+  bf16x4(&g2)[4] = D.g2;
+  bf16x4(&g1)[4] = D.g1;
 #pragma unroll
   for (int t = 0; t < 4; ++t) g4[t] = mask_pack(mfma(ldAT(wl + kW4, 64, t, 0, lane), dyb, zero4()), A.h4[t]);
 #pragma unroll
@@ -524,12 +538,30 @@ DEV void backprop_tile(const uint16_t* wl, uint16_t* tb, bf16x4* ws, int64_t til
     for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW1, 64, t, s, lane), g2[s], acc);
     g1[t] = mask_pack(acc, A.h1[t]);
   }
+}
+
+// Input gradient of layer 0 for inputs 16t .. 16t + 15 (accumulator layout:
+// lane r + 16g holds inputs 16t + 4g .. +3 of sample r).
+DEV f32x4 input_grad_tile(const uint16_t* wl, const Deltas& D, int t, int lane) {
+  f32x4 acc = zero4();
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    f32x4 acc = zero4();
-    for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), g1[s], acc);
-    dx[t] = acc;
-  }
+  for (int s = 0; s < 4; ++s) acc = mfma(ldAT(wl + kW0, 80, t, s, lane), D.g1[s], acc);
+  return acc;
+}
+
+// Backward propagation of one tile without the weight gradient: the masked
+// deltas of every layer, dx of inputs 0..31, and the weight-gradient
+// operands written to the workspace (chunk map above).
+DEV void backprop_tile(const uint16_t* wl, uint16_t* tb, bf16x4* ws, int64_t tile, const Acts& A,
+                       bf16x4 dyb, f32x4 dx[2], int lane) {
+  Deltas D;
+  backprop_deltas(wl, A, dyb, D, lane);
+  const bf16x4(&g4)[4] = D.g4;
+  const bf16x4(&g3)[4] = D.g3;
+  const bf16x4(&g2)[4] = D.g2;
+  const bf16x4(&g1)[4] = D.g1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) dx[t] = input_grad_tile(wl, D, t, lane);
   // operands of the weight gradient
 #pragma unroll
   for (int c = 0; c < 5; ++c) put_chunk(ws, tb, tile, c, A.h0[c], lane);
@@ -655,6 +687,71 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restric
         for (int j = 0; j < 4; ++j) dx[sample * 80 + 16 * t + 4 * g + j] = t < 2 ? dxv[t][j] : 0.f;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// gradient of the cache term through the network's inputs
+// ---------------------------------------------------------------------------
+// Per query (bin order, tiles as in xcd_tiles): forward pass, output gradient
+// dy = dL * beta * [y > 0] with dL = adj[pixel] / spp, the masked deltas back
+// to layer 0, and the input gradient of inputs 64..67 (roughness, albedo),
+// added to the roughness slot and albedo texel the query's vertex read them
+// from.  Roughness sums go through LDS for the first kMaxRoughLds slots (all
+// queries of a conductor hit one slot).
+__global__ __launch_bounds__(kBlockN) void k_nrc_input_grad(
+    DNrcNet net, const float* __restrict__ W, const float* __restrict__ q,
+    const int* __restrict__ qsample, const int* __restrict__ qref, const int* __restrict__ order,
+    const int* __restrict__ count, int64_t capacity, int spp, float inv_spp,
+    const float* __restrict__ adj, DGrads G) {
+  __shared__ uint16_t wl[kLdsW];
+  __shared__ GridLds gl;
+  __shared__ float rough_acc[kMaxRoughLds];
+  stage_weights(wl, W);
+  load_grid_tables(gl, net);
+  if (threadIdx.x < kMaxRoughLds) rough_acc[threadIdx.x] = 0.f;
+  __syncthreads();
+  const int64_t n = min((int64_t)*count, capacity);
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const TileRange tr = xcd_tiles((n + 15) / 16);
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+    const int64_t slot = tile * 16 + (lane & 15);
+    const bool valid = slot < n;
+    const int64_t qi = valid ? (int64_t)order[slot] : 0;
+    const float* rec = q + qi * NRC_REC;
+    float in[5][4];
+    encode_lane(net, gl, rec, valid, g, in);
+    Acts A;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) A.h0[s] = pack4(in[s][0], in[s][1], in[s][2], in[s][3]);
+    const f32x4 y = forward_tile(wl, A, lane);
+    f32x4 d = zero4();
+    if (g == 0 && valid) {
+      const float* a = adj + 3 * (size_t)(qsample[qi] / spp);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = y[c] > 0.f ? a[c] * inv_spp * rec[13 + c] : 0.f;
+    }
+    const bf16x4 dyb = g == 0 ? pack4(d[0], d[1], d[2], 0.f) : zero_b();
+    Deltas D;
+    backprop_deltas(wl, A, dyb, D, lane);
+    const f32x4 dx = input_grad_tile(wl, D, 4, lane);  // lane group 0: inputs 64..67
+    if (g == 0 && valid) {
+      const int texel = qref[2 * qi], ids = qref[2 * qi + 1];
+      const int tex = ids & 0xff, rslot = (ids >> 8) - 1;
+      if (texel >= 0 && G.tex[tex]) {
+        float* t = G.tex[tex] + 3 * (size_t)texel;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (dx[1 + c] != 0.f) atomicAdd(t + c, dx[1 + c]);
+      }
+      if (rslot >= 0 && G.rough && dx[0] != 0.f) {
+        if (rslot < kMaxRoughLds) atomicAdd(&rough_acc[rslot], dx[0]);
+        else atomicAdd(G.rough + rslot, dx[0]);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxRoughLds && G.rough && rough_acc[threadIdx.x] != 0.f)
+    atomicAdd(G.rough + threadIdx.x, rough_acc[threadIdx.x]);
 }
 
 // Phase 2: workgroup b takes record tiles [b T, (b+1) T) and writes its
@@ -814,6 +911,14 @@ hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, 
   // persistent: 4 workgroups per CU (LDS-limited), each wave loops over tiles
   hipLaunchKernelGGL(k_nrc_infer, dim3(grid_for(capacity, 1024)), dim3(kBlockN), 0, st, net, W, q,
                      qpix, order, count, capacity, inv_spp, image);
+  return hipGetLastError();
+}
+hipError_t launch_nrc_input_grad(const DNrcNet& net, const float* W, const float* q,
+                                 const int* qsample, const int* qref, const int* order,
+                                 const int* count, int64_t capacity, int spp, const float* adj,
+                                 const DGrads& g, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_input_grad, dim3(grid_for(capacity, 1024)), dim3(kBlockN), 0, st, net,
+                     W, q, qsample, qref, order, count, capacity, spp, 1.0f / (float)spp, adj, g);
   return hipGetLastError();
 }
 // workspace: operand chunks of every record tile | phase-2 partials |

@@ -293,6 +293,56 @@ def test_cached_adjoint_vs_oracle():
     assert d > 0.02
 
 
+def test_cached_adjoint_input_grad_vs_oracle():
+    """Cached adjoint with the derivative through the network's albedo and
+    roughness inputs against the oracle's, both in total and for the input
+    term alone (with minus without it, on the same streams)."""
+    drt, sc, cfg, W, grid, gs, tex, rough = _cached_adjoint_case()
+    orc = oracle.OracleScene(sc)
+    spp, seed = 4, 3
+    kw = dict(K=3, spp=spp, max_depth=6, rr_depth=3, seed=seed, emu=True)
+    _, amb = orc.render_cached(cfg, grid.astype(np.float32), W.astype(np.float64), ambiguity=True, **kw)
+    adj = np.random.default_rng(13).normal(size=(1, 64, 64, 3)).astype(np.float32)
+    adj = unambiguous_adjoint(orc, adj, amb)
+    args = (gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+            torch.from_numpy(grid.reshape(-1)).cuda(), torch.from_numpy(adj).cuda(), spp, 6, 3, seed)
+    gt, gr = drt.render_adjoint_cached(*args, flags=drt.FLAG_CACHE_INPUT_GRAD)
+    gt0, gr0 = drt.render_adjoint_cached(*args)
+    ok_args = (cfg, grid.astype(np.float32), W.astype(np.float64), adj.astype(np.float64))
+    (ot,), orough = orc.adjoint_cached(*ok_args, input_grad=True, **kw)
+    (ot0,), orough0 = orc.adjoint_cached(*ok_args, **kw)
+    check_grad(gt[0].cpu().numpy(), ot, "cached adjoint through inputs, texture")
+    check_grad(gr.cpu().numpy(), orough, "cached adjoint through inputs, roughness")
+    term = gt[0].cpu().numpy().astype(np.float64) - gt0[0].cpu().numpy()
+    oterm = ot - ot0
+    share = np.linalg.norm(oterm) / np.linalg.norm(ot)
+    r = rel(term, oterm)
+    rterm = float(gr.item() - gr0.item())
+    oterm_r = float(orough[0] - orough0[0])
+    print(f"input term: share of the texture gradient {share:.3g}, rel {r:.3g}; roughness "
+          f"{rterm:.6g} vs {oterm_r:.6g}", flush=True)
+    assert share > 0.02
+    assert r <= 2e-3
+    assert abs(oterm_r) > 0 and abs(rterm - oterm_r) <= 2e-3 * abs(oterm_r)
+
+
+def test_cached_adjoint_input_grad_without_input_weights():
+    """A network that ignores its albedo and roughness inputs: the flag
+    changes nothing beyond the float atomics' summation order."""
+    drt, sc, cfg, W, grid, gs, tex, rough = _cached_adjoint_case()
+    W = W.copy()
+    W[(np.arange(64)[:, None] * 80 + np.arange(64, 68)[None, :]).reshape(-1)] = 0.0
+    adj = torch.from_numpy(np.random.default_rng(14).normal(size=(1, 64, 64, 3)).astype(np.float32)).cuda()
+    args = (gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+            torch.from_numpy(grid.reshape(-1)).cuda(), adj, 4, 6, 3, 6)
+    gt, gr = drt.render_adjoint_cached(*args, flags=drt.FLAG_CACHE_INPUT_GRAD)
+    gt0, gr0 = drt.render_adjoint_cached(*args)
+    r = rel(gt[0].cpu().numpy(), gt0[0].cpu().numpy())
+    print("flag without input weights: rel", r, flush=True)
+    assert r <= 1e-5
+    assert abs(gr.item() - gr0.item()) <= 1e-5 * abs(gr0.item())
+
+
 def test_cached_adjoint_zero_network_equals_plain_depth3():
     """With a zero network the cached adjoint is the plain adjoint at max
     depth 3 on the same streams (GPU against GPU)."""
