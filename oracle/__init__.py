@@ -466,6 +466,29 @@ def _train_records(self, n_paths, K=3, cams=None, max_depth=6, rr_depth=3, flags
     return feat, tgt, valid.astype(bool), amb.astype(bool)
 
 
+def _train_records_self(self, n_paths, cfg, grid, W, K=5, cams=None, max_depth=6, rr_depth=3, flags=0,
+                        seed=7, emu=True, textures=None, roughness=None, threads=None):
+    """Self-training records of n_paths paths, K - 1 slots per path (slot
+    j (K-1) + k - 1 for vertex k): (features [n(K-1),13], targets [n(K-1),3],
+    valid [n(K-1)] bool, ambiguous [n] bool)."""
+    cams = self.sc.cameras if cams is None else cams
+    ca = cam_array(cams)
+    m = n_paths * (K - 1)
+    feat, tgt = np.zeros((m, 13)), np.zeros((m, 3))
+    valid = np.zeros(m, np.int32)
+    amb = np.zeros(n_paths, np.int32)
+    texs, tptr, rough = self._params(textures, roughness)
+    g = np.ascontiguousarray(grid, np.float32).reshape(-1)
+    Wv = np.ascontiguousarray(W, np.float64)
+    lib().oracle_train_records_self(_vp(self.h), tptr, _p(rough), _p(ca), _c_int(len(cams)),
+                                    _c_int(max_depth), _c_int(rr_depth), _c_u32(flags), _c_u64(seed),
+                                    _c_int(K), _p(nrc_cfg_array(cfg)), _p(g), _p(Wv),
+                                    _c_int(1 if emu else 0), _c_i64(n_paths),
+                                    _c_int(threads or n_threads_default()), _p(feat), _p(tgt),
+                                    _p(valid), _p(amb))
+    return feat, tgt, valid.astype(bool), amb.astype(bool)
+
+
 def _adjoint_cached(self, cfg, grid, W, adj, K=3, cams=None, spp=4, max_depth=6, rr_depth=3,
                     flags=0, seed=2, pixel_ids=None, emu=True, textures=None, roughness=None,
                     threads=None, input_grad=False):
@@ -499,3 +522,4 @@ def _adjoint_cached(self, cfg, grid, W, adj, K=3, cams=None, spp=4, max_depth=6,
 OracleScene.render_cached = _render_cached
 OracleScene.adjoint_cached = _adjoint_cached
 OracleScene.train_records = _train_records
+OracleScene.train_records_self = _train_records_self

@@ -811,6 +811,15 @@ struct CacheHook {
   RGB L_at;          // radiance collected up to and including its emission
   bool tex_in = false, rough_in = false;  // features 10..12 / 9 are parameters
   Key k_tex = 0, k_rough = 0;
+  // self-training (mode 0 only): every scattering vertex with index k < K
+  // before the record vertex, with its features, beta and the radiance
+  // collected up to and including its emission
+  struct Visit {
+    int k;
+    double feat[13];
+    RGB beta, L_at;
+  };
+  std::vector<Visit>* visits = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -888,16 +897,28 @@ static RGB trace_sample(const Scene& s, const Params& P, const Opts& opt, const 
     Frame fr = make_frame(n_g);
     V3 wi = fr.to_local(-d);
     ShadeCtx sc = fetch_shading(s, P, s.tri_mat[h.prim], u, v);
-    if (ch && !ch->has && k >= ch->K) {
+    // features of a vertex for the cache: position, direction back along the
+    // incoming ray, normal turned towards it, roughness, albedo
+    const int t = mat.type;
+    const bool ggx = t == BSDF_CONDUCTOR || t == BSDF_DIELECTRIC || t == BSDF_PLASTIC;
+    auto features = [&](double f[13]) {
       V3 w = -d;
       V3 nn = dot(n_g, w) >= 0 ? n_g : -n_g;
-      double f[13] = {p.x, p.y, p.z, w.x, w.y, w.z, nn.x, nn.y, nn.z, 1.0, 0, 0, 0};
-      int t = mat.type;
-      bool ggx = t == BSDF_CONDUCTOR || t == BSDF_DIELECTRIC || t == BSDF_PLASTIC;
-      if (ggx) f[9] = sc.sh.alpha;
       RGB alb = t == BSDF_CONDUCTOR ? mat.f0 : (t == BSDF_DIELECTRIC ? RGB(1, 1, 1) : sc.sh.albedo);
-      f[10] = alb[0]; f[11] = alb[1]; f[12] = alb[2];
-      std::memcpy(ch->feat, f, sizeof(f));
+      double v[13] = {p.x, p.y, p.z, w.x, w.y, w.z, nn.x, nn.y, nn.z, ggx ? sc.sh.alpha : 1.0,
+                      alb[0], alb[1], alb[2]};
+      std::memcpy(f, v, sizeof(v));
+    };
+    if (ch && ch->visits && !ch->has && k < ch->K) {
+      CacheHook::Visit vis;
+      vis.k = k;
+      features(vis.feat);
+      vis.beta = beta;
+      vis.L_at = L;
+      ch->visits->push_back(vis);
+    }
+    if (ch && !ch->has && k >= ch->K) {
+      features(ch->feat);
       ch->tex_in = sc.has_tex && t != BSDF_CONDUCTOR && t != BSDF_DIELECTRIC;
       ch->k_tex = sc.k_tex;
       ch->rough_in = sc.has_rough && ggx;
@@ -1960,6 +1981,71 @@ void oracle_train_records(void* h, const float* const* textures, const float* ro
       if (beta_out) beta_out[3 * j + c] = ch.has ? b : 0.0;
       if (lat_out) lat_out[3 * j + c] = ch.has ? ch.L_at[c] : L[c];
       if (ltot_out) ltot_out[3 * j + c] = L[c];
+    }
+  });
+}
+
+// Self-training records: path j (key = seed, g = j, pixel as in
+// oracle_train_records) runs the cached estimator with record vertex K (the
+// first scattering vertex with index >= K, max_depth as given), so its
+// radiance beyond that vertex is the cache's own answer there.  Every
+// scattering vertex v_k with k < K on the way gives record j (K - 1) + k - 1:
+// its features and target = (L_end - L_k) / beta_k (0 for channels with
+// beta_k = 0), with L_end the path's cached estimate (radiance up to the record
+// vertex plus beta max(C, 0) there) and L_k the radiance collected up to and
+// including v_k's emission -- the radiance scattered from v_k.  valid marks
+// the records written; ambiguous[j] as in oracle_train_records.
+void oracle_train_records_self(void* h, const float* const* textures, const float* roughness,
+                               const double* cams, int n_cams, int max_depth, int rr_depth,
+                               uint32_t flags, uint64_t seed, int K, const double* cfg,
+                               const float* grid, const double* W, int emu, int64_t n_paths,
+                               int n_threads, double* feat, double* target, int* valid,
+                               int* ambiguous) {
+  const Scene& s = *(Scene*)h;
+  Params P{textures, roughness};
+  Opts opt{1, max_depth, rr_depth, flags, seed};
+  GridCfg g = grid_cfg(cfg);
+  std::vector<Cam> cs;
+  for (int c = 0; c < n_cams; ++c) cs.push_back(make_cam(cams + 12 * c));
+  const int Wd = cs[0].W, Ht = cs[0].H;
+  const uint32_t n_pix = (uint32_t)((int64_t)n_cams * Wd * Ht);
+  const int R = K - 1;  // records per path
+  parallel_for(n_paths, n_threads, [&](int, int64_t j) {
+    Stream st = make_stream(seed, (uint64_t)j);
+    uint32_t r[4];
+    st.block(kCameraBlock, 2, r);
+    uint32_t pid = pick(r[0], n_pix);
+    int cam = (int)(pid / ((uint32_t)Wd * Ht));
+    int y = (int)((pid / Wd) % Ht), x = (int)(pid % Wd);
+    V3 o, d;
+    bool amb = false;
+    t_amb = ambiguous ? &amb : nullptr;
+    camera_ray(cs[cam], st, x, y, &o, &d);
+    std::vector<CacheHook::Visit> visits;
+    CacheHook ch;
+    ch.K = K;
+    ch.mode = 0;
+    ch.visits = &visits;
+    RGB L = trace_sample(s, P, opt, st, o, d, nullptr, nullptr, &ch);
+    t_amb = nullptr;
+    if (ch.has) {
+      double enc[80], yv[3];
+      encode(g, grid, ch.feat, enc);
+      mlp_forward(W, enc, emu != 0, nullptr, yv);
+      for (int c = 0; c < 3; ++c) L[c] += ch.beta[c] * std::max(yv[c], 0.0);
+    }
+    if (ambiguous) ambiguous[j] = amb ? 1 : 0;
+    for (int i = 0; i < R; ++i) {
+      valid[j * R + i] = 0;
+      for (int c = 0; c < 13; ++c) feat[13 * (j * R + i) + c] = 0.0;
+      for (int c = 0; c < 3; ++c) target[3 * (j * R + i) + c] = 0.0;
+    }
+    for (const auto& v : visits) {
+      const int64_t slot = j * R + (v.k - 1);
+      valid[slot] = 1;
+      for (int c = 0; c < 13; ++c) feat[13 * slot + c] = v.feat[c];
+      for (int c = 0; c < 3; ++c)
+        target[3 * slot + c] = v.beta[c] != 0 ? (L[c] - v.L_at[c]) / v.beta[c] : 0.0;
     }
   });
 }

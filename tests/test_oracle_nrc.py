@@ -391,3 +391,49 @@ def test_cached_adjoint_input_term_vanishes_without_input_weights():
     (g0,), gr0 = orc.adjoint_cached(cfg, grid, W, adj, **kw)
     np.testing.assert_array_equal(g, g0)
     np.testing.assert_array_equal(gr, gr0)
+
+
+def test_self_training_records_without_tail_equal_single_vertex_records():
+    """Zero network and max depth = K (so no vertex is ever handed to the
+    cache): the self-training record of vertex k is the single-vertex
+    training record with record vertex k, path for path (the Cornell scene
+    has no pass-through surfaces, so vertex k is the k-th scattering one)."""
+    sc = scenes.cornell(texture=scenes.random_texture(16), width=16, height=16, conductor=True)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    orc = oracle.OracleScene(sc)
+    n, K = 2048, 6
+    f, t, v, _ = orc.train_records_self(n, cfg, grid, np.zeros(oracle.mlp_num_weights()), K=K,
+                                        max_depth=6, rr_depth=3, seed=21)
+    f, t, v = f.reshape(n, K - 1, 13), t.reshape(n, K - 1, 3), v.reshape(n, K - 1)
+    for k in range(1, K):
+        f1, t1, v1, _ = orc.train_records(n, K=k, max_depth=6, rr_depth=3, seed=21)
+        np.testing.assert_array_equal(v[:, k - 1], v1)
+        np.testing.assert_array_equal(f[:, k - 1], f1)
+        np.testing.assert_array_equal(t[:, k - 1], t1)
+        assert v1.sum() > n // 16, (k, v1.sum())
+
+
+def test_self_training_tail_is_the_cache_answer_at_vertex_K():
+    """With a constant network c Y_00 the targets move by exactly
+    beta_K / beta_k * c Y_00 when the path reaches a scattering vertex K (the
+    throughputs from the single-vertex records), and not at all otherwise."""
+    sc = scenes.cornell(texture=scenes.random_texture(16), width=16, height=16, conductor=True)
+    cfg = scenes.nrc_config(sc)
+    _, grid = scenes.nrc_init(cfg)
+    orc = oracle.OracleScene(sc)
+    n, K, D = 2048, 4, 5
+    c = np.array([1.5, 1.0, 0.5]) * 0.5 / math.sqrt(math.pi)
+    kw = dict(K=K, max_depth=D, rr_depth=3, seed=23, emu=False)
+    _, t0, v0, _ = orc.train_records_self(n, cfg, grid, np.zeros(oracle.mlp_num_weights()), **kw)
+    _, tc, vc, _ = orc.train_records_self(n, cfg, grid, _constant_network(), **kw)
+    np.testing.assert_array_equal(v0, vc)
+    t0, tc, v0 = t0.reshape(n, K - 1, 3), tc.reshape(n, K - 1, 3), v0.reshape(n, K - 1)
+    _, _, vK, _, bK, _, _ = orc.train_records(n, K=K, max_depth=D, rr_depth=3, seed=23, extra=True)
+    assert 0 < vK.sum() < n
+    for k in range(1, K):
+        _, _, vk, _, bk, _, _ = orc.train_records(n, K=k, max_depth=D, rr_depth=3, seed=23, extra=True)
+        np.testing.assert_array_equal(vk, v0[:, k - 1])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            want = np.where(vK[:, None] & vk[:, None] & (bk != 0), bK / bk * c, 0.0)
+        np.testing.assert_allclose(tc[:, k - 1] - t0[:, k - 1], want, rtol=1e-12, atol=1e-12)
