@@ -313,7 +313,9 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
     reference's own variance (V_plain / ref_spp).  The plain spp needed to
     reach the cache's RMSE is V_plain / RMSE_cache^2, and its time is that
     times the measured plain time per spp.  Training (65,536 paths a frame)
-    is reported per frame beside it."""
+    is reported per frame beside it.  A second cache is trained for the same
+    number of frames by self-training (16,384 paths a frame closed by the
+    cache at v5, records at v1..v4) and measured the same way."""
     sc = scenes.cornell(texture=scenes.random_texture(64), width=R, height=R)
     cfg = scenes.nrc_config(sc)
     W0, grid0 = scenes.nrc_init(cfg, seed=16)
@@ -331,16 +333,20 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
         ref += img.double()
     ref /= ref_spp // chunk
 
-    cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
-    cache.train_frame(gs, tex, None, cams, seed=500)            # warm-up
-    e0, e1 = ev(), ev()
-    torch.cuda.synchronize()
-    e0.record()
-    for f in range(frames):
-        cache.train_frame(gs, tex, None, cams, seed=1000 + f)
-    e1.record()
-    torch.cuda.synchronize()
-    train_ms = e0.elapsed_time(e1) / frames
+    def trained(**kw):
+        c = drt.NrcCache(cfg, W0, grid0, lr=1e-2, **kw)
+        c.train_frame(gs, tex, None, cams, seed=500)            # warm-up
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        for f in range(frames):
+            c.train_frame(gs, tex, None, cams, seed=1000 + f)
+        e1.record()
+        torch.cuda.synchronize()
+        return c, e0.elapsed_time(e1) / frames
+
+    cache, train_ms = trained(n_paths=65536)
+    cache_self, train_self_ms = trained(n_paths=16384, self_training=5)
 
     work = drt.cached_work(R * R * max(spps), "cuda")
 
@@ -363,20 +369,36 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
         m_plain = mse(img)
         cache_ms = timed(lambda: cache.render(gs, tex, None, cams, s, seed=7, out=img, work=work))
         m_cache = mse(img)
+        self_ms = timed(lambda: cache_self.render(gs, tex, None, cams, s, seed=7, out=img, work=work))
+        m_self = mse(img)
         v_plain = m_plain / (1.0 / s + 1.0 / ref_spp)            # per-sample variance of plain
-        m_cache_c = max(m_cache - v_plain / ref_spp, 1e-30)        # cache MSE minus reference noise
-        spp_eq = v_plain / m_cache_c
-        plain_eq_ms = spp_eq * plain_ms / s
+
+        def equal(m, ms, tms):
+            m_c = max(m - v_plain / ref_spp, 1e-30)                # cache MSE minus reference noise
+            spp_eq = v_plain / m_c
+            plain_eq_ms = spp_eq * plain_ms / s
+            return spp_eq, plain_eq_ms / ms, plain_eq_ms / (ms + tms)
+
+        spp_eq, sp, sp_t = equal(m_cache, cache_ms, train_ms)
+        spp_eq_s, sp_s, sp_t_s = equal(m_self, self_ms, train_self_ms)
         rows.append({"spp": s, "plain_ms": round(plain_ms, 3), "cache_ms": round(cache_ms, 3),
                      "rmse_plain": round(m_plain ** 0.5, 6), "rmse_cache": round(m_cache ** 0.5, 6),
                      "plain_spp_at_equal_rmse": round(spp_eq, 3),
-                     "speedup_at_equal_rmse": round(plain_eq_ms / cache_ms, 3),
-                     "speedup_incl_training": round(plain_eq_ms / (cache_ms + train_ms), 3)})
+                     "speedup_at_equal_rmse": round(sp, 3),
+                     "speedup_incl_training": round(sp_t, 3),
+                     "self_training": {"rmse_cache": round(m_self ** 0.5, 6),
+                                       "plain_spp_at_equal_rmse": round(spp_eq_s, 3),
+                                       "speedup_at_equal_rmse": round(sp_s, 3),
+                                       "speedup_incl_training": round(sp_t_s, 3)}})
     return {"workload": f"cornell-box, random 64^2 texture, {R}^2, D6 RR3, cache at v3, "
                         f"hash grid 16x2^19x2 fp16, 80-64x4-3 bf16 network",
             "reference_spp": ref_spp, "train_frames": frames, "train_paths_per_frame": 65536,
             "train_ms_per_frame": round(train_ms, 3),
-            "final_train_loss": round(float(cache.loss.item()), 4), "by_spp": rows}
+            "final_train_loss": round(float(cache.loss.item()), 4),
+            "self_training": {"paths_per_frame": 16384, "tail_vertex": 5,
+                              "train_ms_per_frame": round(train_self_ms, 3),
+                              "final_train_loss": round(float(cache_self.loss.item()), 4)},
+            "by_spp": rows}
 
 
 def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps=3):

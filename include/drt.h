@@ -379,6 +379,34 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
                          int64_t n, void* workspace, int64_t workspace_bytes, float* dW,
                          float* dgrid, float* loss, void* hip_stream);
 
+/* Self-training records of the radiance cache (the cache's answer closes
+ * each training path, so the records see radiance beyond any fixed depth).
+ * n_paths paths, path j starting at the pixel chosen as in drt_nrc_collect,
+ * run the cached estimator with record vertex tail_vertex (first scattering
+ * vertex with index >= tail_vertex, before opts->max_depth; opts->spp is
+ * ignored): the radiance up to that vertex plus beta * max(C, 0) there, C
+ * answered by the network (weights, grid as in drt_render_forward_cached).
+ * Every scattering vertex k < tail_vertex on the way writes record
+ * j * (tail_vertex - 1) + k - 1 of records [n_paths * (tail_vertex - 1)][16]:
+ * features (as in drt_nrc_collect) and target = (path estimate - radiance
+ * collected up to and including vertex k's emission) / beta_k per channel
+ * (0 where beta_k is 0) -- the radiance scattered from vertex k.  valid
+ * [n_paths * (tail_vertex - 1)]: 1 for the records written (others are
+ * zeroed); *count = their number.  The result feeds drt_nrc_train with
+ * n = n_paths * (tail_vertex - 1).  workspace: device scratch of at least
+ * drt_nrc_collect_self_workspace_bytes(n_paths, tail_vertex) bytes.
+ * 2 <= tail_vertex <= 32; n_paths <= INT32_MAX and
+ * n_paths * (tail_vertex - 1) <= 2^31.  The paper does not study caches; this
+ * is the self-training of Mueller et al. (2021) written on the cached
+ * estimator. */
+int64_t drt_nrc_collect_self_workspace_bytes(int64_t n_paths, int32_t tail_vertex);
+drt_status drt_nrc_collect_self(const drt_scene* scene, const drt_params* params,
+                                const drt_camera* cams, int32_t n_cams,
+                                const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                const float* weights, const uint16_t* grid, int32_t tail_vertex,
+                                int64_t n_paths, float* records, int32_t* valid, int32_t* count,
+                                void* workspace, int64_t workspace_bytes, void* hip_stream);
+
 /* Entries of the int32 query scratch of the cached calls for `capacity`
  * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
  * parameter references [capacity][2] | bin histogram [4096]. */

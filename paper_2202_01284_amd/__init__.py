@@ -138,6 +138,11 @@ _SIGS = {
     "drt_nrc_collect": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                  ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_nrc_config),
                                  _c_i64, _vp, _vp, _vp, _vp]),
+    "drt_nrc_collect_self_workspace_bytes": (_c_i64, [_c_i64, _c_i32]),
+    "drt_nrc_collect_self": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                      _c_i32, ctypes.POINTER(drt_render_opts),
+                                      ctypes.POINTER(drt_nrc_config), _vp, _vp, _c_i32, _c_i64, _vp,
+                                      _vp, _vp, _vp, _c_i64, _vp]),
     "drt_nrc_train_workspace_bytes": (_c_i64, [_c_i64]),
     "drt_nrc_train": (_c_i32, [ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp, _c_i64, _vp,
                                _c_i64, _vp, _vp, _vp, _vp]),
@@ -714,6 +719,37 @@ def nrc_collect(scene: Scene, textures, roughness, cams, cfg: dict, n_paths: int
     return rec, valid, count
 
 
+def nrc_collect_self(scene: Scene, textures, roughness, cams, cfg: dict, weights, grid, n_paths: int,
+                     seed: int, tail_vertex: int = 5, max_depth: int = 6, rr_depth: int = 3,
+                     flags: int = 0, out=None, workspace=None, stream=None):
+    """Self-training records: n_paths paths closed by the cache's answer at
+    vertex tail_vertex, one record slot per vertex before it.  Returns
+    (records [n (tail_vertex-1), 16], valid [n (tail_vertex-1)] int32, count [1])."""
+    torch = _torch()
+    dev = scene.buffer.device
+    m = n_paths * (tail_vertex - 1)
+    if out is None:
+        out = (torch.empty((m, NRC_RECORD), dtype=torch.float32, device=dev),
+               torch.empty(m, dtype=torch.int32, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    rec, valid, count = out
+    if rec.shape[0] < m or valid.numel() < m:
+        raise ValueError(f"record buffers hold fewer than {m} records")
+    need = int(lib.drt_nrc_collect_self_workspace_bytes(n_paths, tail_vertex))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(1, max_depth, rr_depth, seed, flags, None)
+    c = nrc_config(cfg)
+    _check(lib.drt_nrc_collect_self(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                    ctypes.byref(c), weights.data_ptr(), grid.data_ptr(),
+                                    tail_vertex, n_paths, rec.data_ptr(), valid.data_ptr(),
+                                    count.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                    _stream(stream)), "drt_nrc_collect_self")
+    return rec, valid, count
+
+
 def nrc_train_workspace(n: int, device="cuda"):
     torch = _torch()
     return torch.empty(int(lib.drt_nrc_train_workspace_bytes(n)), dtype=torch.uint8, device=device)
@@ -832,10 +868,13 @@ class NrcCache:
     """Radiance-cache state on the device: FP32 master weights and hash-grid
     features (with an FP16 copy of the grid for the kernels), Adam moments,
     gradient buffers, and the per-frame training loop
-    (collect -> train -> Adam on the network -> Adam on the grid)."""
+    (collect -> train -> Adam on the network -> Adam on the grid).
+    self_training = 0: one record per path at the cache's truncation vertex
+    from plain paths; self_training = K >= 2: self-training records at every
+    vertex before K of paths closed by the cache's answer at K."""
 
     def __init__(self, cfg: dict, weights0, grid0, n_paths: int = 65536, lr: float = 1e-2,
-                 device: str = "cuda"):
+                 device: str = "cuda", self_training: int = 0):
         torch = _torch()
         self.cfg = dict(cfg)
         self.W = torch.as_tensor(np.asarray(weights0, np.float32)).to(device).contiguous()
@@ -850,20 +889,34 @@ class NrcCache:
         self.step = 0
         self.buf = None
         self.ws = None
+        self.self_training = int(self_training)
+        if self.self_training == 1 or self.self_training < 0:
+            raise ValueError("self_training is 0 or a tail vertex >= 2")
+        self.ws_self = None
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
 
     def train_frame(self, scene: Scene, textures, roughness, cams, seed: int, max_depth: int = 6,
                     rr_depth: int = 3):
         torch = _torch()
+        tail = self.self_training
+        m = self.n_paths * (tail - 1 if tail else 1)
+        dev = self.W.device
         if self.buf is None:
-            dev = self.W.device
-            self.buf = (torch.empty((self.n_paths, NRC_RECORD), dtype=torch.float32, device=dev),
-                        torch.empty(self.n_paths, dtype=torch.int32, device=dev),
+            self.buf = (torch.empty((m, NRC_RECORD), dtype=torch.float32, device=dev),
+                        torch.empty(m, dtype=torch.int32, device=dev),
                         torch.empty(1, dtype=torch.int32, device=dev))
-        rec, valid, count = nrc_collect(scene, textures, roughness, cams, self.cfg, self.n_paths,
-                                        seed, max_depth, rr_depth, out=self.buf)
+        if tail:
+            if self.ws_self is None:
+                self.ws_self = torch.empty(int(lib.drt_nrc_collect_self_workspace_bytes(self.n_paths, tail)),
+                                           dtype=torch.uint8, device=dev)
+            rec, valid, count = nrc_collect_self(scene, textures, roughness, cams, self.cfg, self.W,
+                                                 self.grid16, self.n_paths, seed, tail, max_depth,
+                                                 rr_depth, out=self.buf, workspace=self.ws_self)
+        else:
+            rec, valid, count = nrc_collect(scene, textures, roughness, cams, self.cfg, self.n_paths,
+                                            seed, max_depth, rr_depth, out=self.buf)
         if self.ws is None:
-            self.ws = nrc_train_workspace(self.n_paths, self.W.device)
+            self.ws = nrc_train_workspace(m, dev)
         nrc_train(self.cfg, self.W, self.grid16, rec, valid, count, self.dW, self.dG, self.loss,
                   workspace=self.ws)
         self.step += 1

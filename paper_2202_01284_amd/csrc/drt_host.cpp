@@ -946,6 +946,76 @@ drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
   return ok();
 }
 
+// Workspace of drt_nrc_collect_self, 256-byte aligned parts: tail queries
+// [n][16] | query ints | query count | path estimates [n][3] | record
+// throughputs [n (K - 1)][3].
+static int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+struct SelfWs {
+  int64_t q, ints, qcount, lpath, tbeta, total;
+};
+static SelfWs self_ws(int64_t n, int K) {
+  SelfWs w;
+  w.q = 0;
+  w.ints = w.q + align256(n * NRC_REC * 4);
+  w.qcount = w.ints + align256(drt_nrc_query_ints(n) * 4);
+  w.lpath = w.qcount + 256;
+  w.tbeta = w.lpath + align256(n * 3 * 4);
+  w.total = w.tbeta + align256(n * (K - 1) * 3 * 4);
+  return w;
+}
+
+int64_t drt_nrc_collect_self_workspace_bytes(int64_t n_paths, int32_t tail_vertex) {
+  if (n_paths < 0 || tail_vertex < 2 || tail_vertex > 32) return 0;
+  return self_ws(n_paths, tail_vertex).total;
+}
+
+drt_status drt_nrc_collect_self(const drt_scene* scene, const drt_params* params,
+                                const drt_camera* cams, int32_t n_cams,
+                                const drt_render_opts* opts, const drt_nrc_config* cfg,
+                                const float* weights, const uint16_t* grid, int32_t tail_vertex,
+                                int64_t n_paths, float* records, int32_t* valid, int32_t* count,
+                                void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  DNrcNet net;
+  st = nrc_net(cfg, grid, &net);
+  if (st != DRT_OK) return st;
+  if (tail_vertex < 2 || tail_vertex > 32) return fail(DRT_EINVAL, "tail_vertex must be in [2, 32]");
+  if (n_paths < 0 || n_paths > INT32_MAX || n_paths * (tail_vertex - 1) > ((int64_t)1 << 31))
+    return fail(DRT_EINVAL, "n_paths out of range");
+  if (!weights || !grid || !count) return fail(DRT_EINVAL, "null pointer argument");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e = launch_zero(count, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  if (n_paths == 0) return ok();
+  if (!records || !valid) return fail(DRT_EINVAL, "records and valid are required");
+  const SelfWs w = self_ws(n_paths, tail_vertex);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(DRT_EINVAL, "workspace smaller than drt_nrc_collect_self_workspace_bytes");
+  char* base = static_cast<char*>(workspace);
+  int32_t* qcount = reinterpret_cast<int32_t*>(base + w.qcount);
+  DNrcIO io = query_io(net, cfg, reinterpret_cast<float*>(base + w.q),
+                       reinterpret_cast<int32_t*>(base + w.ints), qcount, n_paths);
+  io.K = tail_vertex;
+  io.lsamp = reinterpret_cast<float*>(base + w.lpath);
+  io.trec = records;
+  io.tbeta = reinterpret_cast<float*>(base + w.tbeta);
+  io.valid = valid;
+  io.rcount = count;
+  e = launch_zero(qcount, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  e = launch_nrc_records_self(scene->dev, dp, dc, dr, n_paths, io, stream);
+  if (e != hipSuccess) return hip_fail(e, "self-training paths launch");
+  e = answer_queries(net, weights, io, n_paths, 1.0f, io.lsamp, stream);
+  if (e != hipSuccess) return hip_fail(e, "cache query launch");
+  e = launch_nrc_self_targets(io, n_paths, stream);
+  if (e != hipSuccess) return hip_fail(e, "self-training targets launch");
+  return ok();
+}
+
 int64_t drt_nrc_train_workspace_bytes(int64_t n) { return n < 0 ? 0 : nrc_train_workspace_bytes(n); }
 
 drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,

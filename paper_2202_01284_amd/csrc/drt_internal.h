@@ -141,7 +141,10 @@ struct DNrcIO {
   float* lsamp;     // per-sample radiance [n_samples][3] (cached adjoint), else null
   uint32_t* qbin;   // queries: spatial bin of each query (null: not binned)
   int* qref;        // queries: [2] per query, the parameters its inputs were read
-                    // from (QueryRef), or null (not recorded)
+                    // from (query_ref_put), or null (not recorded)
+  float* trec;      // self-training: records [n_paths * (K - 1)][NRC_REC]
+  float* tbeta;     // self-training: throughput at each record [n_paths * (K - 1)][3]
+  int* rcount;      // self-training: records written
   float lo[3], inv_ext[3];  // scene box of the cache (query binning)
 };
 
@@ -178,6 +181,12 @@ hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& 
                                 hipStream_t st);
 hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                               int64_t n_paths, const DNrcIO& io, hipStream_t st);
+// Self-training paths (render_pixel<MODE_TRAIN_SELF>), then, once the
+// queries are answered into io.lsamp, the records' targets.
+hipError_t launch_nrc_records_self(const DScene& s, const DParams& p, const DCams& c,
+                                   const DRender& r, int64_t n_paths, const DNrcIO& io,
+                                   hipStream_t st);
+hipError_t launch_nrc_self_targets(const DNrcIO& io, int64_t n_paths, hipStream_t st);
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st);

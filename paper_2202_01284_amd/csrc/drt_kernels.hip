@@ -56,6 +56,11 @@ namespace drt {
 // textures in tab.gtex, tangent roughness in sink.rough_global): the tangents
 // of beta and L ride along the path; `out` receives the sum of the sample
 // radiance tangents.  Attached and detached terms as in the replay.
+// MODE_TRAIN_SELF: self-training path g: as MODE_CACHED_SAMPLES (radiance up
+// to the record vertex to io.lsamp[g], query there with id g), and every
+// scattering vertex k < K before it writes record g (K - 1) + k - 1 of
+// io.trec (features, and for now the radiance collected so far in 13..15)
+// and its throughput to io.tbeta; io.valid marks the records written.
 // Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
 // ---------------------------------------------------------------------------
 enum {
@@ -65,7 +70,8 @@ enum {
   MODE_TRAIN = 3,
   MODE_CACHED_SAMPLES = 4,
   MODE_ADJOINT_CACHED = 5,
-  MODE_JVP = 6
+  MODE_JVP = 6,
+  MODE_TRAIN_SELF = 7
 };
 
 template <int MODE>
@@ -77,8 +83,9 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   constexpr bool JVP = MODE == MODE_JVP;
   // modes with a record vertex (cache queries, training records, cached replay)
   constexpr bool HOOK = MODE == MODE_CACHED || MODE == MODE_TRAIN || MODE == MODE_CACHED_SAMPLES ||
-                        MODE == MODE_ADJOINT_CACHED;
-  constexpr bool QUERY = MODE == MODE_CACHED || MODE == MODE_CACHED_SAMPLES;
+                        MODE == MODE_ADJOINT_CACHED || MODE == MODE_TRAIN_SELF;
+  constexpr bool QUERY = MODE == MODE_CACHED || MODE == MODE_CACHED_SAMPLES || MODE == MODE_TRAIN_SELF;
+  constexpr bool SELF = MODE == MODE_TRAIN_SELF;
   const int W = C.width, H = C.height;
   const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
   const int n_em = s.n_ems;
@@ -95,6 +102,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   // record vertex (MODE_TRAIN)
   bool recorded = false;
   f3 beta_at = mk(0, 0, 0), L_at = mk(0, 0, 0);
+  uint32_t self_mask = 0;  // records written by this path (MODE_TRAIN_SELF)
 
   auto start = [&]() {
     uint64_t g = g_base + (uint64_t)sidx;
@@ -109,6 +117,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     prev_p = o;
     k = 1;
     recorded = false;
+    self_mask = 0;
     cnt.samples++;
   };
 
@@ -214,7 +223,8 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
               if (vrslot >= 0 && sink.rough_global) vr = sink.rough_global[vrslot];
             }
             bool stop_here = false;
-            if (HOOK && !recorded && k >= io.K) {
+            const bool at_hook = HOOK && !recorded && k >= io.K;
+            if (at_hook || (SELF && k < io.K)) {
               // features of the record vertex: position, direction back along
               // the ray, normal facing it, roughness (1 unless microfacet),
               // albedo (f0 for a conductor, 1 for a dielectric)
@@ -225,11 +235,21 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
               f3 alb = type == DRT_BSDF_CONDUCTOR ? sh.f0
                        : (type == DRT_BSDF_DIELECTRIC ? mk(1, 1, 1) : sh.albedo);
               float* rec = nullptr;
-              if (QUERY) {
+              if (SELF && !at_hook) {
+                const size_t r = (size_t)g_base * (io.K - 1) + (k - 1);
+                rec = io.trec + (size_t)NRC_REC * r;
+                rec[13] = L.x;
+                rec[14] = L.y;
+                rec[15] = L.z;
+                io.tbeta[3 * r] = beta.x;
+                io.tbeta[3 * r + 1] = beta.y;
+                io.tbeta[3 * r + 2] = beta.z;
+                self_mask |= 1u << (k - 1);
+              } else if (QUERY) {
                 int slot = atomicAdd(io.count, 1);
                 if (slot < io.capacity) {
                   rec = io.rec + (size_t)NRC_REC * slot;
-                  io.qpix[slot] = MODE == MODE_CACHED_SAMPLES ? (int)glo : (int)pix;
+                  io.qpix[slot] = MODE == MODE_CACHED ? (int)pix : (int)glo;
                   if (io.qbin) io.qbin[slot] = query_bin(p.x, p.y, p.z, io.lo, io.inv_ext);
                   if (io.qref) {
                     const bool tex_in = vtex >= 0 && type != DRT_BSDF_CONDUCTOR &&
@@ -247,7 +267,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                 beta_at = beta;
                 L_at = L;
               }
-              if (MODE != MODE_TRAIN) {
+              if (MODE != MODE_TRAIN && at_hook) {
                 stop_here = true;
                 done = true;
               }
@@ -431,11 +451,16 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z))));
     } else if (JVP) {
       acc = acc + tL;
-    } else if (MODE == MODE_CACHED_SAMPLES) {
+    } else if (MODE == MODE_CACHED_SAMPLES || SELF) {
       float* ls = io.lsamp + 3 * (g_base + (uint64_t)sidx);
       ls[0] = L.x;
       ls[1] = L.y;
       ls[2] = L.z;
+      if (SELF) {
+        int* v = io.valid + (size_t)g_base * (io.K - 1);
+        for (int i = 0; i < io.K - 1; ++i) v[i] = (self_mask >> i) & 1u;
+        if (self_mask) atomicAdd(io.rcount, __popc(self_mask));
+      }
     } else {
       acc = acc + L;
     }
@@ -584,6 +609,45 @@ __global__ __launch_bounds__(kBlock) void k_nrc_records(DScene s, DParams P, DCa
                            stack + threadIdx.x, cnt, none, io, unused);
 }
 
+// Self-training paths: path j as in k_nrc_records, written by
+// render_pixel<MODE_TRAIN_SELF>.
+__global__ __launch_bounds__(kBlock) void k_nrc_records_self(DScene s, DParams P, DCams C, DRender R,
+                                                             int64_t n_paths, DNrcIO io) {
+  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ LdsTables tab;
+  load_tables(tab, s, P, nullptr);
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_paths) return;
+  const uint32_t n_pix = (uint32_t)((int64_t)C.n * C.width * C.height);
+  uint4 r = philox((uint32_t)j, (uint32_t)((uint64_t)j >> 32), 0xFFFFFFFFu, 2u, R.key0, R.key1);
+  const uint32_t pid = pick(r.x, n_pix);
+  const int cam = (int)(pid / ((uint32_t)C.width * C.height));
+  const int y = (int)((pid / C.width) % C.height), x = (int)(pid % C.width);
+  Counters cnt = {};
+  Sink none{&tab, nullptr, nullptr};
+  f3 unused;
+  render_pixel<MODE_TRAIN_SELF>(s, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
+                                stack + threadIdx.x, cnt, none, io, unused);
+}
+
+// Targets of the self-training records: (path estimate - radiance before the
+// record's scattering) / throughput, per channel (0 where beta is 0); the path
+// estimate in io.lsamp already holds the cache's answer at the path's end.
+__global__ __launch_bounds__(256) void k_nrc_self_targets(DNrcIO io, int64_t n_paths) {
+  const int R = io.K - 1;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_paths * R) return;
+  float* rec = io.trec + (size_t)NRC_REC * i;
+  if (!io.valid[i]) {
+    for (int c = 0; c < NRC_REC; ++c) rec[c] = 0.f;
+    return;
+  }
+  const float* L = io.lsamp + 3 * (size_t)(i / R);
+  const float* b = io.tbeta + 3 * (size_t)i;
+  for (int c = 0; c < 3; ++c) rec[13 + c] = b[c] != 0.f ? (L[c] - rec[13 + c]) / b[c] : 0.f;
+}
+
 // Ray queries (closest / any) for tests and traversal measurements.
 __global__ __launch_bounds__(kBlock) void k_trace(DScene s, const float* __restrict__ rays,
                                                   int64_t n, int mode, drt_hit* __restrict__ out) {
@@ -720,6 +784,23 @@ hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c,
   int64_t blocks = (n_paths + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_nrc_records, dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c, r,
                      n_paths, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_nrc_records_self(const DScene& s, const DParams& p, const DCams& c,
+                                   const DRender& r, int64_t n_paths, const DNrcIO& io,
+                                   hipStream_t st) {
+  int64_t blocks = (n_paths + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_nrc_records_self, dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c, r,
+                     n_paths, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_nrc_self_targets(const DNrcIO& io, int64_t n_paths, hipStream_t st) {
+  const int64_t n = n_paths * (io.K - 1);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nrc_self_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, io,
+                     n_paths);
   return hipGetLastError();
 }
 

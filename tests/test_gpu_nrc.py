@@ -150,6 +150,41 @@ def test_collect_vs_oracle():
     assert good.mean() >= 0.999
 
 
+def test_collect_self_vs_oracle():
+    """Self-training records (paths closed by the cache at vertex 4, a
+    record at each vertex before it) against the oracle with the BF16
+    network: validity and features as for plain records; targets within the
+    network's tolerance on the cache tail."""
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64))
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    W = W.copy()
+    W[17408:] = np.abs(W[17408:]) * 4.0      # a tail comparable to the radiance before it
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    rough = torch.from_numpy(sc.roughness).cuda()
+    n, K = 8192, 4
+    rec, valid, count = drt.nrc_collect_self(gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+                                             torch.from_numpy(grid.reshape(-1)).cuda(), n, seed=33,
+                                             tail_vertex=K, max_depth=6, rr_depth=3)
+    rec, valid, count = rec.cpu().numpy(), valid.cpu().numpy().astype(bool), int(count.item())
+    feat, tgt, vo, amb = oracle.OracleScene(sc).train_records_self(
+        n, cfg, grid.astype(np.float32), W.astype(np.float64), K=K, max_depth=6, rr_depth=3, seed=33,
+        emu=True)
+    ok = np.repeat(~amb, K - 1)
+    print("records valid", valid.sum(), "of", n * (K - 1), "ambiguous paths", amb.sum(), flush=True)
+    assert count == valid.sum()
+    np.testing.assert_array_equal(valid[ok], vo[ok])
+    assert np.all(rec[~valid] == 0)
+    m = ok & vo
+    np.testing.assert_allclose(rec[m, :13], feat[m], rtol=1e-3, atol=1e-4)
+    err = np.abs(rec[m, 13:16] - tgt[m])
+    good = (err <= 2e-3 * np.abs(tgt[m]) + 1e-4).all(1)
+    print("target pass", good.mean(), flush=True)
+    assert good.mean() >= 0.999
+
+
 def test_training_pass_vs_oracle():
     """Loss, network gradient and hash-grid gradient of one fused training pass
     on oracle-made records.  The network is scaled so its outputs sit near the
@@ -391,6 +426,36 @@ def test_trained_cache_beats_untrained():
           flush=True)
     assert np.mean(losses[-10:]) < 0.9 * np.mean(losses[:10])
     assert after < 0.5 * before
+
+
+def test_self_trained_cache_removes_truncation_bias():
+    """Self-training (records at vertices 1..4 of paths closed by the cache
+    at vertex 5) on the same scene as the plain-record test: the cache's
+    8x8-block bias against a 4096-spp plain reference falls to the level of
+    the noise, as with plain records."""
+    drt = _drt()
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=64, height=64)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    ref = drt.render_forward(gs, tex, None, sc.cameras, 4096, 6, 3, seed=1284).cpu().numpy()
+    cache = drt.NrcCache(cfg, W0, grid0, n_paths=16384, lr=1e-2, self_training=5)
+    spp = 256
+
+    def blocks(img):
+        return img.reshape(8, 8, 8, 8, 3).mean((1, 3))
+
+    def bias(img):
+        return float(np.sqrt(((blocks(img) - blocks(ref)) ** 2).mean()))
+
+    before = bias(cache.render(gs, tex, None, sc.cameras, spp, seed=77).cpu().numpy())
+    losses = [cache.train_frame(gs, tex, None, sc.cameras, seed=1000 + f).item() for f in range(200)]
+    after = bias(cache.render(gs, tex, None, sc.cameras, spp, seed=77).cpu().numpy())
+    print(f"8x8-block rms error at {spp} spp: untrained cache {before:.4g} self-trained cache "
+          f"{after:.4g}; loss {np.mean(losses[:10]):.4g} -> {np.mean(losses[-10:]):.4g}", flush=True)
+    assert after < 0.5 * before
+    assert after < 0.01
 
 
 def test_degenerate_cache_inputs():

@@ -247,4 +247,12 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_render_adjoint_cached(h, ctypes.byref(p), cams, 1, ctypes.byref(o),
                                              ctypes.byref(c), fake, fake, fake, fake, fake, 10, fake,
                                              fake, ctypes.byref(g), None) == -4
+    # self-training: workspace sizes, and the scene check before anything else
+    wsb = int(drt.lib.drt_nrc_collect_self_workspace_bytes(1000, 5))
+    assert wsb >= 1000 * (16 * 4 + 5 * 4 + 3 * 4 + 4 * 3 * 4)
+    assert drt.lib.drt_nrc_collect_self_workspace_bytes(1000, 1) == 0
+    assert drt.lib.drt_nrc_collect_self_workspace_bytes(1000, 33) == 0
+    assert drt.lib.drt_nrc_collect_self_workspace_bytes(-1, 5) == 0
+    assert drt.lib.drt_nrc_collect_self(h, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(c),
+                                        fake, fake, 5, 1000, fake, fake, fake, fake, wsb, None) == -4
     drt.lib.drt_scene_destroy(h)
