@@ -179,8 +179,10 @@ def main():
                                                          "vertices", "scatter", "samples")}}
 
     aux = None
+    checkpointed = None
     if not args.no_aux:
         aux = aux_primal_1m(drt, scenes, torch)
+        checkpointed = checkpoint_compare(drt, scenes, torch, sc, [tex], rough, adj, R, SPP, D)
 
     cache = None
     if not args.no_cache:
@@ -215,6 +217,7 @@ def main():
         "cpu_baseline": cpu,
         "cache": cache,
         "wavefront": wavefront,
+        "checkpointed": checkpointed,
         "aux": aux,
     }
     print(json.dumps(line), flush=True)
@@ -235,6 +238,68 @@ def measured_traffic():
     if h.hexdigest() != rec.get("source_sha256"):
         return None
     return int(rec["hbm_bytes"])
+
+
+def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
+                       depths=(3, 8, 16, 32), R_long=512, spp_long=4):
+    """Image + gradient of <adj, image> by the three strategies the paper
+    compares (Sec. "Evaluation", differentiating existing methods): PRB as
+    megakernels (primal, then pass A + replay), PRB as wavefront kernels,
+    and the checkpointed path tracer (forward with a checkpoint per bounce,
+    then the backward walk; wavefront kernels).  HIP-event times; the
+    checkpoints' memory beside them.  First on the gradient-step workload,
+    then on the Cornell box at R_long^2, spp_long spp without Russian
+    roulette for growing maximum depth."""
+    gs = drt.Scene(sc)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, reps=2):
+        fn()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def measure(cams, spp, depth, a):
+        img = torch.empty((len(cams), cams[0].height, cams[0].width, 3), device="cuda")
+        gt, gr = [torch.zeros_like(t) for t in tex], torch.zeros_like(rough)
+        n = len(cams) * cams[0].width * cams[0].height * spp
+        ws_p = torch.empty(int(drt.lib.drt_render_wavefront_workspace_bytes(n)), dtype=torch.uint8,
+                           device="cuda")
+        ws_a = torch.empty(int(drt.lib.drt_render_adjoint_wavefront_workspace_bytes(n)),
+                           dtype=torch.uint8, device="cuda")
+        mk = timed(lambda: (drt.render_forward(gs, tex, rough, cams, spp, depth, seed=1, out=img),
+                            drt.render_adjoint(gs, tex, rough, cams, a, spp, depth, seed=2,
+                                               grad_textures=gt, grad_roughness=gr)))
+        wf = timed(lambda: (drt.render_wavefront(gs, tex, rough, cams, spp, depth, seed=1, out=img,
+                                                 workspace=ws_p),
+                            drt.render_adjoint_wavefront(gs, tex, rough, cams, a, spp, depth, seed=2,
+                                                         grad_textures=gt, grad_roughness=gr,
+                                                         workspace=ws_a)))
+        del ws_p, ws_a
+        ws_c = drt.checkpoint_workspace(cams, spp, depth)
+        ck = timed(lambda: (drt.render_checkpointed_forward(gs, tex, rough, cams, spp, depth, seed=1,
+                                                            workspace=ws_c, out=img),
+                            drt.render_checkpointed_adjoint(gs, tex, rough, cams, a, spp, depth, ws_c,
+                                                            seed=1, grad_textures=gt,
+                                                            grad_roughness=gr)))
+        mb = ws_c.numel() / 2 ** 20
+        del ws_c
+        return {"max_depth": depth, "prb_megakernel_ms": round(mk, 3), "prb_wavefront_ms": round(wf, 3),
+                "checkpointed_wavefront_ms": round(ck, 3), "checkpointed_workspace_mib": round(mb, 1),
+                "prb_wavefront_workspace_mib": round(n * 13 * 16 / 2 ** 20, 1)}
+
+    head = measure(sc.cameras, SPP, D, adj)
+    cams = scenes.cornell(width=R_long, height=R_long).cameras
+    a = torch.from_numpy(np.random.default_rng(3).normal(size=(1, R_long, R_long, 3))
+                         .astype(np.float32) * 1e-3).cuda()
+    rows = [measure(cams, spp_long, d, a) for d in depths]
+    return {"workload": f"image + gradient; {R}^2 {SPP} spp D{D} (gradient-step scene), then "
+                        f"{R_long}^2 {spp_long} spp without RR at growing max depth",
+            "gradient_step_workload": head, "by_depth": rows}
 
 
 def aux_primal_1m(drt, scenes, torch):

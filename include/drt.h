@@ -245,6 +245,37 @@ drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params
                                         const drt_grads* grads, void* workspace,
                                         int64_t workspace_bytes, void* hip_stream);
 
+/* Checkpointed adjoint: the naive way to differentiate a path tracer that
+ * Sec. "Evaluation" measures Path Replay Backpropagation against -- one
+ * checkpoint per scattering event instead of a replay.
+ * drt_render_checkpointed_forward renders the image (same estimator, sample
+ * streams and arithmetic as drt_render_wavefront) and keeps, in the
+ * workspace, the ray state of every path before every bounce (64 B per path
+ * and bounce: memory grows with opts->max_depth).
+ * drt_render_checkpointed_adjoint then walks the bounces backwards from those
+ * checkpoints: it recomputes each vertex (closest hit, shading with
+ * derivatives, shadow ray), forms its gradient with the radiance collected
+ * by the later vertices, and adds the vertex's own terms to that radiance.
+ * The gradient of sum <adj_image, image> is ADDED to grads; it equals
+ * drt_render_adjoint's with the same seed up to float rounding and atomic
+ * order.  Both calls take the same scene, params, cams and opts, and the
+ * adjoint call needs the workspace as the forward call left it (no other
+ * use in between).  workspace: at least
+ * drt_render_checkpointed_workspace_bytes(n_cams*W*H*spp, opts->max_depth)
+ * bytes, 16-byte aligned (the size function returns 0 for max_depth outside
+ * [1, 65536] or n_paths outside [0, 2^40]). */
+int64_t drt_render_checkpointed_workspace_bytes(int64_t n_paths, int32_t max_depth);
+drt_status drt_render_checkpointed_forward(const drt_scene* scene, const drt_params* params,
+                                           const drt_camera* cams, int32_t n_cams,
+                                           const drt_render_opts* opts, void* workspace,
+                                           int64_t workspace_bytes, float* image,
+                                           void* hip_stream);
+drt_status drt_render_checkpointed_adjoint(const drt_scene* scene, const drt_params* params,
+                                           const drt_camera* cams, int32_t n_cams,
+                                           const drt_render_opts* opts, const float* adj_image,
+                                           const drt_grads* grads, void* workspace,
+                                           int64_t workspace_bytes, void* hip_stream);
+
 /* Forward-mode derivative of the primal image along a parameter direction
  * (Sec. "Physically Based Differentiable Rendering" describes the forward
  * mode used to check and visualise derivatives): image_tangent = d I / d params

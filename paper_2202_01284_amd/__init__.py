@@ -121,6 +121,15 @@ _SIGS = {
     "drt_render_adjoint_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                               _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                               ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
+    "drt_render_checkpointed_workspace_bytes": (_c_i64, [_c_i64, _c_i32]),
+    "drt_render_checkpointed_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params),
+                                                 ctypes.POINTER(drt_camera), _c_i32,
+                                                 ctypes.POINTER(drt_render_opts), _vp, _c_i64, _vp,
+                                                 _vp]),
+    "drt_render_checkpointed_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params),
+                                                 ctypes.POINTER(drt_camera), _c_i32,
+                                                 ctypes.POINTER(drt_render_opts), _vp,
+                                                 ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
     "drt_render_jvp": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
                                 ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_grads), _vp, _vp]),
     "drt_render_adjoint": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
@@ -489,6 +498,73 @@ def render_adjoint_wavefront(scene: Scene, textures: Sequence, roughness, cams, 
                                             adj_image.data_ptr(), ctypes.byref(g), workspace.data_ptr(),
                                             workspace.numel(), _stream(stream)),
            "drt_render_adjoint_wavefront")
+    return grad_textures, grad_roughness
+
+
+def checkpoint_workspace(cams, spp: int, max_depth: int, device="cuda"):
+    """Workspace of the checkpointed calls: state plus one 64-byte checkpoint
+    per path and bounce."""
+    torch = _torch()
+    n = len(cams) * cams[0].width * cams[0].height * spp
+    nbytes = int(lib.drt_render_checkpointed_workspace_bytes(n, max_depth))
+    if nbytes <= 0:
+        raise ValueError("no checkpoint workspace for these sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def render_checkpointed_forward(scene: Scene, textures: Sequence, roughness, cams, spp: int,
+                                max_depth: int, rr_depth: int = NO_RR, seed: int = 1, flags: int = 0,
+                                workspace=None, out=None, stream=None):
+    """Primal image whose per-bounce ray states stay in `workspace` for
+    render_checkpointed_adjoint: (image, workspace)."""
+    torch = _torch()
+    dev = scene.buffer.device
+    if out is None:
+        out = torch.empty(_image_shape(cams), dtype=torch.float32, device=dev)
+    _expect(out, "out", _image_shape(cams))
+    if workspace is None:
+        workspace = checkpoint_workspace(cams, spp, max_depth, dev)
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    _check(lib.drt_render_checkpointed_forward(scene.handle, ctypes.byref(p), ca, len(cams),
+                                               ctypes.byref(o), workspace.data_ptr(),
+                                               workspace.numel(), out.data_ptr(), _stream(stream)),
+           "drt_render_checkpointed_forward")
+    return out, workspace
+
+
+def render_checkpointed_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
+                                spp: int, max_depth: int, workspace, rr_depth: int = NO_RR,
+                                seed: int = 1, flags: int = 0, grad_textures=None,
+                                grad_roughness=None, stream=None):
+    """Gradient of <adj, I> from the checkpoints that
+    render_checkpointed_forward left in `workspace` (same arguments), added
+    into grad_textures / grad_roughness and returned."""
+    torch = _torch()
+    _expect(adj_image, "adj_image", _image_shape(cams))
+    if grad_textures is None:
+        grad_textures = [torch.zeros_like(t) for t in textures]
+    if grad_roughness is None and roughness is not None and roughness.numel() > 0:
+        grad_roughness = torch.zeros_like(roughness)
+    g = drt_grads()
+    for i, t in enumerate(grad_textures):
+        if t is not None:
+            _expect(t, f"grad texture {i}", scene.tex_shapes[i])
+            g.textures[i] = t.data_ptr()
+    if grad_roughness is not None:
+        _expect(grad_roughness, "grad roughness")
+        if grad_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
+        g.roughness = grad_roughness.data_ptr()
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, None)
+    _check(lib.drt_render_checkpointed_adjoint(scene.handle, ctypes.byref(p), ca, len(cams),
+                                               ctypes.byref(o), adj_image.data_ptr(),
+                                               ctypes.byref(g), workspace.data_ptr(),
+                                               workspace.numel(), _stream(stream)),
+           "drt_render_checkpointed_adjoint")
     return grad_textures, grad_roughness
 
 

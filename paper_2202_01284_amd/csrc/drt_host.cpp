@@ -801,6 +801,69 @@ drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params
   return ok();
 }
 
+int64_t drt_render_checkpointed_workspace_bytes(int64_t n_paths, int32_t max_depth) {
+  if (n_paths < 0 || n_paths > ((int64_t)1 << 40) || max_depth < 1 || max_depth > (1 << 16)) return 0;
+  return checkpoint_workspace_bytes(n_paths, max_depth);
+}
+
+// Shared checks of the two checkpointed calls.
+static drt_status checkpoint_args(const drt_scene* scene, const drt_params* params,
+                                  const drt_camera* cams, int32_t n_cams,
+                                  const drt_render_opts* opts, void* workspace,
+                                  int64_t workspace_bytes, DParams* dp, DCams* dc, DRender* dr) {
+  drt_status st = check_params(scene, params, cams, n_cams, opts, dp, dc, dr);
+  if (st != DRT_OK) return st;
+  if (!workspace) return fail(DRT_EINVAL, "workspace is required");
+  const int64_t n = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
+  const int64_t need = checkpoint_workspace_bytes(n, opts->max_depth);
+  if (workspace_bytes < need)
+    return fail(DRT_EINVAL, "workspace of %lld bytes < %lld", (long long)workspace_bytes,
+                (long long)need);
+  if (((uintptr_t)workspace & 15) != 0) return fail(DRT_EINVAL, "workspace is not 16-byte aligned");
+  dr->stats = nullptr;
+  return DRT_OK;
+}
+
+drt_status drt_render_checkpointed_forward(const drt_scene* scene, const drt_params* params,
+                                           const drt_camera* cams, int32_t n_cams,
+                                           const drt_render_opts* opts, void* workspace,
+                                           int64_t workspace_bytes, float* image,
+                                           void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = checkpoint_args(scene, params, cams, n_cams, opts, workspace, workspace_bytes,
+                                  &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!image) return fail(DRT_EINVAL, "image is required");
+  hipError_t e = launch_render_checkpoint_forward(scene->dev, dp, dc, dr, workspace, image,
+                                                  (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "checkpointed forward launch");
+  return ok();
+}
+
+drt_status drt_render_checkpointed_adjoint(const drt_scene* scene, const drt_params* params,
+                                           const drt_camera* cams, int32_t n_cams,
+                                           const drt_render_opts* opts, const float* adj_image,
+                                           const drt_grads* grads, void* workspace,
+                                           int64_t workspace_bytes, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = checkpoint_args(scene, params, cams, n_cams, opts, workspace, workspace_bytes,
+                                  &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!adj_image || !grads) return fail(DRT_EINVAL, "adj_image and grads are required");
+  DGrads dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
+  dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  hipError_t e = launch_render_checkpoint_adjoint(scene->dev, dp, dc, dr, adj_image, dg, workspace,
+                                                  (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "checkpointed adjoint launch");
+  return ok();
+}
+
 drt_status drt_render_jvp(const drt_scene* scene, const drt_params* params, const drt_camera* cams,
                           int32_t n_cams, const drt_render_opts* opts, const drt_grads* direction,
                           float* image_tangent, void* hip_stream) {

@@ -202,6 +202,15 @@ hipError_t launch_render_adjoint_wavefront(const DScene& s, const DParams& p, co
                                            void* ws, hipStream_t st);
 hipError_t launch_render_wavefront(const DScene& s, const DParams& p, const DCams& c,
                                    const DRender& r, void* ws, float* image, hipStream_t st);
+// Checkpointed adjoint (drt_wavefront.hip): forward pass keeping the ray
+// state of every bounce, then the backward pass from those checkpoints.
+int64_t checkpoint_workspace_bytes(int64_t n_paths, int max_depth);
+hipError_t launch_render_checkpoint_forward(const DScene& s, const DParams& p, const DCams& c,
+                                            const DRender& r, void* ws, float* image,
+                                            hipStream_t st);
+hipError_t launch_render_checkpoint_adjoint(const DScene& s, const DParams& p, const DCams& c,
+                                            const DRender& r, const float* adj, const DGrads& G,
+                                            void* ws, hipStream_t st);
 hipError_t launch_trace(const DScene& s, const float* rays, int64_t n, int mode, drt_hit* hits,
                         hipStream_t st);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out,

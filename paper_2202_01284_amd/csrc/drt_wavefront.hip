@@ -21,18 +21,41 @@
 //   pa4 = ((d f/d albedo)/f, unused) pr4 = ((d f/d alpha)/f, unused)
 //   pn4 = (next-event albedo gradient, next-event roughness gradient)
 //   pv4 = (texture, texel, roughness slot, BSDF sample pending) as int bits
+// and, for the checkpointed adjoint, pe4 = (emission found at the vertex,
+// unused).  The shading kernel reads the ray state from o4, d4, b4, pp4 and
+// writes the next bounce's to no4, nd4, nb4, npp4 (the same arrays, except
+// in the checkpointed variant).
+//
+// Checkpointed adjoint (the naive alternative to Path Replay
+// Backpropagation that Sec. "Evaluation" measures against it: a standard
+// path tracer differentiated with one checkpoint per scattering event).
+// The forward pass is the primal, with the ray state before every bounce
+// kept in a tape slice of the workspace (o4, d4, b4, pp4: 64 B per path and
+// bounce), so it costs memory in proportion to the path length.  The
+// backward pass walks the bounces from the last to the first: it restores
+// the ray of bounce i from its slice, recomputes the vertex (closest hit,
+// shading with derivatives, shadow ray), forms the vertex's gradient with
+// A = the radiance collected by the later vertices -- the quantity the
+// replay obtains as L_rem by subtraction -- and then adds the vertex's own
+// emission and next-event terms to A.
 #include "drt_device.h"
 
 namespace drt {
 
 struct WState {
   float4 *o4, *d4, *b4, *L4, *pp4, *h4, *so4, *sd4, *sc4;
-  float4 *pa4, *pr4, *pn4, *pv4;
+  float4 *pa4, *pr4, *pn4, *pv4, *pe4;
+  float4 *no4, *nd4, *nb4, *npp4;  // where the shading kernel writes the next ray state
 };
 
 constexpr int kWfBlock = 64;    // one wave per workgroup (LDS traversal stack per lane)
 constexpr int kWfArrays = 9;    // primal state
 constexpr int kWfArraysAdj = 13;  // with the replay's pending terms
+constexpr int kWfArraysCk = 10;   // checkpointed adjoint: L4 .. pe4 besides the tape
+constexpr int kTapeArrays = 4;    // o4, d4, b4, pp4 per bounce
+
+// what the shading kernel computes
+enum { WF_PRIMAL = 0, WF_REPLAY = 1, WF_BACKWARD = 2 };
 
 // the path's share of the image adjoint (zero: the path is not traced)
 DEV f3 path_dL(const float* adj, int64_t g, int spp) {
@@ -82,19 +105,25 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_trace(DScene s, int64_t n, WSta
 
 // the vertex found by the closest hit: emission (MIS), then, below the
 // maximum depth, a pass-through or the next-event candidate (its shadow ray
-// left pending) and the BSDF sample with Russian roulette.  RB (the replay):
-// the collected terms are subtracted from L_rem in L4 and the vertex's
-// derivative terms are left pending for k_wf_resolve.
-template <bool RB>
+// left pending) and the BSDF sample with Russian roulette.  WF_REPLAY: the
+// collected terms are subtracted from L_rem in L4 and the vertex's
+// derivative terms are left pending for k_wf_resolve.  WF_BACKWARD: L4 (the
+// radiance of the later vertices) is left alone; the emission goes to pe4
+// and the derivative terms are left pending as in the replay.
+template <int WM>
 __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRender R, int64_t n,
                                                        const float* __restrict__ adj, WState S) {
+  constexpr bool RB = WM == WF_REPLAY, CK = WM == WF_BACKWARD, DER = RB || CK;
   __shared__ LdsTables tab;
   load_tables(tab, s, P, nullptr);
   __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * kWfBlock + threadIdx.x;
   if (g >= n) return;
   float4 b4 = S.b4[g];
-  if (__float_as_int(b4.w) == 0) return;
+  if (__float_as_int(b4.w) == 0) {
+    if (S.nb4 != S.b4) S.nb4[g] = b4;  // an ended path stays ended in the next slice
+    return;
+  }
   const int n_em = s.n_ems;
   const float p_sel = n_em > 0 ? 1.0f / (float)n_em : 0.f;
   const bool no_nee = (R.flags & DRT_FLAG_NO_NEE) != 0;
@@ -110,7 +139,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
   f3 nee_c = mk(0, 0, 0), so = o, sd = d;
   float stmax = 0.f;
   // replay: the vertex's derivative terms
-  const f3 dL = RB ? path_dL(adj, g, R.spp) : mk(0, 0, 0);
+  const f3 dL = DER ? path_dL(adj, g, R.spp) : mk(0, 0, 0);
+  f3 e = mk(0, 0, 0);  // emission found here (WF_BACKWARD)
   f3 nee_gt = mk(0, 0, 0), rat_alb = mk(0, 0, 0), rat_alpha = mk(0, 0, 0);
   float nee_gr = 0.f;
   int vtex = -1, vtexel = 0, vrslot = -1;
@@ -123,7 +153,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
       float w = 1.0f;
       if (!(prev_pdf == 0.f || no_nee)) w = power_heuristic(prev_pdf, p_sel * env_pdf(s, row, col, st));
       f3 c = beta * env_lookup(s, row, col) * w;
-      L = RB ? L - c : L + c;
+      if (CK) e = c;
+      else L = RB ? L - c : L + c;
     }
     done = true;
   } else {
@@ -144,7 +175,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         w = power_heuristic(prev_pdf, p_sel * dot(dv, dv) / (E.area * cos_y));
       }
       f3 c = beta * mk(E.radiance[0], E.radiance[1], E.radiance[2]) * w;
-      L = RB ? L - c : L + c;
+      if (CK) e = c;
+      else L = RB ? L - c : L + c;
     }
     if (k == R.max_depth) {
       done = true;
@@ -220,12 +252,12 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
             valid = true;
           }
           if (valid) {
-            BEval fe = bsdf_eval<RB>(sh, wi, to_local(fr, wl));
+            BEval fe = bsdf_eval<DER>(sh, wi, to_local(fr, wl));
             if (nonzero(fe.f)) {
               float w = delta ? 1.0f : power_heuristic(p_sel * pdf_l, fe.pdf);
               f3 coef = beta * Le * (w / (p_sel * pdf_l));
               nee_c = coef * fe.f;
-              if (RB) {
+              if (DER) {
                 nee_gt = dL * coef * fe.dalb;
                 f3 gr = dL * coef * fe.dalpha;
                 nee_gr = gr.x + gr.y + gr.z;
@@ -245,8 +277,8 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
         }
         f3 wo;
         BEval be;
-        const bool ok = bsdf_sample<RB>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
-        if (RB && ok) {
+        const bool ok = bsdf_sample<DER>(sh, wi, u01(r1.x), u01(r1.y), u01(r0.w), wo, be);
+        if (DER && ok) {
           bsdf_pend = true;
           rat_alb = mk(be.f.x != 0.f ? be.dalb.x / be.f.x : 0.f, be.f.y != 0.f ? be.dalb.y / be.f.y : 0.f,
                        be.f.z != 0.f ? be.dalb.z / be.f.z : 0.f);
@@ -273,17 +305,18 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
       }
     }
   }
-  S.o4[g] = f4(o, prev_pdf);
-  S.d4[g] = f4(d, __int_as_float(k));
-  S.b4[g] = f4(beta, __int_as_float(done ? 0 : 1));
-  S.L4[g] = f4(L, 0.f);
-  S.pp4[g] = f4(prev_p, 0.f);
+  S.no4[g] = f4(o, prev_pdf);
+  S.nd4[g] = f4(d, __int_as_float(k));
+  S.nb4[g] = f4(beta, __int_as_float(done ? 0 : 1));
+  if (CK) S.pe4[g] = f4(e, 0.f);
+  else S.L4[g] = f4(L, 0.f);
+  S.npp4[g] = f4(prev_p, 0.f);
   if (nee) {
     S.so4[g] = f4(so, stmax);
     S.sc4[g] = f4(nee_c, 0.f);
   }
   S.sd4[g] = f4(sd, __int_as_float(nee ? 1 : 0));
-  if (RB) {
+  if (DER) {
     if (shaded) {
       S.pa4[g] = f4(rat_alb, 0.f);
       S.pr4[g] = f4(rat_alpha, 0.f);
@@ -315,7 +348,13 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shadow(DScene s, int64_t n, WSt
 // replay: the vertex's shadow ray, then its gradient as the megakernel forms
 // it -- the next-event term if visible (L_rem loses it first), plus dL L_rem
 // (d f/f) for the sampled continuation -- scattered into its texel and
-// roughness slot (roughness pre-reduced in LDS per workgroup)
+// roughness slot (roughness pre-reduced in LDS per workgroup).
+// CK (checkpointed backward): L4 holds A, the radiance of the later
+// vertices; the gradient is the next-event term if visible plus dL A (d f/f),
+// and then A gains the vertex's emission and visible next-event term.  Every
+// path live at this bounce takes part (its emission counts even where the
+// vertex has no derivative).
+template <bool CK>
 __global__ __launch_bounds__(kWfBlock) void k_wf_resolve(DScene s, DParams P, DGrads G, DRender R,
                                                          int64_t n, const float* __restrict__ adj,
                                                          WState S) {
@@ -333,16 +372,18 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_resolve(DScene s, DParams P, DG
     const bool nee = __float_as_int(sd4.w) != 0;
     const int vtex = __float_as_int(pv.x), vtexel = __float_as_int(pv.y), vrslot = __float_as_int(pv.z);
     const bool bsdf_pend = __float_as_int(pv.w) != 0;
-    if (nee || bsdf_pend) {
-      f3 Lrem = xyz(S.L4[g]);
-      f3 gtex = mk(0, 0, 0);
+    const bool live = CK ? __float_as_int(S.b4[g].w) != 0 : (nee || bsdf_pend);
+    if (live) {
+      f3 Lrem = xyz(S.L4[g]);  // CK: A
+      f3 gtex = mk(0, 0, 0), add = mk(0, 0, 0);
       float grough = 0.f;
       if (nee) {
         const float4 so4 = S.so4[g];
         Hit h;
         RayPre rp = ray_pre(xyz(so4), xyz(sd4));
         if (!traverse(s, rp, 0.f, so4.w, true, h, stack + threadIdx.x, cnt)) {
-          Lrem = Lrem - xyz(S.sc4[g]);
+          if (CK) add = xyz(S.sc4[g]);
+          else Lrem = Lrem - xyz(S.sc4[g]);
           const float4 pn = S.pn4[g];
           gtex = xyz(pn);
           grough = pn.w;
@@ -357,6 +398,7 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_resolve(DScene s, DParams P, DG
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
       if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
       if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
+      if (CK) Lrem = Lrem + xyz(S.pe4[g]) + add;
       S.L4[g] = f4(Lrem, 0.f);
       S.sd4[g] = make_float4(sd4.x, sd4.y, sd4.z, 0.f);
       S.pv4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -384,6 +426,9 @@ __global__ __launch_bounds__(256) void k_wf_accumulate(int64_t n_pix, int spp, W
 
 int64_t wavefront_workspace_bytes(int64_t n_paths) { return n_paths * kWfArrays * 16; }
 int64_t wavefront_adjoint_workspace_bytes(int64_t n_paths) { return n_paths * kWfArraysAdj * 16; }
+int64_t checkpoint_workspace_bytes(int64_t n_paths, int max_depth) {
+  return n_paths * (kWfArraysCk + kTapeArrays * (int64_t)(max_depth + 1)) * 16;
+}
 
 static WState state_in(void* ws, int64_t n, int n_arrays) {
   float4* base = static_cast<float4*>(ws);
@@ -391,6 +436,34 @@ static WState state_in(void* ws, int64_t n, int n_arrays) {
   float4** arrays[kWfArraysAdj] = {&S.o4, &S.d4, &S.b4, &S.L4, &S.pp4, &S.h4, &S.so4,
                                    &S.sd4, &S.sc4, &S.pa4, &S.pr4, &S.pn4, &S.pv4};
   for (int a = 0; a < n_arrays; ++a) *arrays[a] = base + (size_t)a * n;
+  S.no4 = S.o4;
+  S.nd4 = S.d4;
+  S.nb4 = S.b4;
+  S.npp4 = S.pp4;
+  return S;
+}
+
+// Checkpointed layout: L4 h4 so4 sd4 sc4 pa4 pr4 pn4 pv4 pe4, then the tape,
+// slice i = (o4, d4, b4, pp4) of bounce i (i = 0 .. max_depth; the last is
+// written by the last bounce and never read).  Bounce i reads slice i and
+// writes slice `out`.
+static WState state_ck(void* ws, int64_t n, int i, int out) {
+  float4* base = static_cast<float4*>(ws);
+  WState S = {};
+  float4** arrays[kWfArraysCk] = {&S.L4, &S.h4, &S.so4, &S.sd4, &S.sc4,
+                                  &S.pa4, &S.pr4, &S.pn4, &S.pv4, &S.pe4};
+  for (int a = 0; a < kWfArraysCk; ++a) *arrays[a] = base + (size_t)a * n;
+  float4* tape = base + (size_t)kWfArraysCk * n;
+  float4* in = tape + (size_t)kTapeArrays * i * n;
+  float4* nx = tape + (size_t)kTapeArrays * out * n;
+  S.o4 = in;
+  S.d4 = in + n;
+  S.b4 = in + 2 * n;
+  S.pp4 = in + 3 * n;
+  S.no4 = nx;
+  S.nd4 = nx + n;
+  S.nb4 = nx + 2 * n;
+  S.npp4 = nx + 3 * n;
   return S;
 }
 
@@ -404,7 +477,7 @@ static void primal_passes(const DScene& s, const DParams& p, const DCams& c, con
     hipLaunchKernelGGL((k_wf_camera<false, false>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, adj, S);
   for (int depth = 1; depth <= r.max_depth; ++depth) {
     hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
-    hipLaunchKernelGGL(k_wf_shade<false>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
+    hipLaunchKernelGGL(k_wf_shade<WF_PRIMAL>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
     hipLaunchKernelGGL(k_wf_shadow, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
   }
 }
@@ -430,8 +503,47 @@ hipError_t launch_render_adjoint_wavefront(const DScene& s, const DParams& p, co
   hipLaunchKernelGGL((k_wf_camera<true, true>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n, adj, S);
   for (int depth = 1; depth <= r.max_depth; ++depth) {
     hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
-    hipLaunchKernelGGL(k_wf_shade<true>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
-    hipLaunchKernelGGL(k_wf_resolve, dim3(blocks), dim3(kWfBlock), 0, st, s, p, G, r, n, adj, S);
+    hipLaunchKernelGGL(k_wf_shade<WF_REPLAY>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n, adj, S);
+    hipLaunchKernelGGL(k_wf_resolve<false>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, G, r, n, adj, S);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_render_checkpoint_forward(const DScene& s, const DParams& p, const DCams& c,
+                                            const DRender& r, void* ws, float* image,
+                                            hipStream_t st) {
+  const int64_t n_pix = (int64_t)c.n * c.width * c.height;
+  const int64_t n = n_pix * r.spp;
+  const unsigned blocks = (unsigned)((n + kWfBlock - 1) / kWfBlock);
+  const WState S0 = state_ck(ws, n, 0, 0);
+  hipLaunchKernelGGL((k_wf_camera<false, false>), dim3(blocks), dim3(kWfBlock), 0, st, c, r, n,
+                     nullptr, S0);
+  for (int i = 0; i < r.max_depth; ++i) {
+    const WState S = state_ck(ws, n, i, i + 1);
+    hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+    hipLaunchKernelGGL(k_wf_shade<WF_PRIMAL>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n,
+                       nullptr, S);
+    hipLaunchKernelGGL(k_wf_shadow, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+  }
+  hipLaunchKernelGGL(k_wf_accumulate, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, st, n_pix,
+                     r.spp, S0, image);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_checkpoint_adjoint(const DScene& s, const DParams& p, const DCams& c,
+                                            const DRender& r, const float* adj, const DGrads& G,
+                                            void* ws, hipStream_t st) {
+  const int64_t n = (int64_t)c.n * c.width * c.height * r.spp;
+  const unsigned blocks = (unsigned)((n + kWfBlock - 1) / kWfBlock);
+  hipError_t e = launch_zero(state_ck(ws, n, 0, 0).L4, 4 * n, st);  // A = 0 beyond the last vertex
+  if (e != hipSuccess) return e;
+  for (int i = r.max_depth - 1; i >= 0; --i) {
+    // the next-ray outputs of the recomputed bounce go to the unused last slice
+    const WState S = state_ck(ws, n, i, r.max_depth);
+    hipLaunchKernelGGL(k_wf_trace, dim3(blocks), dim3(kWfBlock), 0, st, s, n, S);
+    hipLaunchKernelGGL(k_wf_shade<WF_BACKWARD>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, r, n,
+                       adj, S);
+    hipLaunchKernelGGL(k_wf_resolve<true>, dim3(blocks), dim3(kWfBlock), 0, st, s, p, G, r, n, adj, S);
   }
   return hipGetLastError();
 }
