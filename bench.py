@@ -6,7 +6,10 @@ wall and one roughness scalar; 1024x1024 pixels, 16 spp, max depth 3, no
 Russian roulette.  One step = primal render (seed A) -> L2 loss and
 image-space adjoint -> replayed adjoint (seed B) scattering texel and
 roughness gradients -> Adam on texture and roughness (gradients re-zeroed by
-the same kernel).  Inputs are resident in HBM before timing starts.
+the same kernel).  The replay reads pass A's intersections from a 48 MiB
+record buffer instead of tracing the same rays again (identical gradients);
+the re-tracing replay's time is reported beside it.  Inputs are resident in
+HBM before timing starts.
 
 Reported: Msamples/s = 1024*1024*16 / step time; the adjoint kernel's
 roofline (ALU bound; algorithmic FLOPs from the traversal/shading counters of
@@ -90,6 +93,7 @@ def main():
     ws = torch.empty(int(drt.lib.drt_loss_workspace_floats(img.numel())), dtype=torch.float32,
                      device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
+    hits = drt.adjoint_hit_records(cams, D)
     ev = []
 
     def step(k, timed):
@@ -99,7 +103,7 @@ def main():
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
         drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * k + 2,
-                           grad_textures=[gtex], grad_roughness=grough)
+                           grad_textures=[gtex], grad_roughness=grough, hit_records=hits)
         if timed:
             e1.record()
             ev.append((e0, e1))
@@ -150,7 +154,7 @@ def main():
                            grad_roughness=g_r)
     e1.record()
     torch.cuda.synchronize()
-    mk_adj = e0.elapsed_time(e1) / 2
+    mk_adj = e0.elapsed_time(e1) / 2  # the replay tracing its rays again
     e0.record()
     for k in range(2):
         drt.render_adjoint_wavefront(gs, [tex], rough, cams, adj, SPP, D, seed=4 + k, grad_textures=[g_t],
@@ -160,7 +164,9 @@ def main():
     wf_adj = e0.elapsed_time(e1) / 2
     del ws, g_t, g_r
     wavefront = {"primal_ms_megakernel": round(mk_ms, 3), "primal_ms_wavefront": round(wf_ms, 3),
-                 "adjoint_ms_megakernel": round(mk_adj, 3), "adjoint_ms_wavefront": round(wf_adj, 3),
+                 "adjoint_ms_megakernel": round(mk_adj, 3),
+                 "adjoint_ms_megakernel_records": round(adj_ms, 3),
+                 "adjoint_ms_wavefront": round(wf_adj, 3),
                  "wavefront_over_megakernel_time": {"primal": round(wf_ms / mk_ms, 3),
                                                     "adjoint": round(wf_adj / mk_adj, 3)}}
 
@@ -168,11 +174,11 @@ def main():
     stats = drt.new_stats()
     drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * args.warmup + 2,
                        grad_textures=[torch.zeros_like(tex)], grad_roughness=torch.zeros_like(rough),
-                       stats=stats)
+                       stats=stats, hit_records=hits)
     st = drt.read_stats(stats)
     flops = st["nodes"] * FLOP_PER_NODE + st["tris"] * FLOP_PER_TRI + st["vertices"] * FLOP_PER_VERTEX
     achieved = flops / (adj_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_render_adjoint", "bound": "alu", "achieved": round(achieved, 4),
+    roofline = {"kernel": "k_render_adjoint<false, 1, true>", "bound": "alu", "achieved": round(achieved, 4),
                 "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
                 "traffic": measured_traffic(), "launch_ms": round(adj_ms, 3),
                 "units_per_launch": {k: st[k] for k in ("rays", "shadow_rays", "nodes", "tris",
@@ -274,6 +280,13 @@ def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
         mk = timed(lambda: (drt.render_forward(gs, tex, rough, cams, spp, depth, seed=1, out=img),
                             drt.render_adjoint(gs, tex, rough, cams, a, spp, depth, seed=2,
                                                grad_textures=gt, grad_roughness=gr)))
+        hits = drt.adjoint_hit_records(cams, depth)
+        mkr = timed(lambda: (drt.render_forward(gs, tex, rough, cams, spp, depth, seed=1, out=img),
+                             drt.render_adjoint(gs, tex, rough, cams, a, spp, depth, seed=2,
+                                                grad_textures=gt, grad_roughness=gr,
+                                                hit_records=hits)))
+        rec_mb = hits.numel() / 2 ** 20
+        del hits
         wf = timed(lambda: (drt.render_wavefront(gs, tex, rough, cams, spp, depth, seed=1, out=img,
                                                  workspace=ws_p),
                             drt.render_adjoint_wavefront(gs, tex, rough, cams, a, spp, depth, seed=2,
@@ -288,7 +301,9 @@ def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
                                                             grad_roughness=gr)))
         mb = ws_c.numel() / 2 ** 20
         del ws_c
-        return {"max_depth": depth, "prb_megakernel_ms": round(mk, 3), "prb_wavefront_ms": round(wf, 3),
+        return {"max_depth": depth, "prb_megakernel_ms": round(mk, 3),
+                "prb_megakernel_records_ms": round(mkr, 3), "records_mib": round(rec_mb, 1),
+                "prb_wavefront_ms": round(wf, 3),
                 "checkpointed_wavefront_ms": round(ck, 3), "checkpointed_workspace_mib": round(mb, 1),
                 "prb_wavefront_workspace_mib": round(n * 13 * 16 / 2 ** 20, 1)}
 
@@ -356,12 +371,23 @@ def aux_primal_1m(drt, scenes, torch):
     e1.record()
     torch.cuda.synchronize()
     adj_wf = e0.elapsed_time(e1)
-    del ws, gt, gr, adj
+    del ws
+    hits = drt.adjoint_hit_records(sc.cameras, 6)
+    drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=5, grad_textures=gt,
+                       grad_roughness=gr, hit_records=hits)
+    e0.record()
+    drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=6, grad_textures=gt,
+                       grad_roughness=gr, hit_records=hits)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_rec = e0.elapsed_time(e1)
+    del gt, gr, adj, hits
     return {"workload": "procedural ~1M triangles, 8 BSDFs, env + 16 quad lights, 1024^2 64spp D6 RR3",
             "triangles": sc.n_triangles, "primal_msamples_s": round(1024 * 1024 * 64 / ms / 1e3, 2),
             "primal_ms": round(ms, 2), "wavefront_primal_ms": round(wf_ms, 2),
             "wavefront_over_megakernel_time": round(wf_ms / ms, 3),
-            "adjoint_16spp_ms": {"megakernel": round(adj_mk, 2), "wavefront": round(adj_wf, 2)},
+            "adjoint_16spp_ms": {"megakernel": round(adj_mk, 2), "megakernel_records": round(adj_rec, 2),
+                                 "wavefront": round(adj_wf, 2)},
             "mrays_s": round(rays / ms / 1e3, 1),
             "nodes_per_ray": round(st["nodes"] / max(rays, 1), 2),
             "tris_per_ray": round(st["tris"] / max(rays, 1), 2),

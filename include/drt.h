@@ -217,6 +217,25 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
                               const float* adj_image, const drt_grads* grads, void* hip_stream);
 
+/* drt_render_adjoint with intersection records: pass A keeps, per step of
+ * each lane's current sample, its closest hit (triangle, barycentrics) and
+ * its shadow ray's outcome in hit_records, and the replay reads them back
+ * instead of tracing the same rays again (the replay's sampling, L_rem
+ * subtraction and scatter are unchanged, so are the gradients, up to atomic
+ * order).  The records are reused sample after sample: their size depends
+ * on the image and max_depth, not on spp --
+ * drt_render_adjoint_hit_bytes(n_cams, W, H, max_depth) = workgroups of 8x8
+ * pixels x max_depth x 64 lanes x 16 B (0 for invalid sizes).  hit_records:
+ * device scratch of at least that many bytes, 16-byte aligned, overwritten;
+ * calls that overlap on one buffer race. */
+int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
+                                     int32_t max_depth);
+drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* params,
+                                   const drt_camera* cams, int32_t n_cams,
+                                   const drt_render_opts* opts, const float* adj_image,
+                                   const drt_grads* grads, void* hit_records, int64_t hit_bytes,
+                                   void* hip_stream);
+
 /* The primal image by the wavefront variant of the same estimator (same
  * sample streams and conventions as drt_render_forward): per bounce, a
  * closest-hit kernel, a shading kernel and a shadow-ray kernel exchange the

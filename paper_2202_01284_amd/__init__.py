@@ -121,6 +121,10 @@ _SIGS = {
     "drt_render_adjoint_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                               _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                               ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
+    "drt_render_adjoint_hit_bytes": (_c_i64, [_c_i32, _c_i32, _c_i32, _c_i32]),
+    "drt_render_adjoint_hits": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                         _c_i32, ctypes.POINTER(drt_render_opts), _vp,
+                                         ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
     "drt_render_checkpointed_workspace_bytes": (_c_i64, [_c_i64, _c_i32]),
     "drt_render_checkpointed_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params),
                                                  ctypes.POINTER(drt_camera), _c_i32,
@@ -413,9 +417,12 @@ def render_forward(scene: Scene, textures: Sequence, roughness, cams, spp: int, 
 
 def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image, spp: int,
                    max_depth: int, rr_depth: int = NO_RR, seed: int = 2, flags: int = 0,
-                   grad_textures=None, grad_roughness=None, stats=None, stream=None):
+                   grad_textures=None, grad_roughness=None, stats=None, hit_records=None,
+                   stream=None):
     """Adds d<adj, I>/d params into grad_textures / grad_roughness (allocated
-    as zeros when not given) and returns them."""
+    as zeros when not given) and returns them.  With hit_records (a device
+    buffer of adjoint_hit_bytes(...) bytes) the replay reads pass A's
+    intersections instead of tracing again."""
     torch = _torch()
     _expect(adj_image, "adj_image", _image_shape(cams))
     if grad_textures is None:
@@ -437,10 +444,25 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
-    _check(lib.drt_render_adjoint(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                  adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
-           "drt_render_adjoint")
+    if hit_records is not None:
+        _check(lib.drt_render_adjoint_hits(scene.handle, ctypes.byref(p), ca, len(cams),
+                                           ctypes.byref(o), adj_image.data_ptr(), ctypes.byref(g),
+                                           hit_records.data_ptr(), hit_records.numel(),
+                                           _stream(stream)), "drt_render_adjoint_hits")
+    else:
+        _check(lib.drt_render_adjoint(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                      adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
+               "drt_render_adjoint")
     return grad_textures, grad_roughness
+
+
+def adjoint_hit_records(cams, max_depth: int, device="cuda"):
+    """Intersection-record buffer for render_adjoint(hit_records=...)."""
+    torch = _torch()
+    nbytes = int(lib.drt_render_adjoint_hit_bytes(len(cams), cams[0].width, cams[0].height, max_depth))
+    if nbytes <= 0:
+        raise ValueError("no intersection records for these sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 def render_wavefront(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_depth: int,

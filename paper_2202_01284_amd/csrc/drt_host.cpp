@@ -581,6 +581,7 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   dr->key0 = (uint32_t)o->seed;
   dr->key1 = (uint32_t)(o->seed >> 32);
   dr->stats = o->stats;
+  dr->hits = nullptr;
   return DRT_OK;
 }
 
@@ -739,6 +740,40 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
   std::memset(&dg, 0, sizeof(dg));
   for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
   dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  hipError_t e = launch_render_adjoint(scene->dev, dp, dc, dr, adj_image, dg, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "render_adjoint launch");
+  return ok();
+}
+
+int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
+                                     int32_t max_depth) {
+  if (n_cams < 1 || width < 1 || height < 1 || max_depth < 1 || max_depth > (1 << 16)) return 0;
+  const int64_t groups = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+  return groups * max_depth * kBlock * (int64_t)sizeof(int4);
+}
+
+drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* params,
+                                   const drt_camera* cams, int32_t n_cams,
+                                   const drt_render_opts* opts, const float* adj_image,
+                                   const drt_grads* grads, void* hit_records, int64_t hit_bytes,
+                                   void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!adj_image || !grads || !hit_records)
+    return fail(DRT_EINVAL, "adj_image, grads and hit_records are required");
+  const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
+                                                    opts->max_depth);
+  if (need <= 0 || hit_bytes < need)
+    return fail(DRT_EINVAL, "hit_records of %lld bytes < %lld", (long long)hit_bytes, (long long)need);
+  if (((uintptr_t)hit_records & 15) != 0) return fail(DRT_EINVAL, "hit_records is not 16-byte aligned");
+  DGrads dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
+  dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  dr.hits = static_cast<int4*>(hit_records);
   hipError_t e = launch_render_adjoint(scene->dev, dp, dc, dr, adj_image, dg, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "render_adjoint launch");
   return ok();

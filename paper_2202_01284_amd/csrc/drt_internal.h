@@ -115,6 +115,10 @@ struct DRender {
   uint32_t flags;
   uint32_t key0, key1;
   uint64_t* stats;
+  // replayed adjoint: pass A's intersections, [workgroup][max_depth][kBlock]
+  // records of (triangle or -1, b1, b2, shadow ray unoccluded), which the
+  // replay reads instead of tracing again (null: the replay traces)
+  int4* hits;
 };
 
 // Radiance-cache record: 16 floats = position[3], direction[3], normal[3],

@@ -62,6 +62,9 @@ namespace drt {
 // io.trec (features, and for now the radiance collected so far in 13..15)
 // and its throughput to io.tbeta; io.valid marks the records written.
 // Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
+// HC (MODE_ADJOINT with intersection records): pass A stores each step's
+// closest hit and shadow-ray outcome at hrec[(k - 1) kBlock], and the replay
+// reads them back instead of tracing the same rays again.
 // ---------------------------------------------------------------------------
 enum {
   MODE_PRIMAL = 0,
@@ -74,11 +77,11 @@ enum {
   MODE_TRAIN_SELF = 7
 };
 
-template <int MODE>
+template <int MODE, bool HC = false>
 DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
                       const LdsTables& tab, int cam, int x, int y, uint64_t g_base, int n_samples,
                       f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
-                      f3& out) {
+                      f3& out, int4* hrec = nullptr) {
   constexpr bool ADJ = MODE == MODE_ADJOINT || MODE == MODE_ADJOINT_CACHED;
   constexpr bool JVP = MODE == MODE_JVP;
   // modes with a record vertex (cache queries, training records, cached replay)
@@ -127,6 +130,12 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   auto step = [&](auto replay) -> bool {
     constexpr bool RB = ADJ && decltype(replay)::value;
     constexpr bool DER = RB || JVP;  // BSDF parameter derivatives needed
+    constexpr bool HREAD = HC && MODE == MODE_ADJOINT && RB;    // replay: read the records
+    constexpr bool HWRITE = HC && MODE == MODE_ADJOINT && !RB;  // pass A: write them
+    int4* rec = (HREAD || HWRITE) ? hrec + (size_t)(k - 1) * kBlock : nullptr;
+    int rec_tri = -1;
+    float rec_b1 = 0.f, rec_b2 = 0.f;
+    bool rec_vis = false;
     bool done = false, nee = false;
     f3 nee_c = mk(0, 0, 0), nee_gt = mk(0, 0, 0), nee_t = mk(0, 0, 0), so = o, sd = d;
     float nee_gr = 0.f, stmax = 0.f;
@@ -135,10 +144,25 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     int vtex = -1, vtexel = 0, vrslot = -1;
     // ---------------- phase A: closest hit and the vertex's work
     {
-      RayPre rp = ray_pre(o, d);
       Hit h;
-      cnt.rays++;
-      const bool hit = traverse(s, rp, 0.f, INFINITY, false, h, stk, cnt);
+      bool hit;
+      if constexpr (HREAD) {
+        const int4 r = *rec;
+        h.tri = r.x;
+        h.b1 = __int_as_float(r.y);
+        h.b2 = __int_as_float(r.z);
+        hit = r.x >= 0;
+        rec_vis = r.w != 0;
+      } else {
+        RayPre rp = ray_pre(o, d);
+        cnt.rays++;
+        hit = traverse(s, rp, 0.f, INFINITY, false, h, stk, cnt);
+      }
+      if constexpr (HWRITE) {
+        rec_tri = hit ? h.tri : -1;
+        rec_b1 = h.b1;
+        rec_b2 = h.b2;
+      }
       if (!hit) {
         if (s.env_emitter >= 0) {
           int row, col;
@@ -391,10 +415,17 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     f3 gtex = mk(0, 0, 0);
     float grough = 0.f;
     if (nee) {
-      RayPre rp = ray_pre(so, sd);
-      Hit h;
-      cnt.shadow++;
-      if (!traverse(s, rp, 0.f, stmax, true, h, stk, cnt)) {
+      bool vis;
+      if constexpr (HREAD) {
+        vis = rec_vis;
+      } else {
+        RayPre rp = ray_pre(so, sd);
+        Hit h;
+        cnt.shadow++;
+        vis = !traverse(s, rp, 0.f, stmax, true, h, stk, cnt);
+      }
+      if constexpr (HWRITE) rec_vis = vis;
+      if (vis) {
         L = L + nee_c;
         if (JVP) tL = tL + nee_t;
         if (RB) {
@@ -415,6 +446,8 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
       if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
     }
+    if constexpr (HWRITE)
+      *rec = make_int4(rec_tri, __float_as_int(rec_b1), __float_as_int(rec_b2), rec_vis ? 1 : 0);
     return done;
   };
   // lanes start each path together (coherent primary rays); a lane whose
@@ -519,8 +552,9 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
 
 // Held to 128 VGPRs (4 waves per SIMD): measured faster than 3 waves at 131.
 // MODE: MODE_ADJOINT (both passes) or MODE_ADJOINT_CACHED (replay from the
-// per-sample cached estimates in io.lsamp).
-template <bool STATS, int MODE>
+// per-sample cached estimates in io.lsamp).  HC: the replay reads pass A's
+// intersection records from R.hits (this workgroup's slice).
+template <bool STATS, int MODE, bool HC = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
                                                            const float* __restrict__ adj,
                                                            DGrads G, DNrcIO io) {
@@ -543,8 +577,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (nonzero(dL)) {
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
       f3 unused;
-      render_pixel<MODE>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
-                         stack + threadIdx.x, cnt, sink, io, unused);
+      int4* hrec = nullptr;
+      if (HC) {
+        const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        hrec = R.hits + wg * R.max_depth * kBlock + threadIdx.x;
+      }
+      render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
+                             stack + threadIdx.x, cnt, sink, io, unused, hrec);
     }
   }
   __syncthreads();
@@ -809,12 +848,20 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
                                  hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
   DNrcIO none = {};
-  if (r.stats)
+  if (r.hits) {
+    if (r.stats)
+      hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT, true>), grid, dim3(kBlock), 0, st, s,
+                         p, c, r, adj, g, none);
+    else
+      hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, true>), grid, dim3(kBlock), 0, st, s,
+                         p, c, r, adj, g, none);
+  } else if (r.stats) {
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, adj, g, none);
-  else
+  } else {
     hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, adj, g, none);
+  }
   return hipGetLastError();
 }
 

@@ -238,6 +238,71 @@ def test_adjoint_parity(case):
     assert st["lrem_max"] <= 1e-4 * max(1.0, float(np.abs(adj).max()) * 100), st
 
 
+@pytest.mark.parametrize("case", list(ADJ_CASES))
+def test_adjoint_with_intersection_records(case):
+    """The replay reading pass A's intersection records: the same gradient
+    as the re-tracing replay (up to atomic order), the oracle's within the
+    gradient tolerance, no ray traced in the replay, and the replay residual
+    as small (the records reproduce pass A's path exactly)."""
+    drt = _drt()
+    make, kw = ADJ_CASES[case]
+    sc = make()
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    c = sc.cameras[0]
+    rr = kw.get("rr_depth", drt.NO_RR)
+    orc = oracle.OracleScene(sc)
+    _, amb = orc.render(spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr, seed=2, ambiguity=True)
+    adj = unambiguous_adjoint(orc, np.random.default_rng(8).normal(size=(1, c.height, c.width, 3))
+                              .astype(np.float32), amb)
+    a = torch.from_numpy(adj).cuda()
+    hits = drt.adjoint_hit_records(sc.cameras, kw["max_depth"])
+    st_h, st_p = drt.new_stats(), drt.new_stats()
+    ht, hr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, kw["spp"], kw["max_depth"], rr, seed=2,
+                                stats=st_h, hit_records=hits)
+    pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, kw["spp"], kw["max_depth"], rr, seed=2,
+                                stats=st_p)
+    st_h, st_p = drt.read_stats(st_h), drt.read_stats(st_p)
+    print(case, "rays with records", st_h["rays"], "re-traced", st_p["rays"], flush=True)
+    assert 2 * st_h["rays"] == st_p["rays"] and 2 * st_h["shadow_rays"] == st_p["shadow_rays"]
+    assert st_h["lrem_max"] <= 1e-4 * max(1.0, float(np.abs(adj).max()) * 100), st_h
+    for i, (h, p) in enumerate(zip(ht, pt)):
+        h, p = h.cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64)
+        r = np.linalg.norm(h - p) / np.linalg.norm(p)
+        print(case, f"texture {i}: records vs re-trace rel {r:.3g}", flush=True)
+        assert r <= 1e-6
+    if len(sc.roughness):
+        assert np.allclose(hr.cpu().numpy(), pr.cpu().numpy(), rtol=1e-6, atol=1e-9)
+    ot, orr = orc.adjoint(adj.astype(np.float64), spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
+                          seed=2)
+    for i, (g, o) in enumerate(zip(ht, ot)):
+        check_grad(g.cpu().numpy(), o, f"{case} records texture {i}")
+    if len(sc.roughness):
+        check_grad(hr.cpu().numpy(), orr, f"{case} records roughness")
+
+
+def test_intersection_records_multi_camera_ragged_and_size_check():
+    """Ragged tiles (W, H not multiples of 8) over three cameras, and a
+    record buffer one byte short is refused."""
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64),
+                        cameras=scenes.ring_cameras(3, 44, 27))
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    a = torch.from_numpy(np.random.default_rng(9).normal(size=(3, 27, 44, 3)).astype(np.float32)).cuda()
+    need = int(drt.lib.drt_render_adjoint_hit_bytes(3, 44, 27, 4))
+    assert need == 3 * 6 * 4 * 4 * 64 * 16
+    with pytest.raises(RuntimeError, match="hit_records"):
+        drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5,
+                           hit_records=torch.empty(need - 1, dtype=torch.uint8, device="cuda"))
+    ht, hr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5,
+                                hit_records=drt.adjoint_hit_records(sc.cameras, 4))
+    pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5)
+    h, p = ht[0].cpu().numpy().astype(np.float64), pt[0].cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(h - p) <= 1e-6 * np.linalg.norm(p)
+    assert abs(hr.item() - pr.item()) <= 1e-6 * abs(pr.item())
+
+
 def test_adjoint_matches_central_differences_on_gpu():
     """Texel gradients of <adj, I> vs central differences of the GPU primal
     with common random numbers (the adjoint's seed), h = 1e-2."""

@@ -247,6 +247,19 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_render_adjoint_cached(h, ctypes.byref(p), cams, 1, ctypes.byref(o),
                                              ctypes.byref(c), fake, fake, fake, fake, fake, 10, fake,
                                              fake, ctypes.byref(g), None) == -4
+    # intersection records of the replay: 8x8 workgroups x depth x 64 lanes x 16 B
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 3) == 16384 * 3 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2) == 2 * 2 * 3 * 2 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 0, 8, 3) == 0
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 0) == 0
+    assert drt.lib.drt_render_adjoint_hits(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
+                                           ctypes.byref(g), fake, 1 << 30, None) == -4
+    # checkpointed calls: sizes grow by 64 B per path and bounce
+    assert (drt.lib.drt_render_checkpointed_workspace_bytes(100, 4)
+            - drt.lib.drt_render_checkpointed_workspace_bytes(100, 3)) == 100 * 64
+    assert drt.lib.drt_render_checkpointed_workspace_bytes(100, 0) == 0
+    assert drt.lib.drt_render_checkpointed_forward(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
+                                                   1 << 30, fake, None) == -4
     # self-training: workspace sizes, and the scene check before anything else
     wsb = int(drt.lib.drt_nrc_collect_self_workspace_bytes(1000, 5))
     assert wsb >= 1000 * (16 * 4 + 5 * 4 + 3 * 4 + 4 * 3 * 4)
