@@ -519,6 +519,8 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
         cache.train_frame(gs, [tex], rough, cams, seed=9000 + f)
     n = R * R * SPP
     work = drt.cached_work(n, dev, sample_radiance=True)
+    hits = drt.adjoint_hit_records(cams, D)                     # both replays read intersections
+    hits_c = drt.cached_hit_records(cams, SPP, D)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
     def step(k, cached, input_grad=False):
@@ -529,11 +531,11 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
         drt.loss_l2(img, target, adj=adj)
         if cached:
             cache.adjoint(gs, [tex], rough, cams, adj, SPP, seed=2 * k + 2, grad_textures=[gtex],
-                          grad_roughness=grough, work=work, input_grad=input_grad)
+                          grad_roughness=grough, work=work, input_grad=input_grad, hit_records=hits_c)
             cache.train_frame(gs, [tex], rough, cams, seed=20000 + k)
         else:
             drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, RR, seed=2 * k + 2,
-                               grad_textures=[gtex], grad_roughness=grough)
+                               grad_textures=[gtex], grad_roughness=grough, hit_records=hits)
         drt.adam_step(tex, gtex, m_t, v_t, k + 1, lr=1e-2, lo=0.0, hi=1.0, zero_grad=True)
         drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=1e-2, lo=0.01, hi=1.0, zero_grad=True)
 
@@ -600,16 +602,21 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
     for f in range(train_frames):
         cache.train_frame(gs, [tex], rough, cams, seed=3000 + f)
     work = drt.cached_work(n_cams * R * R * spp, dev, sample_radiance=True)
+    hits = drt.adjoint_hit_records(cams, D)                     # both replays read intersections
+    hits_c = drt.cached_hit_records(cams, spp, D)
     g_c, _, t_c = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
-                                                    grad_textures=[gt], grad_roughness=gr, work=work))
+                                                    grad_textures=[gt], grad_roughness=gr, work=work,
+                                                    hit_records=hits_c))
     g_ci, _, t_ci = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
                                                       grad_textures=[gt], grad_roughness=gr, work=work,
-                                                      input_grad=True))
+                                                      input_grad=True, hit_records=hits_c))
     _, _, t_p32 = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, spp, D, RR, seed=105,
-                                                         grad_textures=[gt], grad_roughness=gr))
+                                                         grad_textures=[gt], grad_roughness=gr,
+                                                         hit_records=hits))
     spp_p = max(1, int(round(spp * t_c / t_p32)))
     g_p, _, t_p = grad(lambda gt, gr: drt.render_adjoint(gs, [tex], rough, cams, adj, spp_p, D, RR,
-                                                         seed=107, grad_textures=[gt], grad_roughness=gr))
+                                                         seed=107, grad_textures=[gt], grad_roughness=gr,
+                                                         hit_records=hits))
 
     def err(g):
         d = (g - g_ref).double()

@@ -497,14 +497,22 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
  * estimate (no second forward pass).  Gradients are ADDED to grads as in
  * drt_render_adjoint.  sample_radiance: device float [n_cams*W*H*spp][3]
  * (scratch); queries, query_ints, query_count and capacity as for
- * drt_render_forward_cached. */
+ * drt_render_forward_cached.  hit_records (optional, null: the replay traces
+ * its rays again): device scratch of at least
+ * drt_render_adjoint_cached_hit_bytes(n_cams, W, H, spp, max_depth) bytes
+ * (the intersection records of drt_render_adjoint_hits for every sample:
+ * spp times that size), 16-byte aligned; the cached pass writes them and the
+ * replay reads them instead of tracing. */
+int64_t drt_render_adjoint_cached_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
+                                            int32_t spp, int32_t max_depth);
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
                                      int32_t* query_ints, int32_t* query_count, int64_t capacity,
                                      float* sample_radiance, const float* adj_image,
-                                     const drt_grads* grads, void* hip_stream);
+                                     const drt_grads* grads, void* hit_records, int64_t hit_bytes,
+                                     void* hip_stream);
 
 #ifdef __cplusplus
 }

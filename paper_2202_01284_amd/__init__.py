@@ -168,7 +168,9 @@ _SIGS = {
     "drt_render_adjoint_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                            _c_i32, ctypes.POINTER(drt_render_opts),
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp,
-                                           _c_i64, _vp, _vp, ctypes.POINTER(drt_grads), _vp]),
+                                           _c_i64, _vp, _vp, ctypes.POINTER(drt_grads), _vp, _c_i64,
+                                           _vp]),
+    "drt_render_adjoint_cached_hit_bytes": (_c_i64, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
 }
 
 
@@ -919,11 +921,12 @@ def _check_work(q, ints, n):
 def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, weights, grid,
                           adj_image, spp: int, max_depth: int = 6, rr_depth: int = 3, seed: int = 2,
                           flags: int = 0, grad_textures=None, grad_roughness=None, work=None,
-                          stats=None, stream=None):
+                          stats=None, hit_records=None, stream=None):
     """Adds the gradient of <adj, I_cached> into grad_textures /
     grad_roughness and returns them: with the cache output detached, or,
     with FLAG_CACHE_INPUT_GRAD in flags, also through the network's albedo
-    and roughness inputs."""
+    and roughness inputs.  hit_records (cached_hit_records(...)): the replay
+    reads the cached pass's intersections instead of tracing again."""
     torch = _torch()
     _expect(adj_image, "adj_image", _image_shape(cams))
     if grad_textures is None:
@@ -957,9 +960,22 @@ def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
                                          ctypes.byref(o), ctypes.byref(c), weights.data_ptr(),
                                          grid.data_ptr(), q.data_ptr(), qid.data_ptr(),
                                          qcount.data_ptr(), q.shape[0], lsamp.data_ptr(),
-                                         adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
+                                         adj_image.data_ptr(), ctypes.byref(g),
+                                         None if hit_records is None else hit_records.data_ptr(),
+                                         0 if hit_records is None else hit_records.numel(),
+                                         _stream(stream)),
            "drt_render_adjoint_cached")
     return grad_textures, grad_roughness
+
+
+def cached_hit_records(cams, spp: int, max_depth: int, device="cuda"):
+    """Intersection-record buffer for render_adjoint_cached(hit_records=...)."""
+    torch = _torch()
+    nbytes = int(lib.drt_render_adjoint_cached_hit_bytes(len(cams), cams[0].width, cams[0].height,
+                                                         spp, max_depth))
+    if nbytes <= 0:
+        raise ValueError("no intersection records for these sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 class NrcCache:
@@ -1026,12 +1042,12 @@ class NrcCache:
 
     def adjoint(self, scene: Scene, textures, roughness, cams, adj_image, spp: int, seed: int,
                 max_depth=6, rr_depth=3, grad_textures=None, grad_roughness=None, work=None,
-                input_grad=False):
+                input_grad=False, hit_records=None):
         return render_adjoint_cached(scene, textures, roughness, cams, self.cfg, self.W,
                                      self.grid16, adj_image, spp, max_depth, rr_depth, seed,
                                      flags=FLAG_CACHE_INPUT_GRAD if input_grad else 0,
                                      grad_textures=grad_textures, grad_roughness=grad_roughness,
-                                     work=work)
+                                     work=work, hit_records=hit_records)
 
     def render(self, scene: Scene, textures, roughness, cams, spp: int, seed: int, max_depth=6,
                rr_depth=3, out=None, work=None):

@@ -1174,13 +1174,21 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
   return ok();
 }
 
+int64_t drt_render_adjoint_cached_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
+                                            int32_t spp, int32_t max_depth) {
+  if (spp < 1 || spp > (1 << 20)) return 0;
+  const int64_t one = drt_render_adjoint_hit_bytes(n_cams, width, height, max_depth);
+  return one * spp;
+}
+
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
                                      const drt_camera* cams, int32_t n_cams,
                                      const drt_render_opts* opts, const drt_nrc_config* cfg,
                                      const float* weights, const uint16_t* grid, float* queries,
                                      int32_t* query_ints, int32_t* query_count, int64_t capacity,
                                      float* sample_radiance, const float* adj_image,
-                                     const drt_grads* grads, void* hip_stream) {
+                                     const drt_grads* grads, void* hit_records, int64_t hit_bytes,
+                                     void* hip_stream) {
   DParams dp;
   DCams dc;
   DRender dr;
@@ -1195,6 +1203,14 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
+  if (hit_records) {
+    const int64_t hneed = drt_render_adjoint_cached_hit_bytes(n_cams, cams[0].width, cams[0].height,
+                                                              opts->spp, opts->max_depth);
+    if (hneed <= 0 || hit_bytes < hneed)
+      return fail(DRT_EINVAL, "hit_records of %lld bytes < %lld", (long long)hit_bytes, (long long)hneed);
+    if (((uintptr_t)hit_records & 15) != 0) return fail(DRT_EINVAL, "hit_records is not 16-byte aligned");
+    dr.hits = static_cast<int4*>(hit_records);
+  }
   DGrads dg;
   std::memset(&dg, 0, sizeof(dg));
   for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];

@@ -62,9 +62,12 @@ namespace drt {
 // io.trec (features, and for now the radiance collected so far in 13..15)
 // and its throughput to io.tbeta; io.valid marks the records written.
 // Samples g_base .. g_base + n_samples - 1 start at pixel (cam, x, y).
-// HC (MODE_ADJOINT with intersection records): pass A stores each step's
-// closest hit and shadow-ray outcome at hrec[(k - 1) kBlock], and the replay
-// reads them back instead of tracing the same rays again.
+// HC (intersection records): the tracing pass stores each step's closest
+// hit and shadow-ray outcome, and the replay reads them back instead of
+// tracing the same rays again.  MODE_ADJOINT: pass A writes, the replay of
+// the same sample reads, at hrec[(k - 1) kBlock] (reused sample after
+// sample); MODE_CACHED_SAMPLES writes and MODE_ADJOINT_CACHED (a later
+// launch) reads, at hrec[(sample max_depth + k - 1) kBlock].
 // ---------------------------------------------------------------------------
 enum {
   MODE_PRIMAL = 0,
@@ -130,9 +133,10 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   auto step = [&](auto replay) -> bool {
     constexpr bool RB = ADJ && decltype(replay)::value;
     constexpr bool DER = RB || JVP;  // BSDF parameter derivatives needed
-    constexpr bool HREAD = HC && MODE == MODE_ADJOINT && RB;    // replay: read the records
-    constexpr bool HWRITE = HC && MODE == MODE_ADJOINT && !RB;  // pass A: write them
-    int4* rec = (HREAD || HWRITE) ? hrec + (size_t)(k - 1) * kBlock : nullptr;
+    constexpr bool HREAD = HC && ((MODE == MODE_ADJOINT && RB) || MODE == MODE_ADJOINT_CACHED);
+    constexpr bool HWRITE = HC && ((MODE == MODE_ADJOINT && !RB) || MODE == MODE_CACHED_SAMPLES);
+    const size_t rec_sample = MODE == MODE_ADJOINT ? 0 : (size_t)sidx * R.max_depth;
+    int4* rec = (HREAD || HWRITE) ? hrec + (rec_sample + (size_t)(k - 1)) * kBlock : nullptr;
     int rec_tri = -1;
     float rec_b1 = 0.f, rec_b2 = 0.f;
     bool rec_vis = false;
@@ -520,8 +524,9 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 // ---------------------------------------------------------------------------
 // STATS = false compiles the counters out (they are never read).
 // MODE: MODE_PRIMAL, MODE_CACHED (paths stop at their record vertex and
-// append cache queries) or MODE_CACHED_SAMPLES (per-sample radiance, no image).
-template <bool STATS, int MODE>
+// append cache queries) or MODE_CACHED_SAMPLES (per-sample radiance, no image;
+// with HC also the intersection records of every sample).
+template <bool STATS, int MODE, bool HC = false>
 __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, DCams C, DRender R,
                                                            float* __restrict__ image, DNrcIO io) {
   __shared__ int stack[kStackDepth * kBlock];
@@ -537,8 +542,13 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
     Sink none{&tab, nullptr, nullptr};
     f3 acc;
     const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
-    render_pixel<MODE>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
-                       stack + threadIdx.x, cnt, none, io, acc);
+    int4* hrec = nullptr;
+    if (HC) {
+      const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
+    }
+    render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
+                           stack + threadIdx.x, cnt, none, io, acc, hrec);
     if (MODE != MODE_CACHED_SAMPLES) {
       const float inv = 1.0f / (float)R.spp;
       float* out = image + 3 * (((size_t)cam * H + y) * W + x);
@@ -579,8 +589,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       f3 unused;
       int4* hrec = nullptr;
       if (HC) {
+        // MODE_ADJOINT: one sample's records at a time; MODE_ADJOINT_CACHED: all of them
         const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        hrec = R.hits + wg * R.max_depth * kBlock + threadIdx.x;
+        const size_t per = (MODE == MODE_ADJOINT ? 1 : (size_t)R.spp) * R.max_depth * kBlock;
+        hrec = R.hits + wg * per + threadIdx.x;
       }
       render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
                              stack + threadIdx.x, cnt, sink, io, unused, hrec);
@@ -809,7 +821,10 @@ hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& 
                                 const DRender& r, float* image, const DNrcIO& io,
                                 hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
-  if (io.lsamp)
+  if (io.lsamp && r.hits)
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES, true>), grid, dim3(kBlock), 0,
+                       st, s, p, c, r, image, io);
+  else if (io.lsamp)
     hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES>), grid, dim3(kBlock), 0, st,
                        s, p, c, r, image, io);
   else
@@ -869,7 +884,13 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
                                         const DRender& r, const float* adj, const DGrads& g,
                                         const DNrcIO& io, hipStream_t st) {
   dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
-  if (r.stats)
+  if (r.hits && r.stats)
+    hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED, true>), grid, dim3(kBlock), 0,
+                       st, s, p, c, r, adj, g, io);
+  else if (r.hits)
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED, true>), grid, dim3(kBlock), 0,
+                       st, s, p, c, r, adj, g, io);
+  else if (r.stats)
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED>), grid, dim3(kBlock), 0, st,
                        s, p, c, r, adj, g, io);
   else

@@ -378,6 +378,27 @@ def test_cached_adjoint_input_grad_without_input_weights():
     assert abs(gr.item() - gr0.item()) <= 1e-5 * abs(gr0.item())
 
 
+def test_cached_adjoint_with_intersection_records():
+    """The cached replay reading the cached pass's intersection records:
+    the same gradient as the re-tracing replay up to atomic order (also with
+    the input term), and a record buffer one byte short is refused."""
+    drt, sc, cfg, W, grid, gs, tex, rough = _cached_adjoint_case()
+    adj = torch.from_numpy(np.random.default_rng(15).normal(size=(1, 64, 64, 3)).astype(np.float32)).cuda()
+    args = (gs, tex, rough, sc.cameras, cfg, torch.from_numpy(W).cuda(),
+            torch.from_numpy(grid.reshape(-1)).cuda(), adj, 4, 6, 3, 7)
+    hits = drt.cached_hit_records(sc.cameras, 4, 6)
+    for flags in (0, drt.FLAG_CACHE_INPUT_GRAD):
+        ht, hr = drt.render_adjoint_cached(*args, flags=flags, hit_records=hits)
+        pt, pr = drt.render_adjoint_cached(*args, flags=flags)
+        h, p = ht[0].cpu().numpy().astype(np.float64), pt[0].cpu().numpy().astype(np.float64)
+        r = np.linalg.norm(h - p) / np.linalg.norm(p)
+        print("cached replay with records vs re-trace, flags", flags, "rel", r, flush=True)
+        assert r <= 1e-6
+        assert abs(hr.item() - pr.item()) <= 1e-6 * abs(pr.item())
+    with pytest.raises(RuntimeError, match="hit_records"):
+        drt.render_adjoint_cached(*args, hit_records=hits[:-1])
+
+
 def test_cached_adjoint_zero_network_equals_plain_depth3():
     """With a zero network the cached adjoint is the plain adjoint at max
     depth 3 on the same streams (GPU against GPU)."""

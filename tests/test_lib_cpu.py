@@ -246,7 +246,10 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
                                   fake, None) == -1
     assert drt.lib.drt_render_adjoint_cached(h, ctypes.byref(p), cams, 1, ctypes.byref(o),
                                              ctypes.byref(c), fake, fake, fake, fake, fake, 10, fake,
-                                             fake, ctypes.byref(g), None) == -4
+                                             fake, ctypes.byref(g), None, 0, None) == -4
+    assert (drt.lib.drt_render_adjoint_cached_hit_bytes(1, 64, 64, 4, 6)
+            == 4 * drt.lib.drt_render_adjoint_hit_bytes(1, 64, 64, 6))
+    assert drt.lib.drt_render_adjoint_cached_hit_bytes(1, 64, 64, 0, 6) == 0
     # intersection records of the replay: 8x8 workgroups x depth x 64 lanes x 16 B
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 3) == 16384 * 3 * 64 * 16
     assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2) == 2 * 2 * 3 * 2 * 64 * 16
