@@ -663,8 +663,14 @@ def loss_l2(img, target, adj=None, stream=None):
 def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9,
               beta2: float = 0.99, eps: float = 1e-8, lo: float = -np.inf, hi: float = np.inf,
               zero_grad: bool = False, half_out=None, stream=None):
+    torch = _torch()
     for t, w in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
         _expect(t, w)
+        if t.numel() != param.numel():
+            raise ValueError(f"{w} has {t.numel()} elements, param {param.numel()}")
+    if half_out is not None and not (half_out.is_cuda and half_out.dtype == torch.float16 and
+                                     half_out.is_contiguous() and half_out.numel() == param.numel()):
+        raise ValueError("half_out must be a contiguous float16 device tensor of param's size")
     o = drt_adam_opts()
     o.lr, o.beta1, o.beta2, o.eps = lr, beta1, beta2, eps
     o.step = int(step)

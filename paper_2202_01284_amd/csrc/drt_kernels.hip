@@ -779,24 +779,63 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
   if (threadIdx.x == 0) loss[0] = (float)(red[0] / (double)n);
 }
 
+struct AdamArgs {
+  float lr, b1, b2, eps, c1, c2, lo, hi;
+};
+// one parameter: moments updated in place, the new (clamped) value returned
+DEV float adam1(const AdamArgs& a, float pi, float gi, float& mi, float& vi) {
+  mi = a.b1 * mi + (1.0f - a.b1) * gi;
+  vi = a.b2 * vi + (1.0f - a.b2) * gi * gi;
+  const float x = pi - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+  return fminf(fmaxf(x, a.lo), a.hi);
+}
+
+// Scalar form: parameters [i0, n) (the vector form's tail, or all of them
+// when the arrays are not 16-byte aligned).
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
-                                              int64_t n, float lr, float b1, float b2, float eps,
-                                              float c1, float c2, float lo, float hi, int zero,
+                                              int64_t i0, int64_t n, AdamArgs a, int zero,
                                               uint16_t* __restrict__ half_out) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t i = i0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * 256;
   for (; i < n; i += stride) {
-    float gi = g[i];
+    float gi = g[i], mi = m[i], vi = v[i];
     if (zero) g[i] = 0.f;
-    float mi = b1 * m[i] + (1.0f - b1) * gi;
-    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float x = adam1(a, p[i], gi, mi, vi);
     m[i] = mi;
     v[i] = vi;
-    float x = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    x = fminf(fmaxf(x, lo), hi);
     p[i] = x;
     if (half_out) half_out[i] = __half_as_ushort(__float2half_rn(x));
+  }
+}
+
+// Vector form: four parameters per thread and iteration (16-byte loads and
+// stores), parameters [0, 4 n4).
+__global__ __launch_bounds__(256) void k_adam4(float4* __restrict__ p, float4* __restrict__ g,
+                                               float4* __restrict__ m, float4* __restrict__ v,
+                                               int64_t n4, AdamArgs a, int zero,
+                                               uint2* __restrict__ half_out) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (; i < n4; i += stride) {
+    const float4 gi = g[i], pi = p[i];
+    float4 mi = m[i], vi = v[i];
+    if (zero) g[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 x;
+    x.x = adam1(a, pi.x, gi.x, mi.x, vi.x);
+    x.y = adam1(a, pi.y, gi.y, mi.y, vi.y);
+    x.z = adam1(a, pi.z, gi.z, mi.z, vi.z);
+    x.w = adam1(a, pi.w, gi.w, mi.w, vi.w);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] = x;
+    if (half_out) {
+      const uint32_t lo = __half_as_ushort(__float2half_rn(x.x)) |
+                          ((uint32_t)__half_as_ushort(__float2half_rn(x.y)) << 16);
+      const uint32_t hi = __half_as_ushort(__float2half_rn(x.z)) |
+                          ((uint32_t)__half_as_ushort(__float2half_rn(x.w)) << 16);
+      half_out[i] = make_uint2(lo, hi);
+    }
   }
 }
 
@@ -935,13 +974,27 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, int64_t n, float* 
 
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n,
                        const drt_adam_opts& o, hipStream_t st) {
-  double c1 = 1.0 - pow((double)o.beta1, (double)o.step);
-  double c2 = 1.0 - pow((double)o.beta2, (double)o.step);
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p, g, m, v, n, o.lr,
-                     o.beta1, o.beta2, o.eps, (float)c1, (float)c2, o.lo, o.hi, o.zero_grad,
-                     o.half_out);
+  const double c1 = 1.0 - pow((double)o.beta1, (double)o.step);
+  const double c2 = 1.0 - pow((double)o.beta2, (double)o.step);
+  const AdamArgs a = {o.lr, o.beta1, o.beta2, o.eps, (float)c1, (float)c2, o.lo, o.hi};
+  auto aligned = [](const void* q, uintptr_t k) { return ((uintptr_t)q & (k - 1)) == 0; };
+  const bool vec = aligned(p, 16) && aligned(g, 16) && aligned(m, 16) && aligned(v, 16) &&
+                   (!o.half_out || aligned(o.half_out, 8));
+  const int64_t n4 = vec ? n / 4 : 0;
+  if (n4 > 0) {
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_adam4, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<float4*>(p), reinterpret_cast<float4*>(g),
+                       reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n4, a,
+                       o.zero_grad, reinterpret_cast<uint2*>(o.half_out));
+  }
+  if (4 * n4 < n) {
+    int64_t blocks = (n - 4 * n4 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p, g, m, v, 4 * n4, n, a,
+                       o.zero_grad, o.half_out);
+  }
   return hipGetLastError();
 }
 

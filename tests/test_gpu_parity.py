@@ -360,6 +360,23 @@ def test_loss_and_adam_vs_oracle():
         drt.adam_step(pt, gt, m, v, t, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8, lo=0.0, hi=1.0)
         oracle.adam(po, g.astype(np.float64), mo, vo, 1e-2, 0.9, 0.99, 1e-8, t, 0.0, 1.0)
     np.testing.assert_allclose(pt.cpu().numpy(), po, rtol=0, atol=2e-6)
+    # arrays that start one element past a 16-byte boundary take the scalar
+    # form; both forms write the FP16 copy
+    base = torch.from_numpy(np.concatenate([[0.0], p]).astype(np.float32)).cuda()
+    gb = torch.from_numpy(np.concatenate([[0.0], g]).astype(np.float32)).cuda()
+    mb, vb = torch.zeros_like(base), torch.zeros_like(base)
+    half = torch.empty(n, dtype=torch.float16, device="cuda")
+    po, mo, vo = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in (1, 2):
+        drt.adam_step(base[1:], gb[1:], mb[1:], vb[1:], t, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8,
+                      lo=0.0, hi=1.0, half_out=half)
+        oracle.adam(po, g.astype(np.float64), mo, vo, 1e-2, 0.9, 0.99, 1e-8, t, 0.0, 1.0)
+    np.testing.assert_allclose(base[1:].cpu().numpy(), po, rtol=0, atol=2e-6)
+    np.testing.assert_array_equal(half.cpu().numpy(), base[1:].cpu().numpy().astype(np.float16))
+    half2 = torch.empty(n, dtype=torch.float16, device="cuda")
+    drt.adam_step(pt, gt, m, v, 4, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8, lo=0.0, hi=1.0,
+                  half_out=half2)
+    np.testing.assert_array_equal(half2.cpu().numpy(), pt.cpu().numpy().astype(np.float16))
 
 
 def test_empty_and_degenerate_inputs():
