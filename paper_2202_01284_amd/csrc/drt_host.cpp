@@ -1135,7 +1135,7 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
   hipError_t e = launch_zero(loss, 1, stream);
   if (e != hipSuccess) return hip_fail(e, "zero launch");
   if (n == 0) return ok();
-  e = launch_nrc_train2(net, weights, records, valid, count, n, workspace, dW, dgrid, loss, stream);
+  e = launch_nrc_train(net, weights, records, valid, count, n, workspace, dW, dgrid, loss, stream);
   if (e != hipSuccess) return hip_fail(e, "nrc_train launch");
   return ok();
 }

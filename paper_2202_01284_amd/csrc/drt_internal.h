@@ -248,7 +248,7 @@ hipError_t launch_nrc_input_grad(const DNrcNet& net, const float* W, const float
 hipError_t launch_nrc_grid_backward(const DNrcNet& net, const float* rec, const float* dx,
                                     int64_t n, float* dgrid, hipStream_t st);
 int64_t nrc_train_workspace_bytes(int64_t n);
-hipError_t launch_nrc_train2(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
                              const int* count, int64_t n, void* ws, float* dW, float* dgrid,
                              float* loss, hipStream_t st);
 

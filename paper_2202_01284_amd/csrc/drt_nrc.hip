@@ -947,7 +947,7 @@ hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, 
   return hipGetLastError();
 }
 
-hipError_t launch_nrc_train2(const DNrcNet& net, const float* W, const float* rec, const int* valid,
+hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec, const int* valid,
                              const int* count, int64_t n, void* ws, float* dW, float* dgrid,
                              float* loss, hipStream_t st) {
   const int64_t n_tiles = (n + 15) / 16;
