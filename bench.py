@@ -93,7 +93,7 @@ def main():
     ws = torch.empty(int(drt.lib.drt_loss_workspace_floats(img.numel())), dtype=torch.float32,
                      device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
-    hits = drt.adjoint_hit_records(cams, D)
+    hits = drt.adjoint_hit_records(cams, SPP, D)
     ev = []
 
     def step(k, timed):
@@ -280,7 +280,7 @@ def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
         mk = timed(lambda: (drt.render_forward(gs, tex, rough, cams, spp, depth, seed=1, out=img),
                             drt.render_adjoint(gs, tex, rough, cams, a, spp, depth, seed=2,
                                                grad_textures=gt, grad_roughness=gr)))
-        hits = drt.adjoint_hit_records(cams, depth)
+        hits = drt.adjoint_hit_records(cams, spp, depth)
         mkr = timed(lambda: (drt.render_forward(gs, tex, rough, cams, spp, depth, seed=1, out=img),
                              drt.render_adjoint(gs, tex, rough, cams, a, spp, depth, seed=2,
                                                 grad_textures=gt, grad_roughness=gr,
@@ -372,7 +372,7 @@ def aux_primal_1m(drt, scenes, torch):
     torch.cuda.synchronize()
     adj_wf = e0.elapsed_time(e1)
     del ws
-    hits = drt.adjoint_hit_records(sc.cameras, 6)
+    hits = drt.adjoint_hit_records(sc.cameras, 16, 6)
     drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 16, 6, 3, seed=5, grad_textures=gt,
                        grad_roughness=gr, hit_records=hits)
     e0.record()
@@ -519,7 +519,7 @@ def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps
         cache.train_frame(gs, [tex], rough, cams, seed=9000 + f)
     n = R * R * SPP
     work = drt.cached_work(n, dev, sample_radiance=True)
-    hits = drt.adjoint_hit_records(cams, D)                     # both replays read intersections
+    hits = drt.adjoint_hit_records(cams, SPP, D)                # both replays read intersections
     hits_c = drt.cached_hit_records(cams, SPP, D)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
@@ -602,7 +602,7 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
     for f in range(train_frames):
         cache.train_frame(gs, [tex], rough, cams, seed=3000 + f)
     work = drt.cached_work(n_cams * R * R * spp, dev, sample_radiance=True)
-    hits = drt.adjoint_hit_records(cams, D)                     # both replays read intersections
+    hits = drt.adjoint_hit_records(cams, spp, D)                # both replays read intersections
     hits_c = drt.cached_hit_records(cams, spp, D)
     g_c, _, t_c = grad(lambda gt, gr: cache.adjoint(gs, [tex], rough, cams, adj, spp, seed=103,
                                                     grad_textures=[gt], grad_roughness=gr, work=work,

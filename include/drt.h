@@ -222,13 +222,14 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
  * its shadow ray's outcome in hit_records, and the replay reads them back
  * instead of tracing the same rays again (the replay's sampling, L_rem
  * subtraction and scatter are unchanged, so are the gradients, up to atomic
- * order).  The records are reused sample after sample: their size depends
- * on the image and max_depth, not on spp --
- * drt_render_adjoint_hit_bytes(n_cams, W, H, max_depth) = workgroups of 8x8
- * pixels x max_depth x 64 lanes x 16 B (0 for invalid sizes).  hit_records:
- * device scratch of at least that many bytes, 16-byte aligned, overwritten;
- * calls that overlap on one buffer race. */
-int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
+ * order).  The records are reused sample after sample: their size grows
+ * with the image and max_depth, not with spp --
+ * drt_render_adjoint_hit_bytes(n_cams, W, H, spp, max_depth) = workgroups
+ * (8x8 pixels, each tile's samples split over min(spp, 4) of them) x
+ * max_depth x 64 lanes x 16 B (0 for invalid sizes).  hit_records: device
+ * scratch of at least that many bytes, 16-byte aligned, overwritten; calls
+ * that overlap on one buffer race. */
+int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t spp,
                                      int32_t max_depth);
 drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* params,
                                    const drt_camera* cams, int32_t n_cams,
@@ -500,8 +501,8 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
  * drt_render_forward_cached.  hit_records (optional, null: the replay traces
  * its rays again): device scratch of at least
  * drt_render_adjoint_cached_hit_bytes(n_cams, W, H, spp, max_depth) bytes
- * (the intersection records of drt_render_adjoint_hits for every sample:
- * spp times that size), 16-byte aligned; the cached pass writes them and the
+ * (records for every sample: workgroups of 8x8 pixels x spp x max_depth x
+ * 64 lanes x 16 B), 16-byte aligned; the cached pass writes them and the
  * replay reads them instead of tracing. */
 int64_t drt_render_adjoint_cached_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
                                             int32_t spp, int32_t max_depth);

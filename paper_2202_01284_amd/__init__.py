@@ -121,7 +121,7 @@ _SIGS = {
     "drt_render_adjoint_wavefront": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                               _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                               ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
-    "drt_render_adjoint_hit_bytes": (_c_i64, [_c_i32, _c_i32, _c_i32, _c_i32]),
+    "drt_render_adjoint_hit_bytes": (_c_i64, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
     "drt_render_adjoint_hits": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                          _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                          ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
@@ -458,10 +458,11 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
     return grad_textures, grad_roughness
 
 
-def adjoint_hit_records(cams, max_depth: int, device="cuda"):
+def adjoint_hit_records(cams, spp: int, max_depth: int, device="cuda"):
     """Intersection-record buffer for render_adjoint(hit_records=...)."""
     torch = _torch()
-    nbytes = int(lib.drt_render_adjoint_hit_bytes(len(cams), cams[0].width, cams[0].height, max_depth))
+    nbytes = int(lib.drt_render_adjoint_hit_bytes(len(cams), cams[0].width, cams[0].height, spp,
+                                                  max_depth))
     if nbytes <= 0:
         raise ValueError("no intersection records for these sizes")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)

@@ -745,11 +745,19 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
   return ok();
 }
 
-int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
-                                     int32_t max_depth) {
+// One record slot (max_depth x kBlock x 16 B) per workgroup of 8x8 pixels;
+// 0 for invalid sizes.
+static int64_t record_slot_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t max_depth) {
   if (n_cams < 1 || width < 1 || height < 1 || max_depth < 1 || max_depth > (1 << 16)) return 0;
   const int64_t groups = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   return groups * max_depth * kBlock * (int64_t)sizeof(int4);
+}
+
+int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t spp,
+                                     int32_t max_depth) {
+  if (spp < 1) return 0;
+  // the launch splits each tile's samples over adjoint_split(spp) workgroups
+  return record_slot_bytes(n_cams, width, height, max_depth) * adjoint_split(spp);
 }
 
 drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* params,
@@ -765,7 +773,7 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
   if (!adj_image || !grads || !hit_records)
     return fail(DRT_EINVAL, "adj_image, grads and hit_records are required");
   const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
-                                                    opts->max_depth);
+                                                    opts->spp, opts->max_depth);
   if (need <= 0 || hit_bytes < need)
     return fail(DRT_EINVAL, "hit_records of %lld bytes < %lld", (long long)hit_bytes, (long long)need);
   if (((uintptr_t)hit_records & 15) != 0) return fail(DRT_EINVAL, "hit_records is not 16-byte aligned");
@@ -1177,8 +1185,7 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
 int64_t drt_render_adjoint_cached_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
                                             int32_t spp, int32_t max_depth) {
   if (spp < 1 || spp > (1 << 20)) return 0;
-  const int64_t one = drt_render_adjoint_hit_bytes(n_cams, width, height, max_depth);
-  return one * spp;
+  return record_slot_bytes(n_cams, width, height, max_depth) * spp;
 }
 
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,

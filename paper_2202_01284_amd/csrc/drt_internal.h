@@ -22,6 +22,12 @@ constexpr int kMaxInteriorDepth = 24;
 constexpr int kBlock = 64;             // threads per workgroup of the megakernels (one wave)
 constexpr int kTile = 8;               // workgroup = 8 x 8 pixel tile
 constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
+// The replayed adjoint splits each tile's samples over this many workgroups
+// (contiguous sample ranges): four times more, shorter waves leave less of
+// the GPU idle at the end of the launch.  The launch and the size of the
+// intersection records both take the factor from adjoint_split().
+constexpr int kAdjointSplit = 4;
+__host__ __device__ inline int adjoint_split(int spp) { return spp < kAdjointSplit ? spp : kAdjointSplit; }
 
 // Four-child BVH node, 128 bytes (one L2 line): per child its box (lo xyz,
 // hi xyz; two children per three float4, so the boxes are loaded and tested
@@ -117,7 +123,8 @@ struct DRender {
   uint64_t* stats;
   // replayed adjoint: pass A's intersections, [workgroup][max_depth][kBlock]
   // records of (triangle or -1, b1, b2, shadow ray unoccluded), which the
-  // replay reads instead of tracing again (null: the replay traces)
+  // replay reads instead of tracing again (null: the replay traces); the
+  // cached replay's: [workgroup][spp][max_depth][kBlock]
   int4* hits;
 };
 

@@ -578,9 +578,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int W = C.width, H = C.height;
   const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
   const int y = blockIdx.y * kTile + (threadIdx.x / kTile);
-  const int cam = blockIdx.z;
+  // blockIdx.z = camera x split + part: this workgroup replays samples [s0, s1)
+  const int split = (int)gridDim.z / C.n;
+  const int cam = blockIdx.z / split, part = blockIdx.z % split;
+  const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
   Counters cnt = {};
-  if (x < W && y < H) {
+  if (x < W && y < H && s1 > s0) {
     const size_t pix = ((size_t)cam * H + y) * W + x;
     const float inv = 1.0f / (float)R.spp;
     f3 dL = mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const size_t per = (MODE == MODE_ADJOINT ? 1 : (size_t)R.spp) * R.max_depth * kBlock;
         hrec = R.hits + wg * per + threadIdx.x;
       }
-      render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, dL,
+      render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0, dL,
                              stack + threadIdx.x, cnt, sink, io, unused, hrec);
     }
   }
@@ -900,7 +903,8 @@ hipError_t launch_nrc_self_targets(const DNrcIO& io, int64_t n_paths, hipStream_
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile,
+            c.n * adjoint_split(r.spp));
   DNrcIO none = {};
   if (r.hits) {
     if (r.stats)

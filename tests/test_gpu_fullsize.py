@@ -60,7 +60,7 @@ def test_reverse_config_adjoint_sparse_pixels(c3):
     # the bench's launch: the replay reads pass A's intersection records
     gt, gr = drt.render_adjoint(gs, tex, rough, sc.cameras,
                                 torch.from_numpy(adj.reshape(1, 1024, 1024, 3)).cuda(), 16, 3, seed=4,
-                                hit_records=drt.adjoint_hit_records(sc.cameras, 3))
+                                hit_records=drt.adjoint_hit_records(sc.cameras, 16, 3))
     ot, orr = orc.adjoint(vals.astype(np.float32).astype(np.float64), spp=16, max_depth=3, seed=4,
                           pixel_ids=ids)
     check_grad(gt[0].cpu().numpy(), ot[0], "4096^2 texture gradient")
@@ -77,7 +77,7 @@ def test_reverse_config_records_equal_retrace_dense(c3):
     rough = torch.from_numpy(sc.roughness).cuda()
     a = torch.from_numpy(np.random.default_rng(3).normal(size=(1, 1024, 1024, 3)).astype(np.float32)).cuda()
     ht, hr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 16, 3, seed=6,
-                                hit_records=drt.adjoint_hit_records(sc.cameras, 3))
+                                hit_records=drt.adjoint_hit_records(sc.cameras, 16, 3))
     pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 16, 3, seed=6)
     h, p = ht[0].double(), pt[0].double()
     r = float((h - p).norm() / p.norm())

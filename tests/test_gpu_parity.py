@@ -256,7 +256,7 @@ def test_adjoint_with_intersection_records(case):
     adj = unambiguous_adjoint(orc, np.random.default_rng(8).normal(size=(1, c.height, c.width, 3))
                               .astype(np.float32), amb)
     a = torch.from_numpy(adj).cuda()
-    hits = drt.adjoint_hit_records(sc.cameras, kw["max_depth"])
+    hits = drt.adjoint_hit_records(sc.cameras, kw["spp"], kw["max_depth"])
     st_h, st_p = drt.new_stats(), drt.new_stats()
     ht, hr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, kw["spp"], kw["max_depth"], rr, seed=2,
                                 stats=st_h, hit_records=hits)
@@ -290,13 +290,13 @@ def test_intersection_records_multi_camera_ragged_and_size_check():
     gs = drt.Scene(sc)
     tex, rough = _params(sc)
     a = torch.from_numpy(np.random.default_rng(9).normal(size=(3, 27, 44, 3)).astype(np.float32)).cuda()
-    need = int(drt.lib.drt_render_adjoint_hit_bytes(3, 44, 27, 4))
-    assert need == 3 * 6 * 4 * 4 * 64 * 16
+    need = int(drt.lib.drt_render_adjoint_hit_bytes(3, 44, 27, 3, 4))
+    assert need == 3 * 6 * 4 * 3 * 4 * 64 * 16
     with pytest.raises(RuntimeError, match="hit_records"):
         drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5,
                            hit_records=torch.empty(need - 1, dtype=torch.uint8, device="cuda"))
     ht, hr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5,
-                                hit_records=drt.adjoint_hit_records(sc.cameras, 4))
+                                hit_records=drt.adjoint_hit_records(sc.cameras, 3, 4))
     pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5)
     h, p = ht[0].cpu().numpy().astype(np.float64), pt[0].cpu().numpy().astype(np.float64)
     assert np.linalg.norm(h - p) <= 1e-6 * np.linalg.norm(p)

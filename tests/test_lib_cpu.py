@@ -248,13 +248,16 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
                                              ctypes.byref(c), fake, fake, fake, fake, fake, 10, fake,
                                              fake, ctypes.byref(g), None, 0, None) == -4
     assert (drt.lib.drt_render_adjoint_cached_hit_bytes(1, 64, 64, 4, 6)
-            == 4 * drt.lib.drt_render_adjoint_hit_bytes(1, 64, 64, 6))
+            == 4 * 8 * 8 * 6 * 64 * 16)
     assert drt.lib.drt_render_adjoint_cached_hit_bytes(1, 64, 64, 0, 6) == 0
     # intersection records of the replay: 8x8 workgroups x depth x 64 lanes x 16 B
-    assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 3) == 16384 * 3 * 64 * 16
-    assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2) == 2 * 2 * 3 * 2 * 64 * 16
-    assert drt.lib.drt_render_adjoint_hit_bytes(1, 0, 8, 3) == 0
-    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 0) == 0
+    # (each tile's samples split over min(spp, 4) workgroups)
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 16, 3) == 16384 * 4 * 3 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2, 2) == 2 * 2 * 3 * 2 * 2 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 1, 3) == 3 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 0, 8, 4, 3) == 0
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 4, 0) == 0
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 0, 3) == 0
     assert drt.lib.drt_render_adjoint_hits(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
                                            ctypes.byref(g), fake, 1 << 30, None) == -4
     # checkpointed calls: sizes grow by 64 B per path and bounce
