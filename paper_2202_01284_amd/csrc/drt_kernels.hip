@@ -536,9 +536,15 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
   const int W = C.width, H = C.height;
   const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
   const int y = blockIdx.y * kTile + (threadIdx.x / kTile);
-  const int cam = blockIdx.z;
+  // MODE_PRIMAL may split a tile's samples over two workgroups (blockIdx.z =
+  // camera x 2 + half), which then add their halves onto a zeroed image:
+  // two addends onto zero give the same sum in either order, so the image
+  // stays deterministic
+  const int split = (int)gridDim.z / C.n;
+  const int cam = blockIdx.z / split, part = blockIdx.z % split;
+  const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
   Counters cnt = {};
-  if (x < W && y < H) {
+  if (x < W && y < H && s1 > s0) {
     Sink none{&tab, nullptr, nullptr};
     f3 acc;
     const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
@@ -547,14 +553,20 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
       const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
       hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
     }
-    render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
-                           stack + threadIdx.x, cnt, none, io, acc, hrec);
+    render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
+                           mk(0, 0, 0), stack + threadIdx.x, cnt, none, io, acc, hrec);
     if (MODE != MODE_CACHED_SAMPLES) {
       const float inv = 1.0f / (float)R.spp;
       float* out = image + 3 * (((size_t)cam * H + y) * W + x);
-      out[0] = acc.x * inv;
-      out[1] = acc.y * inv;
-      out[2] = acc.z * inv;
+      if (split == 1) {
+        out[0] = acc.x * inv;
+        out[1] = acc.y * inv;
+        out[2] = acc.z * inv;
+      } else {
+        atomicAdd(out, acc.x * inv);
+        atomicAdd(out + 1, acc.y * inv);
+        atomicAdd(out + 2, acc.z * inv);
+      }
     }
   }
   if constexpr (STATS) flush_counters(R, cnt);
@@ -848,7 +860,13 @@ __global__ __launch_bounds__(256) void k_adam4(float4* __restrict__ p, float4* _
 // ---------------------------------------------------------------------------
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, float* image, hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  // two workgroups per tile (sample halves) adding onto a zeroed image
+  const int split = r.spp >= 2 ? 2 : 1;
+  if (split > 1) {
+    hipError_t e = launch_zero(image, 3 * (int64_t)c.n * c.width * c.height, st);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n * split);
   DNrcIO none = {};
   if (r.stats)
     hipLaunchKernelGGL((k_render_forward<true, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p, c,

@@ -493,7 +493,9 @@ def test_degenerate_cache_inputs():
     Wt, gt = torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda()
     img = drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wt, gt, spp=4, seed=5)
     ref = drt.render_forward(gs, tex, None, sc.cameras, 4, 6, 3, seed=5)
-    np.testing.assert_array_equal(img.cpu().numpy(), ref.cpu().numpy())
+    # same samples; the primal adds its two sample halves, the cached render
+    # its samples in one sum, so pixels may differ in the last bit
+    np.testing.assert_allclose(img.cpu().numpy(), ref.cpu().numpy(), rtol=1e-6, atol=1e-9)
     rec, valid, count = drt.nrc_collect(gs, tex, None, sc.cameras, cfg, 1000, seed=3)
     assert int(count.item()) == 0 and int(valid.sum().item()) == 0
     dW = torch.zeros(17600, device="cuda")
