@@ -167,6 +167,9 @@ FWD_CASES = {
     "furnace_cube_nonee": (lambda: scenes.furnace_cube(), dict(spp=2, max_depth=5, flags=1)),
     "lit_plane": (lambda: scenes.lit_plane(), dict(spp=2, max_depth=3)),
     "zoo_rr": (lambda: scenes.bsdf_zoo(width=64, height=64), dict(spp=4, max_depth=6, rr_depth=3)),
+    # odd spp: the primal's two sample halves are 2 + 3 samples
+    "cornell_spp5": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=40,
+                                            height=24), dict(spp=5, max_depth=3)),
 }
 
 
@@ -205,6 +208,9 @@ ADJ_CASES = {
     "cornell_conductor": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64)),
                           dict(spp=4, max_depth=3)),
     "zoo": (lambda: scenes.bsdf_zoo(width=48, height=48), dict(spp=4, max_depth=6, rr_depth=3)),
+    # odd spp and ragged tiles: the adjoint's four sample ranges are 1, 1, 1, 2
+    "cornell_spp5": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=40,
+                                            height=24), dict(spp=5, max_depth=3)),
 }
 
 
