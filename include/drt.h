@@ -222,11 +222,14 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
  * its shadow ray's outcome in hit_records, and the replay reads them back
  * instead of tracing the same rays again (the replay's sampling, L_rem
  * subtraction and scatter are unchanged, so are the gradients, up to atomic
- * order).  The records are reused sample after sample: their size grows
- * with the image and max_depth, not with spp --
- * drt_render_adjoint_hit_bytes(n_cams, W, H, spp, max_depth) = workgroups
- * (8x8 pixels, each tile's samples split over min(spp, 4) of them) x
- * max_depth x 64 lanes x 16 B (0 for invalid sizes).  hit_records: device
+ * order).  The launch runs as many workgroups as the current device holds
+ * at once; they take the work units (an 8x8 tile and one of min(spp, 4)
+ * ranges of its samples) from a counter, and each keeps its records in its own
+ * slot, reused sample after sample -- so the size depends on the device and
+ * max_depth, not on spp and, past the device's size, not on the image:
+ * drt_render_adjoint_hit_bytes(n_cams, W, H, spp, max_depth) = 256 B
+ * (counter) + min(resident workgroups, work units) x max_depth x 64 lanes x
+ * 16 B, for the current device (0 for invalid sizes).  hit_records: device
  * scratch of at least that many bytes, 16-byte aligned, overwritten; calls
  * that overlap on one buffer race. */
 int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t spp,

@@ -582,6 +582,7 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   dr->key1 = (uint32_t)(o->seed >> 32);
   dr->stats = o->stats;
   dr->hits = nullptr;
+  dr->items = nullptr;
   return DRT_OK;
 }
 
@@ -753,11 +754,21 @@ static int64_t record_slot_bytes(int32_t n_cams, int32_t width, int32_t height, 
   return groups * max_depth * kBlock * (int64_t)sizeof(int4);
 }
 
+// Record buffer of the replayed adjoint: a 256-byte header (the persistent
+// workgroups' work counter), then one slot per persistent workgroup -- as
+// many as are resident on the current device, at most one per work unit
+// (tile x sample range).
+static constexpr int64_t kHitHeader = 256;
 int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t spp,
                                      int32_t max_depth) {
   if (spp < 1) return 0;
-  // the launch splits each tile's samples over adjoint_split(spp) workgroups
-  return record_slot_bytes(n_cams, width, height, max_depth) * adjoint_split(spp);
+  const int64_t per_tile = record_slot_bytes(n_cams, width, height, max_depth);
+  if (per_tile <= 0) return 0;
+  const int64_t tiles = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+  const int64_t units = tiles * adjoint_split(spp);
+  const int resident = adjoint_resident_groups();
+  const int64_t slots = resident > 0 && resident < units ? resident : units;
+  return kHitHeader + per_tile / tiles * slots;
 }
 
 drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* params,
@@ -781,7 +792,8 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
   std::memset(&dg, 0, sizeof(dg));
   for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
   dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
-  dr.hits = static_cast<int4*>(hit_records);
+  dr.items = static_cast<uint32_t*>(hit_records);
+  dr.hits = reinterpret_cast<int4*>(static_cast<char*>(hit_records) + kHitHeader);
   hipError_t e = launch_render_adjoint(scene->dev, dp, dc, dr, adj_image, dg, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "render_adjoint launch");
   return ok();

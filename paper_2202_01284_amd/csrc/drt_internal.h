@@ -126,6 +126,9 @@ struct DRender {
   // replay reads instead of tracing again (null: the replay traces); the
   // cached replay's: [workgroup][spp][max_depth][kBlock]
   int4* hits;
+  // replayed adjoint with records: work counter of its persistent workgroups
+  // (zeroed before the launch; it lives in the caller's record buffer)
+  uint32_t* items;
 };
 
 // Radiance-cache record: 16 floats = position[3], direction[3], normal[3],
@@ -201,6 +204,10 @@ hipError_t launch_nrc_self_targets(const DNrcIO& io, int64_t n_paths, hipStream_
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st);
+// Workgroups of the persistent replayed adjoint (with records) on the current
+// device: as many as can be resident at once (0 if the device cannot be
+// queried).  The launch and the record size both use it.
+int adjoint_resident_groups();
 hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
                                         const DRender& r, const float* adj, const DGrads& g,
                                         const DNrcIO& io, hipStream_t st);

@@ -576,6 +576,11 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
 // MODE: MODE_ADJOINT (both passes) or MODE_ADJOINT_CACHED (replay from the
 // per-sample cached estimates in io.lsamp).  HC: the replay reads pass A's
 // intersection records from R.hits (this workgroup's slice).
+// Work units: (8x8 tile, sample range) -- a tile's samples split into
+// adjoint_split(spp) ranges.  MODE_ADJOINT with records runs persistent
+// workgroups (as many as are resident at once) that take the units from the
+// counter R.items until none is left, each with one record slot; otherwise
+// the grid has one workgroup per unit (blockIdx.z = camera x split + part).
 template <bool STATS, int MODE, bool HC = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
                                                            const float* __restrict__ adj,
@@ -587,30 +592,55 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   load_tables(tab, s, P, &G);
   if (threadIdx.x < kMaxRoughLds) rough_acc[threadIdx.x] = 0.f;
   __syncthreads();
+  constexpr bool PERSIST = HC && MODE == MODE_ADJOINT;
+  __shared__ int unit_s;
   const int W = C.width, H = C.height;
-  const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
-  const int y = blockIdx.y * kTile + (threadIdx.x / kTile);
-  // blockIdx.z = camera x split + part: this workgroup replays samples [s0, s1)
-  const int split = (int)gridDim.z / C.n;
-  const int cam = blockIdx.z / split, part = blockIdx.z % split;
-  const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
+  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  const int split = PERSIST ? adjoint_split(R.spp) : (int)gridDim.z / C.n;
+  const int units = PERSIST ? tiles_x * tiles_y * C.n * split : 1;
   Counters cnt = {};
-  if (x < W && y < H && s1 > s0) {
-    const size_t pix = ((size_t)cam * H + y) * W + x;
-    const float inv = 1.0f / (float)R.spp;
-    f3 dL = mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
-    if (nonzero(dL)) {
-      Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
-      f3 unused;
-      int4* hrec = nullptr;
-      if (HC) {
-        // MODE_ADJOINT: one sample's records at a time; MODE_ADJOINT_CACHED: all of them
-        const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        const size_t per = (MODE == MODE_ADJOINT ? 1 : (size_t)R.spp) * R.max_depth * kBlock;
-        hrec = R.hits + wg * per + threadIdx.x;
+  for (int round = 0;; ++round) {
+    int bx, by, cam, part;
+    if constexpr (PERSIST) {
+      if (threadIdx.x == 0) unit_s = (int)atomicAdd(R.items, 1u);
+      __syncthreads();
+      const int unit = unit_s;
+      __syncthreads();
+      if (unit >= units) break;  // the counter only grows: every wave leaves
+      const int tile = unit / split;
+      part = unit % split;
+      bx = tile % tiles_x;
+      by = (tile / tiles_x) % tiles_y;
+      cam = tile / (tiles_x * tiles_y);
+    } else {
+      if (round > 0) break;
+      bx = blockIdx.x;
+      by = blockIdx.y;
+      cam = blockIdx.z / split;
+      part = blockIdx.z % split;
+    }
+    const int x = bx * kTile + (threadIdx.x % kTile);
+    const int y = by * kTile + (threadIdx.x / kTile);
+    const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
+    if (x < W && y < H && s1 > s0) {
+      const size_t pix = ((size_t)cam * H + y) * W + x;
+      const float inv = 1.0f / (float)R.spp;
+      f3 dL = mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
+      if (nonzero(dL)) {
+        Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
+        f3 unused;
+        int4* hrec = nullptr;
+        if (PERSIST) {
+          // one sample's records at a time, in this workgroup's slot
+          hrec = R.hits + (size_t)blockIdx.x * R.max_depth * kBlock + threadIdx.x;
+        } else if (HC) {
+          // MODE_ADJOINT_CACHED: every sample's records, per tile
+          const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+          hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
+        }
+        render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0, dL,
+                               stack + threadIdx.x, cnt, sink, io, unused, hrec);
       }
-      render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0, dL,
-                             stack + threadIdx.x, cnt, sink, io, unused, hrec);
     }
   }
   __syncthreads();
@@ -925,12 +955,19 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
             c.n * adjoint_split(r.spp));
   DNrcIO none = {};
   if (r.hits) {
+    // persistent workgroups, one record slot each; the host sized the slots
+    // for this many
+    const int64_t units = (int64_t)grid.x * grid.y * grid.z;
+    const int resident = adjoint_resident_groups();
+    const unsigned groups = (unsigned)(resident > 0 && resident < units ? resident : units);
+    hipError_t e = launch_zero(r.items, 1, st);
+    if (e != hipSuccess) return e;
     if (r.stats)
-      hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT, true>), grid, dim3(kBlock), 0, st, s,
-                         p, c, r, adj, g, none);
+      hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT, true>), dim3(groups), dim3(kBlock), 0,
+                         st, s, p, c, r, adj, g, none);
     else
-      hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, true>), grid, dim3(kBlock), 0, st, s,
-                         p, c, r, adj, g, none);
+      hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, true>), dim3(groups), dim3(kBlock), 0,
+                         st, s, p, c, r, adj, g, none);
   } else if (r.stats) {
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, adj, g, none);
@@ -939,6 +976,24 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
                        c, r, adj, g, none);
   }
   return hipGetLastError();
+}
+
+int adjoint_resident_groups() {
+  // per device, queried once: compute units x workgroups of the kernel that
+  // fit on one at a time
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] > 0) return cached[dev];
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_render_adjoint<false, MODE_ADJOINT, true>),
+          kBlock, 0) != hipSuccess)
+    return 0;
+  if (cus <= 0 || per_cu <= 0) return 0;
+  cached[dev] = cus * per_cu;
+  return cached[dev];
 }
 
 hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,

@@ -278,7 +278,10 @@ def test_adjoint_with_intersection_records(case):
         print(case, f"texture {i}: records vs re-trace rel {r:.3g}", flush=True)
         assert r <= 1e-6
     if len(sc.roughness):
-        assert np.allclose(hr.cpu().numpy(), pr.cpu().numpy(), rtol=1e-6, atol=1e-9)
+        # one float32 sum of ~1e4 signed terms, pre-summed per workgroup in
+        # LDS: the persistent workgroups group the terms differently from the
+        # per-tile launch, which moves the sum by ~1e-6 of its value
+        assert np.allclose(hr.cpu().numpy(), pr.cpu().numpy(), rtol=1e-5, atol=1e-9)
     ot, orr = orc.adjoint(adj.astype(np.float64), spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
                           seed=2)
     for i, (g, o) in enumerate(zip(ht, ot)):
@@ -297,7 +300,7 @@ def test_intersection_records_multi_camera_ragged_and_size_check():
     tex, rough = _params(sc)
     a = torch.from_numpy(np.random.default_rng(9).normal(size=(3, 27, 44, 3)).astype(np.float32)).cuda()
     need = int(drt.lib.drt_render_adjoint_hit_bytes(3, 44, 27, 3, 4))
-    assert need == 3 * 6 * 4 * 3 * 4 * 64 * 16
+    assert need == 256 + 3 * 6 * 4 * 3 * 4 * 64 * 16   # 216 work units: fewer than resident workgroups
     with pytest.raises(RuntimeError, match="hit_records"):
         drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5,
                            hit_records=torch.empty(need - 1, dtype=torch.uint8, device="cuda"))
@@ -306,7 +309,7 @@ def test_intersection_records_multi_camera_ragged_and_size_check():
     pt, pr = drt.render_adjoint(gs, tex, rough, sc.cameras, a, 3, 4, seed=5)
     h, p = ht[0].cpu().numpy().astype(np.float64), pt[0].cpu().numpy().astype(np.float64)
     assert np.linalg.norm(h - p) <= 1e-6 * np.linalg.norm(p)
-    assert abs(hr.item() - pr.item()) <= 1e-6 * abs(pr.item())
+    assert abs(hr.item() - pr.item()) <= 1e-5 * abs(pr.item())   # summation grouping, as above
 
 
 def test_adjoint_matches_central_differences_on_gpu():

@@ -251,10 +251,11 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
             == 4 * 8 * 8 * 6 * 64 * 16)
     assert drt.lib.drt_render_adjoint_cached_hit_bytes(1, 64, 64, 0, 6) == 0
     # intersection records of the replay: 8x8 workgroups x depth x 64 lanes x 16 B
-    # (each tile's samples split over min(spp, 4) workgroups)
-    assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 16, 3) == 16384 * 4 * 3 * 64 * 16
-    assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2, 2) == 2 * 2 * 3 * 2 * 2 * 64 * 16
-    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 1, 3) == 3 * 64 * 16
+    # without a device: a 256-byte counter header + one slot per work unit
+    # (tile x one of min(spp, 4) sample ranges)
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 1024, 1024, 16, 3) == 256 + 16384 * 4 * 3 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(2, 9, 17, 2, 2) == 256 + 2 * 2 * 3 * 2 * 2 * 64 * 16
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 1, 3) == 256 + 3 * 64 * 16
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 0, 8, 4, 3) == 0
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 4, 0) == 0
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 0, 3) == 0
