@@ -6,7 +6,7 @@ wall and one roughness scalar; 1024x1024 pixels, 16 spp, max depth 3, no
 Russian roulette.  One step = primal render (seed A) -> L2 loss and
 image-space adjoint -> replayed adjoint (seed B) scattering texel and
 roughness gradients -> Adam on texture and roughness (gradients re-zeroed by
-the same kernel).  The replay reads pass A's intersections from a 192 MiB
+the same kernel).  The replay reads pass A's intersections from a 12 MiB
 record buffer instead of tracing the same rays again (identical gradients);
 the re-tracing replay's time is reported beside it.  Inputs are resident in
 HBM before timing starts.
