@@ -15,6 +15,8 @@
 // call as a switch on the material id with the albedo/roughness fetch hoisted
 // out of it, roughness gradients pre-reduced in LDS per workgroup, texel
 // gradients as hardware float atomics (no return value).
+#include <atomic>
+
 #include "drt_device.h"
 
 namespace drt {
@@ -979,12 +981,14 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
 }
 
 int adjoint_resident_groups() {
-  // per device, queried once: compute units x workgroups of the kernel that
-  // fit on one at a time
-  static int cached[64];
+  // per device, queried once (host threads may race to fill it; they store
+  // the same value): compute units x workgroups of the kernel that fit on one
+  // at a time
+  static std::atomic<int> cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cached[dev] > 0) return cached[dev];
+  const int known = cached[dev].load(std::memory_order_relaxed);
+  if (known > 0) return known;
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -992,8 +996,8 @@ int adjoint_resident_groups() {
           kBlock, 0) != hipSuccess)
     return 0;
   if (cus <= 0 || per_cu <= 0) return 0;
-  cached[dev] = cus * per_cu;
-  return cached[dev];
+  cached[dev].store(cus * per_cu, std::memory_order_relaxed);
+  return cus * per_cu;
 }
 
 hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
