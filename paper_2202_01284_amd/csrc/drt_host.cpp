@@ -783,6 +783,11 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
   if (st != DRT_OK) return st;
   if (!adj_image || !grads || !hit_records)
     return fail(DRT_EINVAL, "adj_image, grads and hit_records are required");
+  // the persistent workgroups count work units in 32 bits
+  const int64_t tiles = (int64_t)n_cams * ((cams[0].width + kTile - 1) / kTile) *
+                        ((cams[0].height + kTile - 1) / kTile);
+  if (tiles * adjoint_split(opts->spp) > ((int64_t)1 << 31))
+    return fail(DRT_EUNSUPPORTED, "image too large for the persistent replay");
   const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
                                                     opts->spp, opts->max_depth);
   if (need <= 0 || hit_bytes < need)

@@ -595,22 +595,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   if (threadIdx.x < kMaxRoughLds) rough_acc[threadIdx.x] = 0.f;
   __syncthreads();
   constexpr bool PERSIST = HC && MODE == MODE_ADJOINT;
-  __shared__ int unit_s;
+  __shared__ uint32_t unit_s;
   const int W = C.width, H = C.height;
   const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
   const int split = PERSIST ? adjoint_split(R.spp) : (int)gridDim.z / C.n;
-  const int units = PERSIST ? tiles_x * tiles_y * C.n * split : 1;
+  const int64_t units = PERSIST ? (int64_t)tiles_x * tiles_y * C.n * split : 1;  // < 2^31 (host)
   Counters cnt = {};
   for (int round = 0;; ++round) {
     int bx, by, cam, part;
     if constexpr (PERSIST) {
-      if (threadIdx.x == 0) unit_s = (int)atomicAdd(R.items, 1u);
+      if (threadIdx.x == 0) unit_s = atomicAdd(R.items, 1u);
       __syncthreads();
-      const int unit = unit_s;
+      const int64_t unit = unit_s;
       __syncthreads();
       if (unit >= units) break;  // the counter only grows: every wave leaves
-      const int tile = unit / split;
-      part = unit % split;
+      const int tile = (int)(unit / split);
+      part = (int)(unit % split);
       bx = tile % tiles_x;
       by = (tile / tiles_x) % tiles_y;
       cam = tile / (tiles_x * tiles_y);
