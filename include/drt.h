@@ -200,7 +200,11 @@ enum {
  * the mean of spp path-traced samples (box filter of one-pixel support).
  * Sample s of pixel (cam, x, y) draws Philox4x32-10 blocks with key = seed
  * and counter = (g_lo, g_hi, b, dim), g = ((cam*H + y)*W + x)*spp + s.
- * image: device float [n_cams][H][W][3], overwritten. */
+ * image: device float [n_cams][H][W][3], overwritten.  With spp >= 2 the
+ * samples of a pixel are summed in two halves (by two workgroups) that are
+ * added onto the zeroed image; the result is deterministic (two addends
+ * onto zero commute exactly) but may differ in the last bit from one
+ * running sum. */
 drt_status drt_render_forward(const drt_scene* scene, const drt_params* params,
                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
                               float* image, void* hip_stream);
