@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--strategies-only", action="store_true",
+                    help="only the image + gradient strategies (PRB megakernel, PRB wavefront, "
+                         "checkpointed) on the gradient-step workload, once each; prints their JSON")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -78,6 +81,13 @@ def main():
     gs = drt.Scene(sc)
     cams = sc.cameras
     tex = torch.full((args.tex, args.tex, 3), 0.5, dtype=torch.float32, device=dev)
+    if args.strategies_only:
+        rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
+        a = torch.from_numpy(np.random.default_rng(4).normal(size=(1, R, R, 3)).astype(np.float32)
+                             * 1e-3).to(dev)
+        print(json.dumps(checkpoint_compare(drt, scenes, torch, sc, [tex], rough, a, R, SPP, D,
+                                            depths=())), flush=True)
+        return
     rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
     # target: seeded random texture, roughness 0.2, rendered once at high spp
     tex_t = torch.from_numpy(scenes.random_texture(args.tex)).to(dev)
