@@ -394,7 +394,8 @@ def test_cached_adjoint_with_intersection_records():
         r = np.linalg.norm(h - p) / np.linalg.norm(p)
         print("cached replay with records vs re-trace, flags", flags, "rel", r, flush=True)
         assert r <= 1e-6
-        assert abs(hr.item() - pr.item()) <= 1e-6 * abs(pr.item())
+        # one float32 sum of many signed terms: atomic order alone moves it ~1e-7..1e-6
+        assert abs(hr.item() - pr.item()) <= 1e-5 * abs(pr.item())
     with pytest.raises(RuntimeError, match="hit_records"):
         drt.render_adjoint_cached(*args, hit_records=hits[:-1])
 
