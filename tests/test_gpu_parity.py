@@ -211,6 +211,13 @@ ADJ_CASES = {
     # odd spp and ragged tiles: the adjoint's four sample ranges are 1, 1, 1, 2
     "cornell_spp5": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=40,
                                             height=24), dict(spp=5, max_depth=3)),
+    # fewer samples than the four-way split: one range of one sample, direct
+    # light only (the camera segment and one next-event segment)
+    "cornell_spp1_direct": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64),
+                                                   width=24, height=16), dict(spp=1, max_depth=2)),
+    # three ranges of one sample each, two scattering bounces past the first
+    "cornell_spp3_d4": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64),
+                                               width=32, height=20), dict(spp=3, max_depth=4)),
 }
 
 
@@ -280,8 +287,10 @@ def test_adjoint_with_intersection_records(case):
     if len(sc.roughness):
         # one float32 sum of ~1e4 signed terms, pre-summed per workgroup in
         # LDS: the persistent workgroups group the terms differently from the
-        # per-tile launch, which moves the sum by ~1e-6 of its value
-        assert np.allclose(hr.cpu().numpy(), pr.cpu().numpy(), rtol=1e-5, atol=1e-9)
+        # per-tile launch (the texture gradients above show the terms
+        # themselves agree), which moves the sum by 1e-6..2e-5 of its value --
+        # the most where the terms cancel to a small total (depth 4)
+        assert np.allclose(hr.cpu().numpy(), pr.cpu().numpy(), rtol=1e-4, atol=1e-9)
     ot, orr = orc.adjoint(adj.astype(np.float64), spp=kw["spp"], max_depth=kw["max_depth"], rr_depth=rr,
                           seed=2)
     for i, (g, o) in enumerate(zip(ht, ot)):
@@ -411,6 +420,19 @@ def test_empty_and_degenerate_inputs():
     z = torch.zeros((1, 1, 1, 3), dtype=torch.float32, device="cuda")
     gt, _ = drt.render_adjoint(gs2, tex, None, sc2.cameras, z, 1, 3)
     assert float(gt[0].abs().sum()) == 0.0
+    # depth 1 (the camera segment alone sees only emission, which no
+    # parameter changes): exactly zero gradients by both replays, as the
+    # oracle's
+    sc3 = scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=16, height=8)
+    gs3 = drt.Scene(sc3)
+    tex3, rough3 = _params(sc3)
+    a3 = torch.from_numpy(np.random.default_rng(5).normal(size=(1, 8, 16, 3)).astype(np.float32)).cuda()
+    ot, orr = oracle.OracleScene(sc3).adjoint(a3.cpu().numpy().astype(np.float64), spp=2, max_depth=1,
+                                              rr_depth=drt.NO_RR, seed=2)
+    assert np.abs(ot[0]).sum() == 0.0 and np.abs(orr).sum() == 0.0
+    for hits in (None, drt.adjoint_hit_records(sc3.cameras, 2, 1)):
+        gt3, gr3 = drt.render_adjoint(gs3, tex3, rough3, sc3.cameras, a3, 2, 1, seed=2, hit_records=hits)
+        assert float(gt3[0].abs().sum()) == 0.0 and float(gr3.abs().sum()) == 0.0
     # invalid arguments are rejected before any launch
     with pytest.raises(drt.DrtError):
         drt.render_forward(gs2, tex, None, sc2.cameras, 0, 3)
