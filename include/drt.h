@@ -176,8 +176,9 @@ typedef struct {
 } drt_grads;
 
 typedef struct {
-  int32_t spp;        /* samples per pixel, >= 1 */
-  int32_t max_depth;  /* D: path segments including the camera ray, >= 1 */
+  int32_t spp;        /* samples per pixel, >= 1; n_cams*W*H*spp <= 2^46, else
+                         DRT_EUNSUPPORTED */
+  int32_t max_depth;  /* D: path segments including the camera ray, 1..65536 */
   int32_t rr_depth;   /* Russian roulette after sampling at vertex k >= rr_depth */
   uint32_t flags;     /* DRT_FLAG_* */
   uint64_t seed;      /* Philox key */
@@ -251,7 +252,8 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
  * megakernels are compared with, Sec. "Evaluation").  For the comparison;
  * opts->stats is ignored.  workspace: device scratch of at least
  * drt_render_wavefront_workspace_bytes(n_cams*W*H*spp) bytes, 16-byte
- * aligned. */
+ * aligned (the size is 0 for n_paths < 0 or > 2^46, the largest sample
+ * count of one rendering call). */
 int64_t drt_render_wavefront_workspace_bytes(int64_t n_paths);
 drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params,
                                 const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
@@ -264,7 +266,7 @@ drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params
  * the path state through the workspace.  Same gradients as
  * drt_render_adjoint (ADDED to grads) up to float rounding and atomic order.
  * workspace: at least drt_render_adjoint_wavefront_workspace_bytes(
- * n_cams*W*H*spp) bytes, 16-byte aligned. */
+ * n_cams*W*H*spp) bytes, 16-byte aligned (0 for n_paths < 0 or > 2^46). */
 int64_t drt_render_adjoint_wavefront_workspace_bytes(int64_t n_paths);
 drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params* params,
                                         const drt_camera* cams, int32_t n_cams,
@@ -423,7 +425,8 @@ drt_status drt_nrc_collect(const drt_scene* scene, const drt_params* params,
 
 /* Bytes of device workspace drt_nrc_train needs for n records (the BF16
  * layer inputs and output gradients of every record, 1216 B per record
- * rounded up to 16-record tiles). */
+ * rounded up to 16-record tiles); 0 for n < 0 or n > 2^31, the range
+ * drt_nrc_train accepts. */
 int64_t drt_nrc_train_workspace_bytes(int64_t n);
 
 /* One training pass: relative-L2 loss (Mueller et al. 2021: mean over valid
@@ -454,7 +457,8 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
  * n = n_paths * (tail_vertex - 1).  workspace: device scratch of at least
  * drt_nrc_collect_self_workspace_bytes(n_paths, tail_vertex) bytes.
  * 2 <= tail_vertex <= 32; n_paths <= INT32_MAX and
- * n_paths * (tail_vertex - 1) <= 2^31.  The paper does not study caches; this
+ * n_paths * (tail_vertex - 1) <= 2^31 (the size function returns 0 outside
+ * 2 <= tail_vertex <= 32, 0 <= n_paths <= INT32_MAX).  The paper does not study caches; this
  * is the self-training of Mueller et al. (2021) written on the cached
  * estimator. */
 int64_t drt_nrc_collect_self_workspace_bytes(int64_t n_paths, int32_t tail_vertex);
@@ -467,7 +471,8 @@ drt_status drt_nrc_collect_self(const drt_scene* scene, const drt_params* params
 
 /* Entries of the int32 query scratch of the cached calls for `capacity`
  * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
- * parameter references [capacity][2] | bin histogram [4096]. */
+ * parameter references [capacity][2] | bin histogram [4096]; 0 for
+ * capacity < 0 or > 2^40, which the cached calls reject. */
 int64_t drt_nrc_query_ints(int64_t capacity);
 
 /* Primal render with the cache: image = (1/spp) sum over samples of the

@@ -42,6 +42,14 @@ drt_status hip_fail(hipError_t e, const char* what) {
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// Limits of the rendering calls: samples per call (n_cams x W x H x spp),
+// path segments, and paths of a wavefront or training workspace.
+constexpr int64_t kMaxSamples = (int64_t)1 << 46;
+constexpr int kMaxDepth = 1 << 16;
+
+// a * b <= lim for non-negative a and b, decided without overflowing
+inline bool prod_le(int64_t a, int64_t b, int64_t lim) { return b == 0 || a <= lim / b; }
+
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
@@ -534,12 +542,16 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   if (n_cams < 1 || n_cams > DRT_MAX_CAMERAS)
     return fail(DRT_EINVAL, "n_cams must be in [1, %d]", DRT_MAX_CAMERAS);
   if (o->spp < 1) return fail(DRT_EINVAL, "spp must be >= 1");
-  if (o->max_depth < 1) return fail(DRT_EINVAL, "max_depth must be >= 1");
+  if (o->max_depth < 1 || o->max_depth > kMaxDepth)
+    return fail(DRT_EINVAL, "max_depth must be in [1, %d]", kMaxDepth);
   if (o->rr_depth < 1) return fail(DRT_EINVAL, "rr_depth must be >= 1");
   const int W = cams[0].width, H = cams[0].height;
   if (W <= 0 || H <= 0) return fail(DRT_EINVAL, "camera size must be positive");
-  if ((int64_t)n_cams * W * H * o->spp > (int64_t)1 << 46)
-    return fail(DRT_EUNSUPPORTED, "sample count too large");
+  int64_t samples = n_cams;
+  for (const int64_t f : {(int64_t)W, (int64_t)H, (int64_t)o->spp}) {
+    if (!prod_le(samples, f, kMaxSamples)) return fail(DRT_EUNSUPPORTED, "sample count too large");
+    samples *= f;
+  }
   const DScene& sc = s->dev;
   for (int t = 0; t < sc.n_tex; ++t)
     if (!p->textures[t]) return fail(DRT_EINVAL, "texture %d pointer is NULL", t);
@@ -749,9 +761,14 @@ drt_status drt_render_adjoint(const drt_scene* scene, const drt_params* params,
 // One record slot (max_depth x kBlock x 16 B) per workgroup of 8x8 pixels;
 // 0 for invalid sizes.
 static int64_t record_slot_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t max_depth) {
-  if (n_cams < 1 || width < 1 || height < 1 || max_depth < 1 || max_depth > (1 << 16)) return 0;
+  if (n_cams < 1 || n_cams > DRT_MAX_CAMERAS || width < 1 || height < 1 || max_depth < 1 ||
+      max_depth > kMaxDepth)
+    return 0;
+  // < 2^5 x 2^28 x 2^28 tiles; their records must stay far from int64's end
   const int64_t groups = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
-  return groups * max_depth * kBlock * (int64_t)sizeof(int4);
+  const int64_t per_group = (int64_t)max_depth * kBlock * (int64_t)sizeof(int4);
+  if (!prod_le(groups, per_group, (int64_t)1 << 60)) return 0;
+  return groups * per_group;
 }
 
 // Record buffer of the replayed adjoint: a 256-byte header (the persistent
@@ -762,7 +779,7 @@ static constexpr int64_t kHitHeader = 256;
 int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t height, int32_t spp,
                                      int32_t max_depth) {
   if (spp < 1) return 0;
-  const int64_t per_tile = record_slot_bytes(n_cams, width, height, max_depth);
+  const int64_t per_tile = record_slot_bytes(n_cams, width, height, max_depth);  // 0 when too large
   if (per_tile <= 0) return 0;
   const int64_t tiles = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   const int64_t units = tiles * adjoint_split(spp);
@@ -805,7 +822,7 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
 }
 
 int64_t drt_render_wavefront_workspace_bytes(int64_t n_paths) {
-  return n_paths < 0 ? 0 : wavefront_workspace_bytes(n_paths);
+  return n_paths < 0 || n_paths > kMaxSamples ? 0 : wavefront_workspace_bytes(n_paths);
 }
 
 drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params,
@@ -830,7 +847,7 @@ drt_status drt_render_wavefront(const drt_scene* scene, const drt_params* params
 }
 
 int64_t drt_render_adjoint_wavefront_workspace_bytes(int64_t n_paths) {
-  return n_paths < 0 ? 0 : wavefront_adjoint_workspace_bytes(n_paths);
+  return n_paths < 0 || n_paths > kMaxSamples ? 0 : wavefront_adjoint_workspace_bytes(n_paths);
 }
 
 drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params* params,
@@ -862,7 +879,7 @@ drt_status drt_render_adjoint_wavefront(const drt_scene* scene, const drt_params
 }
 
 int64_t drt_render_checkpointed_workspace_bytes(int64_t n_paths, int32_t max_depth) {
-  if (n_paths < 0 || n_paths > ((int64_t)1 << 40) || max_depth < 1 || max_depth > (1 << 16)) return 0;
+  if (n_paths < 0 || n_paths > ((int64_t)1 << 40) || max_depth < 1 || max_depth > kMaxDepth) return 0;
   return checkpoint_workspace_bytes(n_paths, max_depth);
 }
 
@@ -1088,7 +1105,7 @@ static SelfWs self_ws(int64_t n, int K) {
 }
 
 int64_t drt_nrc_collect_self_workspace_bytes(int64_t n_paths, int32_t tail_vertex) {
-  if (n_paths < 0 || tail_vertex < 2 || tail_vertex > 32) return 0;
+  if (n_paths < 0 || n_paths > INT32_MAX || tail_vertex < 2 || tail_vertex > 32) return 0;
   return self_ws(n_paths, tail_vertex).total;
 }
 
@@ -1139,7 +1156,9 @@ drt_status drt_nrc_collect_self(const drt_scene* scene, const drt_params* params
   return ok();
 }
 
-int64_t drt_nrc_train_workspace_bytes(int64_t n) { return n < 0 ? 0 : nrc_train_workspace_bytes(n); }
+int64_t drt_nrc_train_workspace_bytes(int64_t n) {
+  return n < 0 || n > ((int64_t)1 << 31) ? 0 : nrc_train_workspace_bytes(n);
+}
 
 drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const uint16_t* grid,
                          const float* records, const int32_t* valid, const int32_t* count,
@@ -1166,7 +1185,7 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
 }
 
 int64_t drt_nrc_query_ints(int64_t capacity) {
-  return capacity < 0 ? 0 : 5 * capacity + kQueryBins;
+  return capacity < 0 || capacity > ((int64_t)1 << 40) ? 0 : 5 * capacity + kQueryBins;
 }
 
 drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
@@ -1188,6 +1207,7 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
   int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
+  if (drt_nrc_query_ints(capacity) == 0) return fail(DRT_EINVAL, "query capacity out of range");
   hipStream_t stream = (hipStream_t)hip_stream;
   DNrcIO io = query_io(net, cfg, queries, query_ints, query_count, capacity);
   hipError_t e = launch_zero(query_count, 1, stream);
@@ -1202,7 +1222,8 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
 int64_t drt_render_adjoint_cached_hit_bytes(int32_t n_cams, int32_t width, int32_t height,
                                             int32_t spp, int32_t max_depth) {
   if (spp < 1 || spp > (1 << 20)) return 0;
-  return record_slot_bytes(n_cams, width, height, max_depth) * spp;
+  const int64_t per_sample = record_slot_bytes(n_cams, width, height, max_depth);
+  return prod_le(per_sample, spp, (int64_t)1 << 62) ? per_sample * spp : 0;
 }
 
 drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* params,
@@ -1227,6 +1248,7 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   int64_t need = (int64_t)n_cams * cams[0].width * cams[0].height * opts->spp;
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
+  if (drt_nrc_query_ints(capacity) == 0) return fail(DRT_EINVAL, "query capacity out of range");
   if (hit_records) {
     const int64_t hneed = drt_render_adjoint_cached_hit_bytes(n_cams, cams[0].width, cams[0].height,
                                                               opts->spp, opts->max_depth);

@@ -259,6 +259,18 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 0, 8, 4, 3) == 0
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 4, 0) == 0
     assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 0, 3) == 0
+    # sizes that would overflow int64 are 0, not wrapped values
+    big = 2 ** 31 - 1
+    assert drt.lib.drt_render_adjoint_hit_bytes(32, big, big, 16, 1 << 16) == 0
+    assert drt.lib.drt_render_adjoint_hit_bytes(1, 8, 8, 4, (1 << 16) + 1) == 0
+    assert drt.lib.drt_render_adjoint_cached_hit_bytes(32, big, big, 1 << 20, 6) == 0
+    assert drt.lib.drt_render_adjoint_cached_hit_bytes(33, 8, 8, 4, 6) == 0
+    assert drt.lib.drt_render_wavefront_workspace_bytes(2 ** 62) == 0
+    assert drt.lib.drt_render_adjoint_wavefront_workspace_bytes(2 ** 62) == 0
+    assert drt.lib.drt_render_wavefront_workspace_bytes(2 ** 46) > 0
+    assert drt.lib.drt_nrc_train_workspace_bytes(2 ** 62) == 0
+    assert drt.lib.drt_nrc_query_ints(2 ** 62) == 0
+    assert drt.lib.drt_nrc_collect_self_workspace_bytes(2 ** 40, 2) == 0
     assert drt.lib.drt_render_adjoint_hits(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
                                            ctypes.byref(g), fake, 1 << 30, None) == -4
     # checkpointed calls: sizes grow by 64 B per path and bounce
