@@ -210,7 +210,19 @@ def _stream(stream=None) -> int:
 
 
 def _ptr(t) -> Optional[int]:
-    return None if t is None else t.data_ptr()
+    return None if t is None else _dp(t, "tensor")
+
+
+def _dp(t, what: str) -> int:
+    """Device address of a contiguous device tensor.  The kernels read raw
+    addresses, so a host tensor or a strided view is rejected here."""
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
 
 
 # ---------------------------------------------------------------------------
@@ -364,13 +376,13 @@ def _params(scene: Scene, textures, roughness):
         raise ValueError(f"scene has {len(scene.tex_shapes)} textures, got {len(textures)}")
     for i, t in enumerate(textures):
         _expect(t, f"texture {i}", scene.tex_shapes[i])
-        p.textures[i] = t.data_ptr()
+        p.textures[i] = _dp(t, f"texture {i}")
     if scene.n_roughness > 0:
         if roughness is None or roughness.numel() < scene.n_roughness:
             raise ValueError(f"scene has {scene.n_roughness} roughness slots")
     if roughness is not None and roughness.numel() > 0:
         _expect(roughness, "roughness")
-        p.roughness = roughness.data_ptr()
+        p.roughness = _dp(roughness, "roughness")
     return p
 
 
@@ -393,7 +405,7 @@ def _opts(spp, max_depth, rr_depth, seed, flags, stats):
     o.rr_depth = int(rr_depth)
     o.flags = int(flags)
     o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
-    o.stats = None if stats is None else stats.data_ptr()
+    o.stats = None if stats is None else _dp(stats, "stats")
     return o
 
 
@@ -413,7 +425,7 @@ def render_forward(scene: Scene, textures: Sequence, roughness, cams, spp: int, 
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
     _check(lib.drt_render_forward(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                  out.data_ptr(), _stream(stream)), "drt_render_forward")
+                                  _dp(out, "out"), _stream(stream)), "drt_render_forward")
     return out
 
 
@@ -437,23 +449,23 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
     for i, t in enumerate(grad_textures):
         if t is not None:
             _expect(t, f"grad texture {i}", scene.tex_shapes[i])
-            g.textures[i] = t.data_ptr()
+            g.textures[i] = _dp(t, f"grad texture {i}")
     if grad_roughness is not None:
         _expect(grad_roughness, "grad roughness")
         if grad_roughness.numel() < scene.n_roughness:
             raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
-        g.roughness = grad_roughness.data_ptr()
+        g.roughness = _dp(grad_roughness, "grad_roughness")
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
     if hit_records is not None:
         _check(lib.drt_render_adjoint_hits(scene.handle, ctypes.byref(p), ca, len(cams),
-                                           ctypes.byref(o), adj_image.data_ptr(), ctypes.byref(g),
-                                           hit_records.data_ptr(), hit_records.numel(),
+                                           ctypes.byref(o), _dp(adj_image, "adj_image"), ctypes.byref(g),
+                                           _dp(hit_records, "hit_records"), _nbytes(hit_records),
                                            _stream(stream)), "drt_render_adjoint_hits")
     else:
         _check(lib.drt_render_adjoint(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                      adj_image.data_ptr(), ctypes.byref(g), _stream(stream)),
+                                      _dp(adj_image, "adj_image"), ctypes.byref(g), _stream(stream)),
                "drt_render_adjoint")
     return grad_textures, grad_roughness
 
@@ -486,7 +498,7 @@ def render_wavefront(scene: Scene, textures: Sequence, roughness, cams, spp: int
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     _check(lib.drt_render_wavefront(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                    workspace.data_ptr(), workspace.numel(), out.data_ptr(),
+                                    _dp(workspace, "workspace"), _nbytes(workspace), _dp(out, "out"),
                                     _stream(stream)), "drt_render_wavefront")
     return out
 
@@ -506,12 +518,12 @@ def render_adjoint_wavefront(scene: Scene, textures: Sequence, roughness, cams, 
     for i, t in enumerate(grad_textures):
         if t is not None:
             _expect(t, f"grad texture {i}", scene.tex_shapes[i])
-            g.textures[i] = t.data_ptr()
+            g.textures[i] = _dp(t, f"grad texture {i}")
     if grad_roughness is not None:
         _expect(grad_roughness, "grad roughness")
         if grad_roughness.numel() < scene.n_roughness:
             raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
-        g.roughness = grad_roughness.data_ptr()
+        g.roughness = _dp(grad_roughness, "grad_roughness")
     n = len(cams) * cams[0].width * cams[0].height * spp
     if workspace is None:
         workspace = torch.empty(int(lib.drt_render_adjoint_wavefront_workspace_bytes(n)), dtype=torch.uint8,
@@ -520,8 +532,9 @@ def render_adjoint_wavefront(scene: Scene, textures: Sequence, roughness, cams, 
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     _check(lib.drt_render_adjoint_wavefront(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                            adj_image.data_ptr(), ctypes.byref(g), workspace.data_ptr(),
-                                            workspace.numel(), _stream(stream)),
+                                            _dp(adj_image, "adj_image"), ctypes.byref(g),
+                                            _dp(workspace, "workspace"), _nbytes(workspace),
+                                            _stream(stream)),
            "drt_render_adjoint_wavefront")
     return grad_textures, grad_roughness
 
@@ -553,8 +566,8 @@ def render_checkpointed_forward(scene: Scene, textures: Sequence, roughness, cam
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     _check(lib.drt_render_checkpointed_forward(scene.handle, ctypes.byref(p), ca, len(cams),
-                                               ctypes.byref(o), workspace.data_ptr(),
-                                               workspace.numel(), out.data_ptr(), _stream(stream)),
+                                               ctypes.byref(o), _dp(workspace, "workspace"),
+                                               _nbytes(workspace), _dp(out, "out"), _stream(stream)),
            "drt_render_checkpointed_forward")
     return out, workspace
 
@@ -576,19 +589,19 @@ def render_checkpointed_adjoint(scene: Scene, textures: Sequence, roughness, cam
     for i, t in enumerate(grad_textures):
         if t is not None:
             _expect(t, f"grad texture {i}", scene.tex_shapes[i])
-            g.textures[i] = t.data_ptr()
+            g.textures[i] = _dp(t, f"grad texture {i}")
     if grad_roughness is not None:
         _expect(grad_roughness, "grad roughness")
         if grad_roughness.numel() < scene.n_roughness:
             raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
-        g.roughness = grad_roughness.data_ptr()
+        g.roughness = _dp(grad_roughness, "grad_roughness")
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     _check(lib.drt_render_checkpointed_adjoint(scene.handle, ctypes.byref(p), ca, len(cams),
-                                               ctypes.byref(o), adj_image.data_ptr(),
-                                               ctypes.byref(g), workspace.data_ptr(),
-                                               workspace.numel(), _stream(stream)),
+                                               ctypes.byref(o), _dp(adj_image, "adj_image"),
+                                               ctypes.byref(g), _dp(workspace, "workspace"),
+                                               _nbytes(workspace), _stream(stream)),
            "drt_render_checkpointed_adjoint")
     return grad_textures, grad_roughness
 
@@ -610,17 +623,17 @@ def render_jvp(scene: Scene, textures: Sequence, roughness, cams, spp: int, max_
     for i, x in enumerate(tan_textures):
         if x is not None:
             _expect(x, f"tangent texture {i}", scene.tex_shapes[i])
-            t.textures[i] = x.data_ptr()
+            t.textures[i] = _dp(x, f"tangent texture {i}")
     if tan_roughness is not None:
         _expect(tan_roughness, "tangent roughness")
         if tan_roughness.numel() < scene.n_roughness:
             raise ValueError(f"tangent roughness needs {scene.n_roughness} entries")
-        t.roughness = tan_roughness.data_ptr()
+        t.roughness = _dp(tan_roughness, "tan_roughness")
     ca = _cams(cams)
     p = _params(scene, textures, roughness)
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     _check(lib.drt_render_jvp(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                              ctypes.byref(t), out.data_ptr(), _stream(stream)), "drt_render_jvp")
+                              ctypes.byref(t), _dp(out, "out"), _stream(stream)), "drt_render_jvp")
     return out
 
 
@@ -631,7 +644,7 @@ def trace(scene: Scene, rays, mode: int = 0, stream=None):
     _expect(rays, "rays")
     n = rays.shape[0]
     out = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
-    _check(lib.drt_trace(scene.handle, rays.data_ptr(), n, mode, out.data_ptr(), _stream(stream)),
+    _check(lib.drt_trace(scene.handle, _dp(rays, "rays"), n, mode, _dp(out, "out"), _stream(stream)),
            "drt_trace")
     return out
 
@@ -641,8 +654,8 @@ def philox(counters, keys, stream=None):
     torch = _torch()
     n = counters.shape[0]
     out = torch.empty((n, 4), dtype=torch.int32, device=counters.device)
-    _check(lib.drt_philox(counters.data_ptr(), keys.data_ptr(), n, out.data_ptr(), _stream(stream)),
-           "drt_philox")
+    _check(lib.drt_philox(_dp(counters, "counters"), _dp(keys, "keys"), n, _dp(out, "out"),
+                          _stream(stream)), "drt_philox")
     return out
 
 
@@ -656,8 +669,8 @@ def loss_l2(img, target, adj=None, stream=None):
         adj = torch.empty_like(img)
     loss = torch.empty(1, dtype=torch.float32, device=img.device)
     ws = torch.empty(int(lib.drt_loss_workspace_floats(n)), dtype=torch.float32, device=img.device)
-    _check(lib.drt_loss_l2(img.data_ptr(), target.data_ptr(), n, adj.data_ptr(), loss.data_ptr(),
-                           ws.data_ptr(), _stream(stream)), "drt_loss_l2")
+    _check(lib.drt_loss_l2(_dp(img, "img"), _dp(target, "target"), n, _dp(adj, "adj"), _dp(loss, "loss"),
+                           _dp(ws, "ws"), _stream(stream)), "drt_loss_l2")
     return loss, adj
 
 
@@ -678,8 +691,8 @@ def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9
     o.lo = float(max(lo, -3.0e38))
     o.hi = float(min(hi, 3.0e38))
     o.zero_grad = 1 if zero_grad else 0
-    o.half_out = None if half_out is None else half_out.data_ptr()
-    _check(lib.drt_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+    o.half_out = None if half_out is None else _dp(half_out, "half_out")
+    _check(lib.drt_adam_step(_dp(param, "param"), _dp(grad, "grad"), _dp(m, "m"), _dp(v, "v"),
                              param.numel(), ctypes.byref(o), _stream(stream)), "drt_adam_step")
 
 
@@ -770,15 +783,15 @@ def nrc_encode(cfg: dict, grid, records, stream=None):
     n = records.shape[0]
     x = torch.empty((n, NRC_INPUTS), dtype=torch.float32, device=records.device)
     c = nrc_config(cfg)
-    _check(lib.drt_nrc_encode(ctypes.byref(c), grid.data_ptr(), records.data_ptr(), n,
-                              x.data_ptr(), _stream(stream)), "drt_nrc_encode")
+    _check(lib.drt_nrc_encode(ctypes.byref(c), _dp(grid, "grid"), _dp(records, "records"), n,
+                              _dp(x, "x"), _stream(stream)), "drt_nrc_encode")
     return x
 
 
 def nrc_grid_backward(cfg: dict, records, dx, dgrid, stream=None):
     c = nrc_config(cfg)
-    _check(lib.drt_nrc_grid_backward(ctypes.byref(c), records.data_ptr(), dx.data_ptr(),
-                                     records.shape[0], dgrid.data_ptr(), _stream(stream)),
+    _check(lib.drt_nrc_grid_backward(ctypes.byref(c), _dp(records, "records"), _dp(dx, "dx"),
+                                     records.shape[0], _dp(dgrid, "dgrid"), _stream(stream)),
            "drt_nrc_grid_backward")
     return dgrid
 
@@ -787,7 +800,7 @@ def nrc_forward(weights, x, stream=None):
     torch = _torch()
     n = x.shape[0]
     y = torch.empty((n, 3), dtype=torch.float32, device=x.device)
-    _check(lib.drt_nrc_forward(weights.data_ptr(), x.data_ptr(), n, y.data_ptr(), _stream(stream)),
+    _check(lib.drt_nrc_forward(_dp(weights, "weights"), _dp(x, "x"), n, _dp(y, "y"), _stream(stream)),
            "drt_nrc_forward")
     return y
 
@@ -800,9 +813,9 @@ def nrc_backward(weights, x, dy, dW=None, workspace=None, stream=None):
     if workspace is None:
         workspace = nrc_train_workspace(n, x.device)
     dx = torch.empty((n, NRC_INPUTS), dtype=torch.float32, device=x.device)
-    _check(lib.drt_nrc_backward(weights.data_ptr(), x.data_ptr(), dy.data_ptr(), n,
-                                workspace.data_ptr(), workspace.numel(), dW.data_ptr(),
-                                dx.data_ptr(), _stream(stream)), "drt_nrc_backward")
+    _check(lib.drt_nrc_backward(_dp(weights, "weights"), _dp(x, "x"), _dp(dy, "dy"), n,
+                                _dp(workspace, "workspace"), _nbytes(workspace), _dp(dW, "dW"),
+                                _dp(dx, "dx"), _stream(stream)), "drt_nrc_backward")
     return dW, dx
 
 
@@ -821,8 +834,8 @@ def nrc_collect(scene: Scene, textures, roughness, cams, cfg: dict, n_paths: int
     o = _opts(1, max_depth, rr_depth, seed, flags, None)
     c = nrc_config(cfg)
     _check(lib.drt_nrc_collect(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                               ctypes.byref(c), n_paths, rec.data_ptr(), valid.data_ptr(),
-                               count.data_ptr(), _stream(stream)), "drt_nrc_collect")
+                               ctypes.byref(c), n_paths, _dp(rec, "rec"), _dp(valid, "valid"),
+                               _dp(count, "count"), _stream(stream)), "drt_nrc_collect")
     return rec, valid, count
 
 
@@ -850,9 +863,9 @@ def nrc_collect_self(scene: Scene, textures, roughness, cams, cfg: dict, weights
     o = _opts(1, max_depth, rr_depth, seed, flags, None)
     c = nrc_config(cfg)
     _check(lib.drt_nrc_collect_self(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
-                                    ctypes.byref(c), weights.data_ptr(), grid.data_ptr(),
-                                    tail_vertex, n_paths, rec.data_ptr(), valid.data_ptr(),
-                                    count.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                    ctypes.byref(c), _dp(weights, "weights"), _dp(grid, "grid"),
+                                    tail_vertex, n_paths, _dp(rec, "rec"), _dp(valid, "valid"),
+                                    _dp(count, "count"), _dp(workspace, "workspace"), _nbytes(workspace),
                                     _stream(stream)), "drt_nrc_collect_self")
     return rec, valid, count
 
@@ -871,10 +884,10 @@ def nrc_train(cfg: dict, weights, grid, records, valid, count, dW, dgrid, loss=N
     if workspace is None:
         workspace = nrc_train_workspace(n, weights.device)
     c = nrc_config(cfg)
-    _check(lib.drt_nrc_train(ctypes.byref(c), weights.data_ptr(), grid.data_ptr(),
-                             records.data_ptr(), valid.data_ptr(), count.data_ptr(), n,
-                             workspace.data_ptr(), workspace.numel(), dW.data_ptr(),
-                             dgrid.data_ptr(), loss.data_ptr(), _stream(stream)), "drt_nrc_train")
+    _check(lib.drt_nrc_train(ctypes.byref(c), _dp(weights, "weights"), _dp(grid, "grid"),
+                             _dp(records, "records"), _dp(valid, "valid"), _dp(count, "count"), n,
+                             _dp(workspace, "workspace"), _nbytes(workspace), _dp(dW, "dW"),
+                             _dp(dgrid, "dgrid"), _dp(loss, "loss"), _stream(stream)), "drt_nrc_train")
     return loss
 
 
@@ -898,9 +911,9 @@ def render_forward_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     o = _opts(spp, max_depth, rr_depth, seed, flags, None)
     c = nrc_config(cfg)
     _check(lib.drt_render_forward_cached(scene.handle, ctypes.byref(p), ca, len(cams),
-                                         ctypes.byref(o), ctypes.byref(c), weights.data_ptr(),
-                                         grid.data_ptr(), q.data_ptr(), qpix.data_ptr(),
-                                         qcount.data_ptr(), q.shape[0], out.data_ptr(),
+                                         ctypes.byref(o), ctypes.byref(c), _dp(weights, "weights"),
+                                         _dp(grid, "grid"), _dp(q, "q"), _dp(qpix, "qpix"),
+                                         _dp(qcount, "qcount"), q.shape[0], _dp(out, "out"),
                                          _stream(stream)), "drt_render_forward_cached")
     return out
 
@@ -946,12 +959,12 @@ def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     for i, t in enumerate(grad_textures):
         if t is not None:
             _expect(t, f"grad texture {i}", scene.tex_shapes[i])
-            g.textures[i] = t.data_ptr()
+            g.textures[i] = _dp(t, f"grad texture {i}")
     if grad_roughness is not None:
         _expect(grad_roughness, "grad roughness")
         if grad_roughness.numel() < scene.n_roughness:
             raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
-        g.roughness = grad_roughness.data_ptr()
+        g.roughness = _dp(grad_roughness, "grad_roughness")
     n = len(cams) * cams[0].width * cams[0].height * spp
     if work is None:
         work = cached_work(n, scene.buffer.device, sample_radiance=True)
@@ -964,12 +977,12 @@ def render_adjoint_cached(scene: Scene, textures, roughness, cams, cfg: dict, we
     o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
     c = nrc_config(cfg)
     _check(lib.drt_render_adjoint_cached(scene.handle, ctypes.byref(p), ca, len(cams),
-                                         ctypes.byref(o), ctypes.byref(c), weights.data_ptr(),
-                                         grid.data_ptr(), q.data_ptr(), qid.data_ptr(),
-                                         qcount.data_ptr(), q.shape[0], lsamp.data_ptr(),
-                                         adj_image.data_ptr(), ctypes.byref(g),
-                                         None if hit_records is None else hit_records.data_ptr(),
-                                         0 if hit_records is None else hit_records.numel(),
+                                         ctypes.byref(o), ctypes.byref(c), _dp(weights, "weights"),
+                                         _dp(grid, "grid"), _dp(q, "q"), _dp(qid, "qid"),
+                                         _dp(qcount, "qcount"), q.shape[0], _dp(lsamp, "lsamp"),
+                                         _dp(adj_image, "adj_image"), ctypes.byref(g),
+                                         None if hit_records is None else _dp(hit_records, "hit_records"),
+                                         0 if hit_records is None else _nbytes(hit_records),
                                          _stream(stream)),
            "drt_render_adjoint_cached")
     return grad_textures, grad_roughness

@@ -436,3 +436,26 @@ def test_empty_and_degenerate_inputs():
     # invalid arguments are rejected before any launch
     with pytest.raises(drt.DrtError):
         drt.render_forward(gs2, tex, None, sc2.cameras, 0, 3)
+
+
+def test_binding_refuses_host_and_strided_tensors():
+    """The kernels read raw addresses: the binding refuses a host tensor or a
+    strided view before anything is launched."""
+    drt = _drt()
+    sc = scenes.cornell(width=16, height=16)
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    adj = torch.zeros((1, 16, 16, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="hit_records"):
+        drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 1, 2,
+                           hit_records=torch.empty(1 << 20, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="workspace"):
+        drt.render_wavefront(gs, tex, rough, sc.cameras, 1, 2,
+                             workspace=torch.empty(1 << 20, dtype=torch.uint8))
+    ctr = torch.zeros((16, 8), dtype=torch.int32, device="cuda")[:, ::2]
+    keys = torch.zeros((16, 2), dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError, match="counters"):
+        drt.philox(ctr, keys)
+    # the same calls with proper buffers go through
+    out = drt.philox(ctr.contiguous(), keys)
+    assert out.shape == (16, 4)
