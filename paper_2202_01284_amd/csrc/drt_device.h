@@ -260,6 +260,29 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       }
     }
     if (found) break;
+    if (any) {
+      // whether anything is hit does not depend on the visiting order: the
+      // hit interior children are taken in slot order, with no sort
+      int next = -1;
+      if (h0 && cn.x == 0) next = ch.x;
+      if (h1 && cn.y == 0) {
+        if (next < 0) next = ch.y; else stk[(sp++) * kBlock] = ch.y;
+      }
+      if (h2 && cn.z == 0) {
+        if (next < 0) next = ch.z; else stk[(sp++) * kBlock] = ch.z;
+      }
+      if (h3 && cn.w == 0) {
+        if (next < 0) next = ch.w; else stk[(sp++) * kBlock] = ch.w;
+      }
+      if (next >= 0) {
+        node = next;
+      } else {
+        if (sp == 0) break;
+        --sp;
+        node = stk[sp * kBlock];
+      }
+      continue;
+    }
     // interior children hit: keys finite for them, +inf otherwise
     float k0 = (h0 && cn.x == 0) ? fminf(t0, 3.0e38f) : INFINITY;
     float k1 = (h1 && cn.y == 0) ? fminf(t1, 3.0e38f) : INFINITY;
