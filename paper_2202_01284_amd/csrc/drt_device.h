@@ -201,8 +201,9 @@ DEV void cswap(float& ka, int& va, float& kb, int& vb) {
 
 // Closest (any = false) or any hit in (tmin, tmax] over the four-wide BVH.
 // Per node: four slab tests; the triangles of every hit leaf child in one
-// loop; hit interior children sorted near to far, the nearest visited next
-// and the others pushed far first.
+// loop; for a closest hit, hit interior children sorted near to far, the
+// nearest visited next and the others pushed far first (an any-hit query
+// takes them in slot order).
 DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool any, Hit& h,
                   int* stk, Counters& cnt) {
   float tbest = tmax;
