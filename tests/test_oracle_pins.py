@@ -404,6 +404,125 @@ def test_bsdf_reflection_reciprocity(type_):
         np.testing.assert_allclose(fab / b[2], fba / a[2], rtol=1e-10, atol=1e-14)
 
 
+def _half_angle_pair(th_i, th_o):
+    """Directions at polar angles th_i, th_o on either side of the normal in
+    one plane: their half vector is the normal tilted by (th_i - th_o) / 2, so
+    the cosine between wi and it is cos((th_i + th_o) / 2)."""
+    wi = np.array([math.sin(th_i), 0.0, math.cos(th_i)])
+    wo = np.array([-math.sin(th_o), 0.0, math.cos(th_o)])
+    return wi, wo, math.cos(0.5 * (th_i + th_o))
+
+
+@pytest.mark.parametrize("alpha", [0.1, 0.4])
+def test_conductor_fresnel_is_schlick(alpha):
+    """Schlick's approximation F = f0 + (1 - f0)(1 - cos)^5, cos between the
+    incident direction and the microfacet normal (Schlick 1994): the conductor
+    value is F times terms that do not depend on f0, so its ratio at two f0
+    isolates F.  At cos = 1 the ratio to f0 = 1 is f0, at cos = 1/2 it is
+    f0 + (1 - f0)/32, at grazing it tends to 1, and with f0 = 0 it is
+    (1 - cos)^5 at asymmetric angles (the cosine is taken at the half
+    vector, not at either direction)."""
+    C = scenes.BSDF_CONDUCTOR
+
+    def ratio(f0, wi, wo):
+        a = oracle.bsdf_eval(C, wi, wo, f0=(f0, f0, f0), alpha=alpha)[0]
+        b = oracle.bsdf_eval(C, wi, wo, f0=(1.0, 1.0, 1.0), alpha=alpha)[0]
+        assert np.all(b > 0)
+        return a / b
+
+    up = np.array([0.0, 0.0, 1.0])
+    for f0 in (0.0, 0.3, 0.9):
+        np.testing.assert_allclose(ratio(f0, up, up), f0, rtol=1e-12, atol=1e-15)
+        wi, wo, c = _half_angle_pair(math.pi / 3, math.pi / 3)
+        assert math.isclose(c, 0.5, rel_tol=1e-12)
+        np.testing.assert_allclose(ratio(f0, wi, wo), f0 + (1 - f0) / 32, rtol=1e-10)
+        wi, wo, c = _half_angle_pair(math.pi / 2 - 1e-6, math.pi / 2 - 1e-6)
+        np.testing.assert_allclose(ratio(f0, wi, wo), 1.0, rtol=1e-5)
+    for th_i, th_o in ((0.2, 1.1), (1.3, 0.4), (0.9, 0.0)):
+        wi, wo, c = _half_angle_pair(th_i, th_o)
+        np.testing.assert_allclose(ratio(0.0, wi, wo), (1 - c) ** 5, rtol=1e-10)
+
+
+def test_dielectric_transmission_generalised_reciprocity():
+    """Radiance BSDF of a refracting interface (Veach 1997, generalised
+    reciprocity): f(a, b) / n_a^2 = f(b, a) / n_b^2 for a camera-side
+    direction a in the medium of index n_a and a light-side direction b in
+    index n_b (outside 1, inside eta = 1.5).  eval() returns f |cos theta_b|,
+    so the values are divided by the cosine of their second argument."""
+    D = scenes.BSDF_DIELECTRIC
+    eta = 1.5
+    rng = np.random.default_rng(12)
+    n_checked = 0
+    for _ in range(400):
+        a = rng.normal(size=3); a /= np.linalg.norm(a)
+        b = rng.normal(size=3); b /= np.linalg.norm(b)
+        if a[2] * b[2] >= 0:
+            b[2] = -b[2]   # opposite sides: transmission
+        for alpha in (0.1, 0.35):
+            fab = oracle.bsdf_eval(D, a, b, alpha=alpha, eta=eta)[0][0] / abs(b[2])
+            fba = oracle.bsdf_eval(D, b, a, alpha=alpha, eta=eta)[0][0] / abs(a[2])
+            na = 1.0 if a[2] > 0 else eta
+            nb = 1.0 if b[2] > 0 else eta
+            if fab == 0 and fba == 0:
+                continue
+            n_checked += 1
+            assert math.isclose(fab / na ** 2, fba / nb ** 2, rel_tol=1e-10), (a, b, alpha)
+    assert n_checked > 100
+
+
+@pytest.mark.parametrize("inside", [False, True])
+def test_dielectric_transmission_normal_incidence_smooth_limit(inside):
+    """As the roughness goes to zero the transmitted part of a normally
+    incident camera direction integrates to the smooth interface's radiance
+    transmittance: (1 - F0) (n_camera / n_light)^2 with F0 = ((eta - 1) /
+    (eta + 1))^2 = 0.04 -- 0.96 / 2.25 looking from outside into glass,
+    0.96 x 2.25 looking out from inside (radiance scales with the square of
+    the index, Veach 1997).  The integrand is symmetric about the normal;
+    the polar integral runs in log(theta) to resolve the peak of width ~alpha."""
+    D = scenes.BSDF_DIELECTRIC
+    eta, alpha = 1.5, 2e-3
+    s = -1.0 if inside else 1.0
+    wi = np.array([0.0, 0.0, s])
+    lt = np.linspace(math.log(1e-9), math.log(math.pi / 2), 20001)
+    th = np.exp(lt)
+    vals = np.empty(th.size)
+    for i, t in enumerate(th):
+        wo = np.array([math.sin(t), 0.0, -s * math.cos(t)])
+        vals[i] = oracle.bsdf_eval(D, wi, wo, alpha=alpha, eta=eta)[0][0]
+    g = vals * np.sin(th) * th   # d(omega) = sin(theta) dtheta dphi, dtheta = theta dlog(theta)
+    integral = 2 * math.pi * float(np.sum(0.5 * (g[1:] + g[:-1]) * np.diff(lt)))
+    f0 = ((eta - 1) / (eta + 1)) ** 2
+    want = (1 - f0) * (eta ** 2 if inside else 1 / eta ** 2)
+    assert math.isclose(integral, want, rel_tol=1e-4), (integral, want)
+
+
+def test_plastic_diffuse_weight():
+    """Plastic's diffuse lobe (1 - F(cos_i)) (1 - F(cos_o)) rho / pi, times
+    cos_o: the value is affine in the albedo, so the difference of two evals
+    isolates it from the specular coat.  Both directions normal: 0.96^2 / pi;
+    incidence normal and outgoing at 60 degrees: 0.96 (1 - F(1/2)) 0.5 / pi,
+    and swapped, 0.96 (1 - F(1/2)) / pi -- F the exact dielectric Fresnel
+    pinned above."""
+    P = scenes.BSDF_PLASTIC
+    eta = 1.5
+
+    def diffuse(wi, wo):
+        one = oracle.bsdf_eval(P, wi, wo, albedo=(1.0, 1.0, 1.0), alpha=0.3, eta=eta)[0]
+        zero = oracle.bsdf_eval(P, wi, wo, albedo=(0.0, 0.0, 0.0), alpha=0.3, eta=eta)[0]
+        return one - zero
+
+    up = np.array([0.0, 0.0, 1.0])
+    tilt = np.array([math.sin(math.pi / 3), 0.0, 0.5])
+    f_half = oracle.fresnel(0.5, eta)
+    np.testing.assert_allclose(diffuse(up, up), 0.96 ** 2 / math.pi, rtol=1e-10)
+    np.testing.assert_allclose(diffuse(up, tilt), 0.96 * (1 - f_half) * 0.5 / math.pi, rtol=1e-10)
+    np.testing.assert_allclose(diffuse(tilt, up), (1 - f_half) * 0.96 / math.pi, rtol=1e-10)
+    # the albedo enters linearly: rho = 0.25 gives a quarter of the lobe
+    quarter = (oracle.bsdf_eval(P, up, up, albedo=(0.25, 0.25, 0.25), alpha=0.3, eta=eta)[0]
+               - oracle.bsdf_eval(P, up, up, albedo=(0.0, 0.0, 0.0), alpha=0.3, eta=eta)[0])
+    np.testing.assert_allclose(quarter, 0.25 * 0.96 ** 2 / math.pi, rtol=1e-10)
+
+
 def test_bsdf_parameter_derivatives_by_finite_differences():
     """d f/d albedo and d f/d alpha of the eval() against FP64 central
     differences of eval() itself at perturbed parameters."""
