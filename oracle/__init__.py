@@ -48,6 +48,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_scene_new.restype = _vp
         L.oracle_scene_free.argtypes = [_vp]
+        L.oracle_scene_accel.argtypes = [_vp, _c_int]
         L.oracle_scene_eps.restype = _c_dbl
         L.oracle_scene_eps.argtypes = [_vp]
         L.oracle_env_pdf.restype = _c_dbl
@@ -78,10 +79,18 @@ def cam_array(cams) -> np.ndarray:
     return out
 
 
-class OracleScene:
-    """The oracle's own copy of a ``scenes.Scene`` (widened to FP64)."""
+# Scenes with at least this many triangles get the oracle's bounding-volume
+# hierarchy by default (it returns what the loop over all triangles returns).
+ACCEL_MIN_TRIANGLES = 4096
 
-    def __init__(self, sc):
+
+class OracleScene:
+    """The oracle's own copy of a ``scenes.Scene`` (widened to FP64).
+
+    accel: None = hierarchy from ACCEL_MIN_TRIANGLES triangles on; True /
+    False = force it on / off (every query then loops over all triangles)."""
+
+    def __init__(self, sc, accel: Optional[bool] = None):
         L = lib()
         self.sc = sc
         self._keep = []
@@ -110,6 +119,8 @@ class OracleScene:
         if not self.h:
             raise ValueError("oracle rejected the scene")
         self._keep = []  # the oracle copied everything
+        self.accel = bool(sc.n_triangles >= ACCEL_MIN_TRIANGLES) if accel is None else bool(accel)
+        L.oracle_scene_accel(_vp(self.h), _c_int(1 if self.accel else 0))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -138,7 +138,18 @@ struct Emitter {
   RGB radiance;
 };
 
+// Optional acceleration structure (see "Acceleration" below).
+struct BvhNode {
+  double lo[3], hi[3];
+  int a, b;  // interior: the two children; leaf: a = first index into order, b = -count
+};
+struct Bvh {
+  std::vector<BvhNode> nodes;
+  std::vector<int> order;  // triangle ids, leaf by leaf
+};
+
 struct Scene {
+  Bvh bvh;                 // empty: every query loops over all triangles
   std::vector<V3> pos;
   std::vector<double> uv;  // 2 per vertex
   std::vector<int> idx;    // 3 per triangle
@@ -244,42 +255,180 @@ struct Hit {
   double b[3] = {0, 0, 0};
 };
 
+// ---------------------------------------------------------------------------
+// Acceleration.  The definition of every ray query is the loop over all
+// triangles; for the ~1M-triangle scenes a binary bounding-volume hierarchy
+// may stand in for that loop without changing any answer.  Each triangle's
+// box is padded by 1e-4 of its own extent plus 1e-9 of the scene's, so any
+// point on the triangle, or within the ambiguity tolerances of it (which
+// reach at most a few 1e-5 of its extent), lies inside every box on the way
+// to it, well beyond the rounding of the slab test.  A query walks the boxes
+// its ray meets within its (padded) distance interval and examines their
+// triangles with exactly the per-triangle code of the loop; only triangles
+// the ray cannot reach are left out, and ties are resolved by id as the loop
+// resolves them, so the answers are the loop's bit for bit (the tests check
+// this on scenes small enough to loop over).
+// ---------------------------------------------------------------------------
+static int bvh_build_range(Scene& s, const std::vector<double>& blo, const std::vector<double>& bhi,
+                           const std::vector<double>& cen, int first, int count) {
+  Bvh& B = s.bvh;
+  const int id = (int)B.nodes.size();
+  B.nodes.push_back(BvhNode());
+  BvhNode nd;
+  double clo[3] = {kInf, kInf, kInf}, chi[3] = {-kInf, -kInf, -kInf};
+  for (int a = 0; a < 3; ++a) { nd.lo[a] = kInf; nd.hi[a] = -kInf; }
+  for (int k = first; k < first + count; ++k) {
+    const int t = B.order[k];
+    for (int a = 0; a < 3; ++a) {
+      nd.lo[a] = std::min(nd.lo[a], blo[3 * (size_t)t + a]);
+      nd.hi[a] = std::max(nd.hi[a], bhi[3 * (size_t)t + a]);
+      clo[a] = std::min(clo[a], cen[3 * (size_t)t + a]);
+      chi[a] = std::max(chi[a], cen[3 * (size_t)t + a]);
+    }
+  }
+  int axis = 0;
+  for (int a = 1; a < 3; ++a)
+    if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+  if (count <= 4 || !(chi[axis] > clo[axis])) {
+    nd.a = first;
+    nd.b = -count;
+    B.nodes[id] = nd;
+    return id;
+  }
+  // median split of the centroids along the widest axis
+  const int half = count / 2;
+  std::nth_element(B.order.begin() + first, B.order.begin() + first + half,
+                   B.order.begin() + first + count, [&](int x, int y) {
+                     return cen[3 * (size_t)x + axis] < cen[3 * (size_t)y + axis];
+                   });
+  nd.a = bvh_build_range(s, blo, bhi, cen, first, half);
+  nd.b = bvh_build_range(s, blo, bhi, cen, first + half, count - half);
+  B.nodes[id] = nd;
+  return id;
+}
+
+static void bvh_build(Scene& s) {
+  const int n = s.n_tris();
+  s.bvh.nodes.clear();
+  s.bvh.order.resize(n);
+  if (n == 0) return;
+  double slo[3] = {kInf, kInf, kInf}, shi[3] = {-kInf, -kInf, -kInf};
+  for (const V3& p : s.pos)
+    for (int a = 0; a < 3; ++a) { slo[a] = std::min(slo[a], p[a]); shi[a] = std::max(shi[a], p[a]); }
+  const double sext = std::max(shi[0] - slo[0], std::max(shi[1] - slo[1], shi[2] - slo[2]));
+  std::vector<double> blo(3 * (size_t)n), bhi(3 * (size_t)n), cen(3 * (size_t)n);
+  for (int t = 0; t < n; ++t) {
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    for (int v = 0; v < 3; ++v) {
+      const V3& p = s.pos[s.idx[3 * (size_t)t + v]];
+      for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+    }
+    const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    const double pad = 1e-4 * ext + 1e-9 * sext;
+    for (int a = 0; a < 3; ++a) {
+      blo[3 * (size_t)t + a] = lo[a] - pad;
+      bhi[3 * (size_t)t + a] = hi[a] + pad;
+      cen[3 * (size_t)t + a] = 0.5 * (lo[a] + hi[a]);
+    }
+    s.bvh.order[t] = t;
+  }
+  s.bvh.nodes.reserve((size_t)n + 2);
+  bvh_build_range(s, blo, bhi, cen, 0, n);
+}
+
+// Whether the ray o + t d meets the node's box for some t in [t0, t1].
+static bool box_meets(const BvhNode& N, V3 o, V3 d, double t0, double t1) {
+  double tn = t0, tf = t1;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0) {
+      if (o[a] < N.lo[a] || o[a] > N.hi[a]) return false;
+      continue;
+    }
+    double ta = (N.lo[a] - o[a]) / d[a], tb = (N.hi[a] - o[a]) / d[a];
+    if (ta > tb) std::swap(ta, tb);
+    tn = std::max(tn, ta);
+    tf = std::min(tf, tb);
+    if (tn > tf) return false;
+  }
+  return true;
+}
+
+// Calls f(triangle) for every triangle of every leaf whose box the ray
+// meets within [t0, *t1]; *t1 may shrink while the walk goes on.  f returns
+// true to stop the walk.  Without a hierarchy: every triangle, in id order.
+template <class F>
+static void for_reachable(const Scene& s, V3 o, V3 d, double t0, const double* t1, F f) {
+  const Bvh& B = s.bvh;
+  if (B.nodes.empty()) {
+    for (int i = 0; i < s.n_tris(); ++i)
+      if (f(i)) return;
+    return;
+  }
+  int stack[128];  // median splits: depth <= log2(n / 4) + 2 < 64 for any int n
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const BvhNode& N = B.nodes[stack[--sp]];
+    if (!box_meets(N, o, d, t0, *t1)) continue;
+    if (N.b < 0) {
+      for (int k = 0; k < -N.b; ++k)
+        if (f(B.order[N.a + k])) return;
+      continue;
+    }
+    stack[sp++] = N.b;
+    stack[sp++] = N.a;
+  }
+}
+
+// The distance interval a query with tolerance 1e-6 x max(1, |t|) reaches:
+// [lo, hi] widened by 1e-5 x max(1, |lo|, |hi|).
+static inline void widen(double* lo, double* hi) {
+  const double w = 1e-5 * std::max(1.0, std::max(std::fabs(*lo), std::fabs(*hi)));
+  *lo -= w;
+  *hi += w;
+}
+
 // Flag the ray if any triangle's edge passes within kTolBary of it in front
 // of t_lim, or another triangle is hit within kTolT of t_hit.
 static void scan_edges(const Scene& s, V3 o, V3 d, double tmin, double t_lim, int hit_prim,
                        bool skip_null) {
-  for (int j = 0; j < s.n_tris(); ++j) {
-    if (skip_null && s.mats[s.tri_mat[j]].type == 0) continue;
+  double w0 = tmin, w1 = t_lim;
+  widen(&w0, &w1);
+  for_reachable(s, o, d, w0, &w1, [&](int j) -> bool {
+    if (skip_null && s.mats[s.tri_mat[j]].type == 0) return false;
     V3 p0 = s.pos[s.idx[3 * j]], p1 = s.pos[s.idx[3 * j + 1]], p2 = s.pos[s.idx[3 * j + 2]];
     V3 e1 = p1 - p0, e2 = p2 - p0, pv = cross(d, e2);
     double det = dot(e1, pv);
-    if (std::fabs(det) <= 1e-14 * length(e1) * length(e2)) continue;
+    if (std::fabs(det) <= 1e-14 * length(e1) * length(e2)) return false;
     V3 tv = o - p0;
     double bu = dot(tv, pv) / det;
     V3 qv = cross(tv, e1);
     double bv = dot(d, qv) / det;
     double tt = dot(e2, qv) / det;
     double tol_t = kTolT * std::max(1.0, std::fabs(tt));
-    if (!(tt > tmin - tol_t && tt < t_lim + tol_t)) continue;
+    if (!(tt > tmin - tol_t && tt < t_lim + tol_t)) return false;
     double bmin = std::min(std::min(bu, bv), 1.0 - bu - bv);
-    if (std::fabs(bmin) < kTolBary) { flag_if(true); return; }
-    if (bmin > 0 && j != hit_prim && std::fabs(tt - t_lim) <= tol_t) { flag_if(true); return; }
-    if (bmin > 0 && std::fabs(tt - tmin) <= tol_t) { flag_if(true); return; }
-  }
+    bool flag = std::fabs(bmin) < kTolBary ||
+                (bmin > 0 && j != hit_prim && std::fabs(tt - t_lim) <= tol_t) ||
+                (bmin > 0 && std::fabs(tt - tmin) <= tol_t);
+    if (flag) flag_if(true);
+    return flag;
+  });
 }
 
+// Closest hit: the minimum t over all triangles, ties to the lowest id.
 static Hit closest_hit(const Scene& s, V3 o, V3 d, double tmin, double tmax) {
   RayPre rp = ray_pre(d);
   Hit h;
   double best = tmax;
-  for (int i = 0; i < s.n_tris(); ++i) {
+  for_reachable(s, o, d, tmin, &best, [&](int i) -> bool {
     double t, b[3];
-    if (tri_hit(s, i, o, rp, tmin, best, &t, b)) {
+    if (tri_hit(s, i, o, rp, tmin, tmax, &t, b) && (t < best || (t == best && i < h.prim))) {
       h.prim = i; h.t = t; h.b[0] = b[0]; h.b[1] = b[1]; h.b[2] = b[2];
       best = t;
     }
-  }
-  // ties: the strict "t < best" above keeps the first (lowest id) of equal t
+    return false;
+  });
   if (t_amb) scan_edges(s, o, d, tmin, h.prim >= 0 ? h.t : tmax, h.prim, false);
   return h;
 }
@@ -288,12 +437,15 @@ static Hit closest_hit(const Scene& s, V3 o, V3 d, double tmin, double tmax) {
 static bool occluded(const Scene& s, V3 o, V3 d, double tmax) {
   if (t_amb) scan_edges(s, o, d, 0.0, tmax, -1, true);
   RayPre rp = ray_pre(d);
-  for (int i = 0; i < s.n_tris(); ++i) {
-    if (s.mats[s.tri_mat[i]].type == BSDF_NULL) continue;
+  bool hit = false;
+  const double t1 = tmax;
+  for_reachable(s, o, d, 0.0, &t1, [&](int i) -> bool {
+    if (s.mats[s.tri_mat[i]].type == BSDF_NULL) return false;
     double t, b[3];
-    if (tri_hit(s, i, o, rp, 0.0, tmax, &t, b)) return true;
-  }
-  return false;
+    hit = tri_hit(s, i, o, rp, 0.0, tmax, &t, b);
+    return hit;
+  });
+  return hit;
 }
 
 // Offset origin of a ray leaving point p along d: to the side of the
@@ -1394,6 +1546,17 @@ void* oracle_scene_new(int nv, const float* positions, const float* uvs, int nt,
 
 void oracle_scene_free(void* h) { delete (Scene*)h; }
 
+// Builds (on != 0) or drops (on == 0) the bounding-volume hierarchy that
+// stands in for the loop over all triangles in every ray query.
+void oracle_scene_accel(void* h, int on) {
+  Scene& s = *(Scene*)h;
+  if (on) {
+    if (s.bvh.nodes.empty()) bvh_build(s);
+  } else {
+    s.bvh = Bvh();
+  }
+}
+
 double oracle_scene_eps(void* h) { return ((Scene*)h)->eps; }
 
 // Philox4x32-10 on n (counter, key) pairs: ctr [n][4], key [n][2] -> out [n][4].
@@ -1420,16 +1583,19 @@ void oracle_trace(void* h, int64_t n, const double* o, const double* d, const do
       t_out[i] = hh.t;
       for (int c = 0; c < 3; ++c) b_out[3 * i + c] = hh.b[c];
     }
-    // ambiguity: examine every triangle's plane hit with signed barycentrics
+    // ambiguity: examine every reachable triangle's plane hit with signed
+    // barycentrics
     int amb = 0;
     double tb = any ? tmax[i] : (prim[i] >= 0 ? t_out[i] : tmax[i]);
-    for (int j = 0; j < s.n_tris() && !amb; ++j) {
-      if (any && s.mats[s.tri_mat[j]].type == BSDF_NULL) continue;
+    double w0 = tmin[i], w1 = tmax[i];
+    widen(&w0, &w1);
+    for_reachable(s, O, D, w0, &w1, [&](int j) -> bool {
+      if (any && s.mats[s.tri_mat[j]].type == BSDF_NULL) return false;
       V3 p0 = s.pos[s.idx[3 * j]], p1 = s.pos[s.idx[3 * j + 1]], p2 = s.pos[s.idx[3 * j + 2]];
       V3 e1 = p1 - p0, e2 = p2 - p0, pv = cross(D, e2);
       double det = dot(e1, pv);
       double scale = length(e1) * length(e2);
-      if (std::fabs(det) <= 1e-12 * scale) continue;
+      if (std::fabs(det) <= 1e-12 * scale) return false;
       V3 tv = O - p0;
       double bu = dot(tv, pv) / det;
       V3 qv = cross(tv, e1);
@@ -1438,13 +1604,14 @@ void oracle_trace(void* h, int64_t n, const double* o, const double* d, const do
       double bmin = std::min(std::min(bu, bv), 1.0 - bu - bv);
       double tol_t = 1e-6 * std::max(1.0, std::fabs(tt));
       bool near_range = tt > tmin[i] - tol_t && tt < tmax[i] + tol_t;
-      if (!near_range) continue;
+      if (!near_range) return false;
       bool near_edge = std::fabs(bmin) <= 1e-6;
       bool inside = bmin > 1e-6;
       if (near_edge && tt <= tb + tol_t) amb = 1;
       if (inside && (std::fabs(tt - tmin[i]) <= tol_t || std::fabs(tt - tmax[i]) <= tol_t)) amb = 1;
       if (!any && inside && j != prim[i] && prim[i] >= 0 && std::fabs(tt - tb) <= tol_t) amb = 1;
-    }
+      return amb != 0;
+    });
     ambiguous[i] = amb;
   });
 }

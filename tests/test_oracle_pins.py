@@ -152,6 +152,63 @@ def test_any_hit_skips_null_and_respects_tmax():
     np.testing.assert_array_equal(prim, [-1, 1, 1])
 
 
+def _small_procedural():
+    return scenes.procedural(n_grid=64, n_spheres=24, sphere_res=(16, 8), env_size=(32, 16),
+                             n_lights=3, tex_size=16, width=24, height=24)
+
+
+@pytest.mark.parametrize("name", ["soup", "zoo", "procedural"])
+def test_hierarchy_queries_equal_the_loop_over_all_triangles(name):
+    """The oracle's bounding-volume hierarchy stands in for its loop over all
+    triangles: closest hits (id, t, barycentrics), any hits and the
+    ambiguity flags must be the loop's, bit for bit, on camera rays, rays
+    between random interior points, finite and infinite t_max."""
+    sc = {"soup": lambda: scenes.triangle_soup(3000, seed=4), "zoo": scenes.bsdf_zoo,
+          "procedural": _small_procedural}[name]()
+    fast, loop = oracle.OracleScene(sc, accel=True), oracle.OracleScene(sc, accel=False)
+    assert fast.accel and not loop.accel
+    rng = np.random.default_rng(8)
+    n = 6000
+    lo, hi = sc.positions.min(0), sc.positions.max(0)
+    o = rng.uniform(lo, hi, (n, 3))
+    d = rng.normal(size=(n, 3))
+    if sc.cameras:
+        cam = sc.cameras[0]
+        k = n // 2
+        o[:k] = cam.origin
+        d[:k] = oracle.camera_dirs(cam, rng.uniform(0, cam.width, k), rng.uniform(0, cam.height, k))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    tmin = np.where(np.arange(n) % 5 == 0, 0.05, 0.0)
+    tmax = np.where(np.arange(n) % 3 == 0, 0.7, np.inf)
+    for any_hit in (False, True):
+        a = fast.trace(o, d, tmin=tmin, tmax=tmax, any_hit=any_hit)
+        b = loop.trace(o, d, tmin=tmin, tmax=tmax, any_hit=any_hit)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+        assert (b[0] >= 0).mean() > 0.1
+
+
+def test_hierarchy_render_and_adjoint_equal_the_loop():
+    """Images, per-pixel ambiguity counts and gradients of the procedural
+    scene (all BSDF types, env map, quad lights, depth 6 with roulette) are
+    identical with and without the hierarchy (one thread, so that the
+    gradient sums run in the same order)."""
+    sc = _small_procedural()
+    fast, loop = oracle.OracleScene(sc, accel=True), oracle.OracleScene(sc, accel=False)
+    kw = dict(spp=3, max_depth=6, rr_depth=3, seed=5)
+    ia, ma = fast.render(ambiguity=True, **kw)
+    ib, mb = loop.render(ambiguity=True, **kw)
+    np.testing.assert_array_equal(ia, ib)
+    np.testing.assert_array_equal(ma, mb)
+    adj = np.random.default_rng(2).normal(size=ia.shape)
+    ga, ra = fast.adjoint(adj, threads=1, **kw)
+    gb, rb = loop.adjoint(adj, threads=1, **kw)
+    for x, y in zip(ga, gb):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(ra, rb)
+    assert np.abs(gb[0]).sum() > 0 and np.abs(rb).sum() > 0
+
+
 # ---------------------------------------------------------------------------
 # camera and frames
 # ---------------------------------------------------------------------------
