@@ -193,7 +193,9 @@ enum {
   DRT_STAT_TRIS = 3,      /* ray/triangle tests */
   DRT_STAT_VERTICES = 4,  /* scattering vertices shaded */
   DRT_STAT_SCATTER = 5,   /* gradient atomics issued (adjoint) */
-  DRT_STAT_LREM_MAX = 6,  /* adjoint: max over samples of |L_rem| at path end, as float bits */
+  DRT_STAT_LREM_MAX = 6,  /* adjoint: max over samples of |L_rem| / |L| at the path's end
+                             (max norms over channels; |L_rem| itself where L = 0), as
+                             float bits: the replay's relative residual */
   DRT_STAT_SAMPLES = 7    /* samples traced */
 };
 
@@ -337,8 +339,11 @@ drt_status drt_philox(const uint32_t* counters, const uint32_t* keys, int64_t n,
 
 /* L2 image loss l = (1/n) sum (img - target)^2 and its adjoint
  * adj = 2 (img - target) / n (the image-space adjoint that drives the
- * adjoint pass).  img, target, adj: device float [n]; loss: device float [1];
- * workspace: device float [drt_loss_workspace_floats(n)]. */
+ * adjoint pass).  img, target, adj: device float [n] (adj may be NULL: loss
+ * only); loss: device float [1]; workspace: device float
+ * [drt_loss_workspace_floats(n)] (per-block partial sums, overwritten).  The
+ * sum is carried in float32 pairs (error-free two-sum and fma product
+ * error), accurate to about 2^-44 before the final rounding to float. */
 int64_t drt_loss_workspace_floats(int64_t n);
 drt_status drt_loss_l2(const float* img, const float* target, int64_t n, float* adj, float* loss,
                        float* workspace, void* hip_stream);

@@ -142,9 +142,21 @@ struct Hit {
   int prim;  // original id
 };
 
+// a b - c d with one rounding's worth of error (Kahan's fma-based
+// difference of products; its relative error is at most 2 ulp, so its sign
+// is exact and it is zero only when a b = c d exactly).
+DEV float diff_of_products(float a, float b, float c, float d) {
+  const float w = __fmul_rn(c, d);
+  const float e = __builtin_fmaf(-c, d, w);  // w - c d, exactly
+  const float f = __builtin_fmaf(a, b, -w);
+  return f + e;
+}
+
 // Watertight ray/triangle test (no culling), t in (tmin, tmax] -- the caller
-// decides about t == tmax.  Exactly-zero edge functions are re-evaluated in
-// double precision, as the method asks.
+// decides about t == tmax.  An edge function that comes out exactly zero is
+// evaluated again without the rounding of its two products (the method's
+// fallback for rays through an edge or a vertex), in float32 by Kahan's
+// difference of products rather than in double precision.
 DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float& t_out, float& b1,
                   float& b2) {
   f3 A = mk(T.p0x, T.p0y, T.p0z) - r.o;
@@ -158,9 +170,9 @@ DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float&
   float V = Ax * Cy - Ay * Cx;
   float W = Bx * Ay - By * Ax;
   if (U == 0.f || V == 0.f || W == 0.f) {
-    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
-    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
-    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    U = diff_of_products(Cx, By, Cy, Bx);
+    V = diff_of_products(Ax, Cy, Ay, Cx);
+    W = diff_of_products(Bx, Ay, By, Ax);
   }
   if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return false;
   float det = U + V + W;

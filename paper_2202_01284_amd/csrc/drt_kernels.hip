@@ -487,7 +487,11 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       start();
       while (!step(std::true_type{})) {
       }
-      cnt.lrem_max = fmaxf(cnt.lrem_max, fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z))));
+      // replay residual relative to the sample's radiance (max norms; a
+      // path that collected nothing must end at exactly zero)
+      const float rmax = fmaxf(fabsf(Lrem.x), fmaxf(fabsf(Lrem.y), fabsf(Lrem.z)));
+      const float lmax = fmaxf(fabsf(L.x), fmaxf(fabsf(L.y), fabsf(L.z)));
+      cnt.lrem_max = fmaxf(cnt.lrem_max, lmax > 0.f ? rmax / lmax : rmax);
     } else if (JVP) {
       acc = acc + tL;
     } else if (MODE == MODE_CACHED_SAMPLES || SELF) {
@@ -791,39 +795,71 @@ __global__ void k_philox(const uint32_t* __restrict__ ctr, const uint32_t* __res
 // ---------------------------------------------------------------------------
 constexpr int kLossBlocks = 1024;
 
-__global__ __launch_bounds__(256) void k_loss_partial(const float* __restrict__ img,
-                                                      const float* __restrict__ tgt, int64_t n,
-                                                      float* __restrict__ adj,
-                                                      double* __restrict__ partial) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  const float scale = (float)(2.0 / (double)n);
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    float r = img[i] - tgt[i];
-    acc += (double)r * (double)r;
-    if (adj) adj[i] = r * scale;
-  }
-  red[threadIdx.x] = acc;
+// Float32 sums carried as unevaluated pairs (hi, lo) with |lo| <= ulp(hi)/2:
+// error-free transformations (Knuth's two-sum, the fma product error) keep
+// the rounding errors, so a sum of a few million squares keeps ~2^-44 of
+// relative accuracy without double precision.
+struct F2 {
+  float hi, lo;
+};
+DEV F2 two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  const float e = (a - (s - bb)) + (b - bb);
+  return F2{s, e};
+}
+DEV F2 f2_add(F2 a, F2 b) {
+  const F2 s = two_sum(a.hi, b.hi);
+  const float lo = s.lo + (a.lo + b.lo);
+  const float hi = s.hi + lo;  // renormalise (fast two-sum: |s.hi| >= |lo|)
+  return F2{hi, lo - (hi - s.hi)};
+}
+DEV F2 f2_add_square(F2 acc, float r) {
+  const float p = __fmul_rn(r, r);
+  const float pe = __builtin_fmaf(r, r, -p);  // r r - p, exactly
+  return f2_add(acc, F2{p, pe});
+}
+DEV void f2_block_reduce(F2& v, F2* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) red[threadIdx.x] = f2_add(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  v = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ partial, int nb,
-                                                    int64_t n, float* __restrict__ loss) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+// partial[2 b], partial[2 b + 1] = (hi, lo) of block b's sum of squares.
+__global__ __launch_bounds__(256) void k_loss_partial(const float* __restrict__ img,
+                                                      const float* __restrict__ tgt, int64_t n,
+                                                      float adj_scale, float* __restrict__ adj,
+                                                      float* __restrict__ partial) {
+  __shared__ F2 red[256];
+  F2 acc{0.f, 0.f};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float r = img[i] - tgt[i];
+    acc = f2_add_square(acc, r);
+    if (adj) adj[i] = r * adj_scale;
   }
-  if (threadIdx.x == 0) loss[0] = (float)(red[0] / (double)n);
+  f2_block_reduce(acc, red);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = acc.hi;
+    partial[2 * blockIdx.x + 1] = acc.lo;
+  }
+}
+
+// loss = (sum of the partial pairs) / n; inv_n = 1/n rounded to float.
+__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ partial, int nb,
+                                                    float inv_n, float* __restrict__ loss) {
+  __shared__ F2 red[256];
+  F2 acc{0.f, 0.f};
+  for (int i = threadIdx.x; i < nb; i += 256) acc = f2_add(acc, F2{partial[2 * i], partial[2 * i + 1]});
+  f2_block_reduce(acc, red);
+  if (threadIdx.x == 0) {
+    // (hi + lo) / n with the pair's two roundings kept apart
+    const float q = acc.hi * inv_n;
+    loss[0] = __builtin_fmaf(acc.lo, inv_n, q);
+  }
 }
 
 struct AdamArgs {
@@ -1046,10 +1082,11 @@ hipError_t launch_loss_l2(const float* img, const float* tgt, int64_t n, float* 
                           float* ws, hipStream_t st) {
   int64_t nb = (n + 255) / 256;
   if (nb > kLossBlocks) nb = kLossBlocks;
-  double* partial = reinterpret_cast<double*>(ws);
-  hipLaunchKernelGGL(k_loss_partial, dim3((unsigned)nb), dim3(256), 0, st, img, tgt, n, adj,
-                     partial);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, partial, (int)nb, n, loss);
+  // the two scale factors are rounded to float once, here on the host
+  const float adj_scale = (float)(2.0 / (double)n), inv_n = (float)(1.0 / (double)n);
+  hipLaunchKernelGGL(k_loss_partial, dim3((unsigned)nb), dim3(256), 0, st, img, tgt, n, adj_scale,
+                     adj, ws);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, ws, (int)nb, inv_n, loss);
   return hipGetLastError();
 }
 

@@ -89,6 +89,80 @@ def test_reverse_config_records_equal_retrace_dense(c3):
     assert abs(hr.item() - pr.item()) <= 1e-3 * abs(pr.item())
 
 
+def test_reverse_config_central_differences_texels_and_roughness(c3):
+    """Central differences (h = 1e-2, common random numbers) of the GPU primal
+    at the reverse-mode size (1024^2, 16 spp, depth 3, 4096^2 texture)
+    against the replayed adjoint in its bench launch (intersection records):
+      - 64 seeded texels with a non-zero gradient, random dense image
+        adjoint: the estimator is a polynomial of degree <= 2 in each texel
+        with sampling independent of it, so the differences are exact up to
+        float32 rounding: |g - fd| <= 2e-2 max(|fd|, 1e-3 max|fd|);
+      - the conductor roughness under the L2-loss adjoint against a target
+        rendered at roughness 0.2: sampling depends on the roughness, so the
+        differences are noise-limited; 16 independent seeds of 64 spp, the
+        mean adjoint within max(2e-2 |fd|, 3 SE) of the mean difference, SE
+        the standard error of the per-seed differences g_s - fd_s."""
+    drt = _drt()
+    sc, gs = c3
+    tex = torch.from_numpy(sc.textures[0]).cuda()
+    flat = tex.view(-1)
+    rough = torch.from_numpy(sc.roughness).cuda()
+    spp, depth, h = 16, 3, 1e-2
+    adj = torch.from_numpy(np.random.default_rng(7).normal(size=(1, 1024, 1024, 3))
+                           .astype(np.float32)).cuda()
+    gt, _ = drt.render_adjoint(gs, [tex], rough, sc.cameras, adj, spp, depth, seed=9,
+                               hit_records=drt.adjoint_hit_records(sc.cameras, spp, depth))
+    g = gt[0].view(-1).double().cpu().numpy()
+    cand = np.flatnonzero(np.abs(g) > 1e-2 * np.abs(g).max())
+    pick = np.random.default_rng(11).choice(cand, 64, replace=False)
+    fds = []
+    for k in pick:
+        k = int(k)
+        orig = flat[k].item()
+        flat[k] = orig + h
+        vp = flat[k].item()
+        Ip = drt.render_forward(gs, [tex], rough, sc.cameras, spp, depth, seed=9)
+        flat[k] = orig - h
+        vm = flat[k].item()
+        Im = drt.render_forward(gs, [tex], rough, sc.cameras, spp, depth, seed=9)
+        flat[k] = orig
+        fds.append(float((adj.double() * (Ip.double() - Im.double())).sum()) / (vp - vm))
+    fds = np.array(fds)
+    scale = np.abs(fds).max()
+    err = np.abs(g[pick] - fds)
+    print("texel fd: max rel err", (err / np.maximum(np.abs(fds), 1e-3 * scale)).max(), flush=True)
+    assert np.all(err <= 2e-2 * np.maximum(np.abs(fds), 1e-3 * scale))
+
+    # roughness: L2-loss adjoint against a target at roughness 0.2
+    n_seeds, spp_r = 16, 64
+    target = drt.render_forward(gs, [tex], torch.full_like(rough, 0.2), sc.cameras, 64, depth, seed=1284)
+    img = drt.render_forward(gs, [tex], rough, sc.cameras, spp_r, depth, seed=3)
+    _, dI = drt.loss_l2(img, target)
+    dI64 = dI.double()
+    hits = drt.adjoint_hit_records(sc.cameras, spp_r, depth)
+    gs_, fd_ = [], []
+    for s in range(n_seeds):
+        seed = 1000 + s
+        _, gr = drt.render_adjoint(gs, [tex], rough, sc.cameras, dI, spp_r, depth, seed=seed,
+                                   hit_records=hits)
+        a0 = float(rough[0].item())
+        rp, rm = rough.clone(), rough.clone()
+        rp[0] = a0 + h
+        rm[0] = a0 - h
+        Ip = drt.render_forward(gs, [tex], rp, sc.cameras, spp_r, depth, seed=seed)
+        Im = drt.render_forward(gs, [tex], rm, sc.cameras, spp_r, depth, seed=seed)
+        step = float(rp[0].item()) - float(rm[0].item())
+        gs_.append(float(gr[0].item()))
+        fd_.append(float((dI64 * (Ip.double() - Im.double())).sum()) / step)
+    gs_, fd_ = np.array(gs_), np.array(fd_)
+    diff = gs_ - fd_
+    se = diff.std(ddof=1) / np.sqrt(n_seeds)
+    print(f"roughness: adjoint {gs_.mean():.6g}, central differences {fd_.mean():.6g}, "
+          f"diff {diff.mean():.3g}, SE {se:.3g}", flush=True)
+    assert abs(diff.mean()) <= max(2e-2 * abs(fd_.mean()), 3 * se)
+    assert abs(fd_.mean()) > 3 * fd_.std(ddof=1) / np.sqrt(n_seeds)   # a resolved derivative
+
+
 @pytest.fixture(scope="module")
 def c2():
     assert torch.cuda.is_available()

@@ -3,12 +3,14 @@ the GPU computes in BF16), through the C ABI.
 
 Tolerances: the encoding's hash-grid features within 2 x 2.4e-7 x N_l + 1e-6
 at level resolution N_l (a float32 position's error scaled to the level), the
-other inputs within 2e-6; network outputs and gradients ||g - o|| <= 2e-3 ||o||
-against the oracle's BF16 emulation (rounding points are the same; FP32 vs
-FP64 accumulation can flip an individual BF16 rounding, 1 ulp = 2^-8
-relative); the fused training pass within 3x the oracle's own change under
-2-ulp float32 position perturbations; records and images as in
-test_gpu_parity.
+other inputs within 2e-6; network outputs and gradients within 1e-3 against
+the oracle's BF16 emulation, in norm and element by element (check_net;
+rounding points are the same; FP32 vs FP64 accumulation can flip an
+individual BF16 rounding, 1 ulp = 2^-8 relative); the fused training pass
+within 1e-3 on records whose encoding is exact in float32 (so both sides
+feed the network identical BF16 inputs), and on scene records within 3x the
+oracle's own change under 2-ulp float32 position perturbations; records and
+images as in test_gpu_parity.
 """
 import math
 
@@ -32,6 +34,26 @@ def rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def check_net(g, o, what, tol=1e-3):
+    """Network outputs and gradients against the BF16-emulating oracle:
+    ||g - o|| <= tol ||o||, and element by element |g - o| <= tol |o| on
+    every entry with |o| >= 1e-2 max|o| (smaller entries within tol 1e-2
+    max|o|)."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    o = np.asarray(o, np.float64).reshape(-1)
+    r = rel(g, o)
+    err = np.abs(g - o)
+    scale = np.abs(o).max()
+    big = np.abs(o) >= 1e-2 * scale
+    worst = (err[big] / np.abs(o[big])).max() if big.any() else 0.0
+    print(f"{what}: rel l2 {r:.3g}, worst per-entry rel {worst:.3g} over {big.sum()} entries, "
+          f"small-entry max err {err[~big].max() if (~big).any() else 0.0:.3g} (scale {scale:.3g})",
+          flush=True)
+    assert r <= tol, (what, r)
+    assert np.all(err[big] <= tol * np.abs(o[big])), (what, worst)
+    assert np.all(err[~big] <= tol * 1e-2 * scale), what
 
 
 def _records(cfg, n, seed):
@@ -96,9 +118,8 @@ def test_network_forward_vs_bf16_oracle():
     x[:, 68:] = 0
     y = drt.nrc_forward(torch.from_numpy(W).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
     yo = oracle.mlp_forward(x.astype(np.float64), W.astype(np.float64), emu=True)
-    r = rel(y, yo)
-    print("forward rel", r, "vs fp64", rel(y, oracle.mlp_forward(x, W.astype(np.float64))), flush=True)
-    assert r <= 2e-3
+    print("forward vs fp64 rel", rel(y, oracle.mlp_forward(x, W.astype(np.float64))), flush=True)
+    check_net(y, yo, "network forward")
 
 
 def test_network_backward_vs_bf16_oracle():
@@ -118,12 +139,8 @@ def test_network_backward_vs_bf16_oracle():
     dW, dx = dW.cpu().numpy(), dx.cpu().numpy()
     offs = [0, 5120, 9216, 13312, 17408, 17600]
     for l in range(5):
-        r = rel(dW[offs[l]:offs[l + 1]], dWo[offs[l]:offs[l + 1]])
-        print(f"dW layer {l} rel {r:.3g}", flush=True)
-        assert r <= 2e-3
-    r = rel(dx[:, :32], dxo[:, :32])
-    print("dx rel", r, flush=True)
-    assert r <= 2e-3
+        check_net(dW[offs[l]:offs[l + 1]], dWo[offs[l]:offs[l + 1]], f"dW layer {l}")
+    check_net(dx[:, :32], dxo[:, :32], "dx (hash features)")
     assert np.all(dx[:, 32:] == 0)
 
 
@@ -234,6 +251,80 @@ def test_training_pass_vs_oracle():
     assert abs(loss.item() - lo) <= 2e-3 * lo
     assert rw <= max(3 * sens_w, 2e-3)
     assert rg <= max(3 * sens_g, 2e-3)
+
+
+def _bf16_far_from_ties(v, margin=2.0 ** -14):
+    """True where the FP64 value v lies more than margin x |v| from every
+    BF16 rounding boundary (so a float32 evaluation of it rounds to the same
+    BF16 value)."""
+    v = np.asarray(v, np.float64)
+    f = v.astype(np.float32)
+    bits = f.view(np.uint32) & np.uint32(0xFFFF0000)
+    lo = bits.view(np.float32).astype(np.float64)
+    up = (bits + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    mid = 0.5 * (lo + up)
+    far = np.abs(np.abs(v) - np.abs(mid)) > margin * np.abs(v)
+    return far | (v == 0)
+
+
+def test_training_pass_exact_inputs_vs_oracle():
+    """The fused training pass on records whose encoding is exact in float32:
+    positions on a 1/16 grid of a power-of-two cache box (normalised
+    coordinates, cell fractions and trilinear weights are short dyadic
+    numbers), grid features multiples of 2^-6, roughness and albedo
+    multiples of 1/8, and directions whose 16 SH values lie away from BF16
+    rounding boundaries.  Both sides then feed the network identical BF16
+    inputs (checked first), and loss, weight gradient and hash-grid gradient
+    agree to 1e-3: what is left is FP32 vs FP64 accumulation in the layers."""
+    drt = _drt()
+    cfg = dict(levels=16, features=2, log2_table=14, base_res=16, max_res=2048,
+               bbox_lo=(-1.0, 0.0, -1.0), bbox_hi=(1.0, 2.0, 1.0), trunc_vertex=3)
+    rng = np.random.default_rng(21)
+    n = 4096 + 5
+    # directions whose SH16 values round to BF16 the same in FP32 and FP64
+    cand = rng.normal(size=(20000, 3))
+    cand = (cand / np.linalg.norm(cand, axis=1, keepdims=True)).astype(np.float32)
+    keep = np.array([_bf16_far_from_ties(oracle.sh16(c.astype(np.float64))).all() for c in cand[:4000]])
+    dirs = cand[:4000][keep]
+    assert dirs.shape[0] > 500
+    rec = np.zeros((n, 16), np.float32)
+    lo, hi = np.array(cfg["bbox_lo"]), np.array(cfg["bbox_hi"])
+    rec[:, 0:3] = lo + (hi - lo) * rng.integers(0, 17, (n, 3)) / 16.0
+    rec[:, 3:6] = dirs[rng.integers(0, dirs.shape[0], n)]
+    rec[:, 6:9] = dirs[rng.integers(0, dirs.shape[0], n)]
+    rec[:, 9] = rng.integers(1, 9, n) / 8.0
+    rec[:, 10:13] = rng.integers(0, 9, (n, 3)) / 8.0
+    rec[:, 13:16] = rng.uniform(0.05, 2.0, (n, 3))
+    valid = (rng.random(n) < 0.9).astype(np.int32)
+    grid = (rng.integers(-64, 65, (16, 1 << cfg["log2_table"], 2)) / 64.0).astype(np.float16)
+    W, _ = scenes.nrc_init(cfg, seed=8)
+    W = W.copy()
+    W[17408:] = np.abs(W[17408:]) * 4.0          # positive, larger output layer
+    # identical inputs: the GPU encoding equals the oracle's (hash features
+    # exactly, the rest after BF16 rounding)
+    x_g = drt.nrc_encode(cfg, torch.from_numpy(grid.reshape(-1)).cuda(),
+                         torch.from_numpy(rec).cuda()).cpu().numpy()
+    f64 = rec[:, :13].astype(np.float64)
+    x_o = oracle.nrc_encode(f64, cfg, grid.astype(np.float32))
+    np.testing.assert_array_equal(x_g[:, :32], x_o[:, :32])
+    bf = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(bf(x_g), bf(x_o.astype(np.float32)))
+    dWg = torch.zeros(17600, dtype=torch.float32, device="cuda")
+    dGg = torch.zeros(grid.size, dtype=torch.float32, device="cuda")
+    cnt = torch.tensor([int(valid.sum())], dtype=torch.int32, device="cuda")
+    loss = drt.nrc_train(cfg, torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda(),
+                         torch.from_numpy(rec).cuda(), torch.from_numpy(valid).cuda(), cnt, dWg, dGg)
+    v = valid.astype(bool)
+    y = oracle.mlp_forward(x_o[v], W.astype(np.float64), emu=True)
+    lo_, dy = oracle.rel_l2(y, rec[v, 13:16].astype(np.float64))
+    dWo, dx = oracle.mlp_backward(x_o[v], W.astype(np.float64), dy, emu=True)
+    dGo = oracle.nrc_grid_backward(f64[v], cfg, dx)
+    rw, rg = rel(dWg.cpu().numpy(), dWo), rel(dGg.cpu().numpy(), dGo)
+    print(f"exact-input training pass: loss {loss.item()} vs {lo_}; dW rel {rw:.3g}; "
+          f"dgrid rel {rg:.3g}", flush=True)
+    assert abs(loss.item() - lo_) <= 1e-4 * lo_
+    assert rw <= 1e-3
+    assert rg <= 1e-3
 
 
 def test_cached_render_vs_oracle():

@@ -247,8 +247,10 @@ def test_adjoint_parity(case):
         check_grad(g.cpu().numpy(), o, f"{case} texture {i}")
     if len(sc.roughness):
         check_grad(gr.cpu().numpy(), orr, f"{case} roughness")
-    # replay residual: the subtraction recovers the full path radiance
-    assert st["lrem_max"] <= 1e-4 * max(1.0, float(np.abs(adj).max()) * 100), st
+    # replay residual: the subtraction recovers each sample's full radiance,
+    # up to float32 rounding of its few terms (<= 1e-5 of the sample's
+    # radiance, whatever the adjoint)
+    assert st["lrem_max"] <= 1e-5, st
 
 
 @pytest.mark.parametrize("case", list(ADJ_CASES))
@@ -278,7 +280,7 @@ def test_adjoint_with_intersection_records(case):
     st_h, st_p = drt.read_stats(st_h), drt.read_stats(st_p)
     print(case, "rays with records", st_h["rays"], "re-traced", st_p["rays"], flush=True)
     assert 2 * st_h["rays"] == st_p["rays"] and 2 * st_h["shadow_rays"] == st_p["shadow_rays"]
-    assert st_h["lrem_max"] <= 1e-4 * max(1.0, float(np.abs(adj).max()) * 100), st_h
+    assert st_h["lrem_max"] <= 1e-5, st_h
     for i, (h, p) in enumerate(zip(ht, pt)):
         h, p = h.cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64)
         r = np.linalg.norm(h - p) / np.linalg.norm(p)

@@ -727,6 +727,36 @@ def test_adjoint_albedo_matches_central_differences():
 # loss and Adam
 # ---------------------------------------------------------------------------
 
+def test_roughness_gradient_matches_central_differences_in_expectation():
+    """The oracle's roughness gradient (detached sampling) against central
+    differences of its own estimator in the roughness (h = 1e-2, common
+    random numbers, no roulette).  Sampling depends on the roughness, so a
+    single seed's differences carry noise the detached gradient does not;
+    both are unbiased for the derivative of the expected image.  16 seeds of
+    128 spp: the mean difference within max(2e-2 |fd|, 3 SE) (3 SE is ~10%
+    of the derivative here)."""
+    sc = scenes.cornell(conductor=True, width=24, height=24)
+    orc = oracle.OracleScene(sc)
+    adj = np.ones((1, 24, 24, 3)) / (24 * 24 * 3)     # derivative of the mean brightness
+    a0 = float(sc.roughness[0])
+    h = 1e-2
+    g, fd = [], []
+    for s in range(16):
+        seed = 300 + s
+        _, gr = orc.adjoint(adj, spp=128, max_depth=3, seed=seed)
+        ip = orc.render(spp=128, max_depth=3, seed=seed, roughness=np.array([a0 + h], np.float32))
+        im = orc.render(spp=128, max_depth=3, seed=seed, roughness=np.array([a0 - h], np.float32))
+        step = float(np.float32(a0 + h)) - float(np.float32(a0 - h))
+        g.append(gr[0])
+        fd.append(float((adj * (ip - im)).sum()) / step)
+    g, fd = np.array(g), np.array(fd)
+    diff = g - fd
+    se = diff.std(ddof=1) / math.sqrt(len(diff))
+    assert abs(fd.mean()) > 3 * fd.std(ddof=1) / math.sqrt(len(fd))
+    assert abs(diff.mean()) <= max(2e-2 * abs(fd.mean()), 3 * se), (g.mean(), fd.mean(), se)
+    assert 3 * se < 0.15 * abs(fd.mean())     # the comparison resolves a 15% error
+
+
 def test_loss_l2_closed_form():
     img = np.array([1.0, 2.0, 3.0, 4.0])
     tgt = np.array([0.0, 2.0, 5.0, 3.0])
