@@ -247,6 +247,26 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
                                    const drt_grads* grads, void* hit_records, int64_t hit_bytes,
                                    void* hip_stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc:
+ * drt_render_adjoint_hits with the intersection records and the work
+ * counter in a scratch array that the library holds in device memory
+ * instead of a caller buffer.  Same arguments, results and conventions
+ * otherwise (gradients ADDED to grads).  The array holds
+ * DRT_NOALLOC_SCRATCH_BYTES (256 B counter + 32 MiB of record slots); each
+ * GPU the library runs this on keeps its own copy until the process ends.
+ * Sizes whose drt_render_adjoint_hit_bytes() exceeds it return
+ * DRT_EUNSUPPORTED before anything is enqueued (with 4096 resident
+ * workgroups, as on MI355X: max_depth <= 8).  Calls nothing that allocates
+ * (no hipMalloc / hipFree); the counter is cleared by a fill kernel on the
+ * stream.  All calls on one GPU share its array: calls that overlap on one
+ * GPU (on any streams) race. */
+#define DRT_NOALLOC_SCRATCH_BYTES (256 + (32LL << 20))
+drt_status drt_render_adjoint_noalloc(const drt_scene* scene, const drt_params* params,
+                                      const drt_camera* cams, int32_t n_cams,
+                                      const drt_render_opts* opts, const float* adj_image,
+                                      const drt_grads* grads, void* hip_stream);
+
 /* The primal image by the wavefront variant of the same estimator (same
  * sample streams and conventions as drt_render_forward): per bounce, a
  * closest-hit kernel, a shading kernel and a shadow-ray kernel exchange the

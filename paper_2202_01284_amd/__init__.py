@@ -125,6 +125,9 @@ _SIGS = {
     "drt_render_adjoint_hits": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                          _c_i32, ctypes.POINTER(drt_render_opts), _vp,
                                          ctypes.POINTER(drt_grads), _vp, _c_i64, _vp]),
+    "drt_render_adjoint_noalloc": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
+                                            _c_i32, ctypes.POINTER(drt_render_opts), _vp,
+                                            ctypes.POINTER(drt_grads), _vp]),
     "drt_render_checkpointed_workspace_bytes": (_c_i64, [_c_i64, _c_i32]),
     "drt_render_checkpointed_forward": (_c_i32, [_vp, ctypes.POINTER(drt_params),
                                                  ctypes.POINTER(drt_camera), _c_i32,
@@ -467,6 +470,38 @@ def render_adjoint(scene: Scene, textures: Sequence, roughness, cams, adj_image,
         _check(lib.drt_render_adjoint(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
                                       _dp(adj_image, "adj_image"), ctypes.byref(g), _stream(stream)),
                "drt_render_adjoint")
+    return grad_textures, grad_roughness
+
+
+NOALLOC_SCRATCH_BYTES = 256 + (32 << 20)
+
+
+def render_adjoint_noalloc(scene: Scene, textures: Sequence, roughness, cams, adj_image, spp: int,
+                           max_depth: int, grad_textures, grad_roughness=None, rr_depth: int = NO_RR,
+                           seed: int = 2, flags: int = 0, stats=None, stream=None):
+    """drt_render_adjoint_noalloc: the replay from intersection records with
+    the records in the library's own device scratch.  The caller passes the
+    gradient buffers (added into); nothing is allocated here or in the
+    library."""
+    _expect(adj_image, "adj_image", _image_shape(cams))
+    g = drt_grads()
+    if len(grad_textures) > len(scene.tex_shapes):
+        raise ValueError("more gradient textures than scene textures")
+    for i, t in enumerate(grad_textures):
+        if t is not None:
+            _expect(t, f"grad texture {i}", scene.tex_shapes[i])
+            g.textures[i] = _dp(t, f"grad texture {i}")
+    if grad_roughness is not None:
+        _expect(grad_roughness, "grad roughness")
+        if grad_roughness.numel() < scene.n_roughness:
+            raise ValueError(f"grad roughness needs {scene.n_roughness} entries")
+        g.roughness = _dp(grad_roughness, "grad_roughness")
+    ca = _cams(cams)
+    p = _params(scene, textures, roughness)
+    o = _opts(spp, max_depth, rr_depth, seed, flags, stats)
+    _check(lib.drt_render_adjoint_noalloc(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                          _dp(adj_image, "adj_image"), ctypes.byref(g), _stream(stream)),
+           "drt_render_adjoint_noalloc")
     return grad_textures, grad_roughness
 
 

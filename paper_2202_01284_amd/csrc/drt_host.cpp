@@ -821,6 +821,42 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
   return ok();
 }
 
+drt_status drt_render_adjoint_noalloc(const drt_scene* scene, const drt_params* params,
+                                      const drt_camera* cams, int32_t n_cams,
+                                      const drt_render_opts* opts, const float* adj_image,
+                                      const drt_grads* grads, void* hip_stream) {
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!adj_image || !grads) return fail(DRT_EINVAL, "adj_image and grads are required");
+  const int64_t tiles = (int64_t)n_cams * ((cams[0].width + kTile - 1) / kTile) *
+                        ((cams[0].height + kTile - 1) / kTile);
+  if (tiles * adjoint_split(opts->spp) > ((int64_t)1 << 31))
+    return fail(DRT_EUNSUPPORTED, "image too large for the persistent replay");
+  const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
+                                                    opts->spp, opts->max_depth);
+  if (need <= 0) return fail(DRT_EINVAL, "invalid sizes for the intersection records");
+  if (need > kNoAllocScratchBytes)
+    return fail(DRT_EUNSUPPORTED,
+                "intersection records of %lld bytes exceed the library's scratch of %lld bytes "
+                "(lower max_depth; 4096 resident workgroups allow max_depth <= 8)",
+                (long long)need, (long long)kNoAllocScratchBytes);
+  void* scratch = nullptr;
+  hipError_t e = noalloc_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "scratch address (hipGetSymbolAddress)");
+  DGrads dg;
+  std::memset(&dg, 0, sizeof(dg));
+  for (int t = 0; t < scene->dev.n_tex; ++t) dg.tex[t] = grads->textures[t];
+  dg.rough = scene->dev.n_rough > 0 ? grads->roughness : nullptr;
+  dr.items = static_cast<uint32_t*>(scratch);
+  dr.hits = reinterpret_cast<int4*>(static_cast<char*>(scratch) + kHitHeader);
+  e = launch_render_adjoint(scene->dev, dp, dc, dr, adj_image, dg, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "render_adjoint launch");
+  return ok();
+}
+
 int64_t drt_render_wavefront_workspace_bytes(int64_t n_paths) {
   return n_paths < 0 || n_paths > kMaxSamples ? 0 : wavefront_workspace_bytes(n_paths);
 }

@@ -208,6 +208,15 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
 // device: as many as can be resident at once (0 if the device cannot be
 // queried).  The launch and the record size both use it.
 int adjoint_resident_groups();
+// Devices the per-device caches of the library cover.
+constexpr int kMaxDevices = 64;
+// Scratch of drt_render_adjoint_noalloc: the 256-byte work-counter header
+// and 32 MiB of record slots (4096 resident workgroups x depth 8 x 64 lanes
+// x 16 B).
+constexpr int64_t kNoAllocScratchBytes = DRT_NOALLOC_SCRATCH_BYTES;
+// Address of the calling thread's current device's copy of that scratch,
+// looked up once per device (hipGetSymbolAddress) and cached.
+hipError_t noalloc_scratch(void** out);
 hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
                                         const DRender& r, const float* adj, const DGrads& g,
                                         const DNrcIO& io, hipStream_t st);

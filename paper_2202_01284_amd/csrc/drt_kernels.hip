@@ -16,6 +16,7 @@
 // out of it, roughness gradients pre-reduced in LDS per workgroup, texel
 // gradients as hardware float atomics (no return value).
 #include <atomic>
+#include <mutex>
 
 #include "drt_device.h"
 
@@ -1020,9 +1021,9 @@ int adjoint_resident_groups() {
   // per device, queried once (host threads may race to fill it; they store
   // the same value): compute units x workgroups of the kernel that fit on one
   // at a time
-  static std::atomic<int> cached[64];
+  static std::atomic<int> cached[kMaxDevices];
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
   const int known = cached[dev].load(std::memory_order_relaxed);
   if (known > 0) return known;
   int cus = 0, per_cu = 0;
@@ -1127,6 +1128,39 @@ hipError_t launch_zero(void* p, int64_t n_words, hipStream_t st) {
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, n_words);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Library-held scratch for the entry point that allocates nothing: the
+// intersection records and work counter of the persistent replay.  Each GPU
+// holds its own copy for the life of the process.  In host code the array's
+// name is not a device address: kernels and fills only ever receive the
+// address hipGetSymbolAddress returned for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** out) {
+  static std::atomic<void*> ptrs[kMaxDevices];
+  static std::mutex mu;
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* p = ptrs[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(mu);
+    p = ptrs[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      // once per device, with that device current (hipGetDevice above)
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      if (!p) return hipErrorInvalidSymbol;
+      ptrs[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return hipSuccess;
 }
 
 }  // namespace drt

@@ -287,4 +287,7 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_nrc_collect_self_workspace_bytes(-1, 5) == 0
     assert drt.lib.drt_nrc_collect_self(h, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(c),
                                         fake, fake, 5, 1000, fake, fake, fake, fake, wsb, None) == -4
+    # the entry point that allocates nothing checks the scene before anything else
+    assert drt.lib.drt_render_adjoint_noalloc(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
+                                              ctypes.byref(g), None) == -4
     drt.lib.drt_scene_destroy(h)
