@@ -494,6 +494,50 @@ drt_status drt_nrc_collect_self(const drt_scene* scene, const drt_params* params
                                 int64_t n_paths, float* records, int32_t* valid, int32_t* count,
                                 void* workspace, int64_t workspace_bytes, void* hip_stream);
 
+/* Device state of a radiance cache (all caller-owned device memory).  The
+ * gradient buffers must be zero on the first frame; each frame leaves them
+ * zero again. */
+typedef struct {
+  float* weights;          /* [DRT_NRC_WEIGHTS] FP32 master weights */
+  float* weights_m;        /* [DRT_NRC_WEIGHTS] Adam first moments */
+  float* weights_v;        /* [DRT_NRC_WEIGHTS] Adam second moments */
+  float* weights_grad;     /* [DRT_NRC_WEIGHTS] gradient accumulator */
+  float* grid;             /* [levels][2^log2_table][2] FP32 master features */
+  float* grid_m, *grid_v;  /* same size: Adam moments */
+  float* grid_grad;        /* same size: gradient accumulator */
+  uint16_t* grid_half;     /* same size, FP16: the copy the kernels read; rewritten each frame */
+  float* records;          /* [n_records][16], n_records = n_paths (plain records) or
+                              n_paths (K - 1) (self-training with tail vertex K) */
+  int32_t* valid;          /* [n_records] */
+  int32_t* count;          /* [1] */
+  void* train_workspace;   /* drt_nrc_train_workspace_bytes(n_records) bytes, 16-byte aligned */
+  int64_t train_workspace_bytes;
+  void* self_workspace;    /* self-training: drt_nrc_collect_self_workspace_bytes(n_paths, K) */
+  int64_t self_workspace_bytes;
+  float* loss;             /* [1]: the frame's training loss */
+} drt_nrc_state;
+
+typedef struct {
+  int64_t n_paths;         /* training paths of the frame */
+  int32_t self_training;   /* 0: records of plain paths at the truncation vertex
+                              (drt_nrc_collect); K >= 2: self-training records of paths
+                              closed by the cache at vertex K (drt_nrc_collect_self) */
+  int32_t step;            /* Adam step t >= 1 of this frame */
+  float lr, beta1, beta2, eps;
+} drt_nrc_frame_opts;
+
+/* One training frame of the radiance cache, enqueued on the stream:
+ * records (drt_nrc_collect, or drt_nrc_collect_self with the current
+ * network) -> one fused training pass (drt_nrc_train: relative-L2 loss,
+ * network and hash-grid gradients) -> Adam on the weights and on the grid
+ * (step frame->step; gradients re-zeroed; the FP16 grid rewritten).  opts
+ * carries the training paths' seed, max_depth, rr_depth and flags (spp is
+ * ignored).  All arguments are checked before anything is enqueued. */
+drt_status drt_nrc_train_frame(const drt_scene* scene, const drt_params* params,
+                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                               const drt_nrc_config* cfg, const drt_nrc_frame_opts* frame,
+                               const drt_nrc_state* state, void* hip_stream);
+
 /* Entries of the int32 query scratch of the cached calls for `capacity`
  * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
  * parameter references [capacity][2] | bin histogram [4096]; 0 for

@@ -102,6 +102,19 @@ class drt_nrc_config(ctypes.Structure):
                 ("bbox_lo", _c_f * 3), ("bbox_hi", _c_f * 3)]
 
 
+class drt_nrc_state(ctypes.Structure):
+    _fields_ = [("weights", _vp), ("weights_m", _vp), ("weights_v", _vp), ("weights_grad", _vp),
+                ("grid", _vp), ("grid_m", _vp), ("grid_v", _vp), ("grid_grad", _vp),
+                ("grid_half", _vp), ("records", _vp), ("valid", _vp), ("count", _vp),
+                ("train_workspace", _vp), ("train_workspace_bytes", _c_i64),
+                ("self_workspace", _vp), ("self_workspace_bytes", _c_i64), ("loss", _vp)]
+
+
+class drt_nrc_frame_opts(ctypes.Structure):
+    _fields_ = [("n_paths", _c_i64), ("self_training", _c_i32), ("step", _c_i32), ("lr", _c_f),
+                ("beta1", _c_f), ("beta2", _c_f), ("eps", _c_f)]
+
+
 # Every entry point of include/drt.h with its ctypes signature.
 _SIGS = {
     "drt_last_error": (ctypes.c_char_p, []),
@@ -168,6 +181,10 @@ _SIGS = {
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp,
                                            _vp, _c_i64, _vp, _vp]),
     "drt_nrc_query_ints": (_c_i64, [_c_i64]),
+    "drt_nrc_train_frame": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera), _c_i32,
+                                     ctypes.POINTER(drt_render_opts), ctypes.POINTER(drt_nrc_config),
+                                     ctypes.POINTER(drt_nrc_frame_opts), ctypes.POINTER(drt_nrc_state),
+                                     _vp]),
     "drt_render_adjoint_cached": (_c_i32, [_vp, ctypes.POINTER(drt_params), ctypes.POINTER(drt_camera),
                                            _c_i32, ctypes.POINTER(drt_render_opts),
                                            ctypes.POINTER(drt_nrc_config), _vp, _vp, _vp, _vp, _vp,
@@ -1065,7 +1082,9 @@ class NrcCache:
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
 
     def train_frame(self, scene: Scene, textures, roughness, cams, seed: int, max_depth: int = 6,
-                    rr_depth: int = 3):
+                    rr_depth: int = 3, stream=None):
+        """One training frame (drt_nrc_train_frame: records -> fused training
+        pass -> Adam on the weights and the grid); returns the loss tensor."""
         torch = _torch()
         tail = self.self_training
         m = self.n_paths * (tail - 1 if tail else 1)
@@ -1074,25 +1093,35 @@ class NrcCache:
             self.buf = (torch.empty((m, NRC_RECORD), dtype=torch.float32, device=dev),
                         torch.empty(m, dtype=torch.int32, device=dev),
                         torch.empty(1, dtype=torch.int32, device=dev))
-        if tail:
-            if self.ws_self is None:
-                self.ws_self = torch.empty(int(lib.drt_nrc_collect_self_workspace_bytes(self.n_paths, tail)),
-                                           dtype=torch.uint8, device=dev)
-            rec, valid, count = nrc_collect_self(scene, textures, roughness, cams, self.cfg, self.W,
-                                                 self.grid16, self.n_paths, seed, tail, max_depth,
-                                                 rr_depth, out=self.buf, workspace=self.ws_self)
-        else:
-            rec, valid, count = nrc_collect(scene, textures, roughness, cams, self.cfg, self.n_paths,
-                                            seed, max_depth, rr_depth, out=self.buf)
+        if tail and self.ws_self is None:
+            self.ws_self = torch.empty(int(lib.drt_nrc_collect_self_workspace_bytes(self.n_paths, tail)),
+                                       dtype=torch.uint8, device=dev)
         if self.ws is None:
             self.ws = nrc_train_workspace(m, dev)
-        nrc_train(self.cfg, self.W, self.grid16, rec, valid, count, self.dW, self.dG, self.loss,
-                  workspace=self.ws)
+        st = drt_nrc_state()
+        for name, t in (("weights", self.W), ("weights_m", self.mW), ("weights_v", self.vW),
+                        ("weights_grad", self.dW), ("grid", self.grid), ("grid_m", self.mG),
+                        ("grid_v", self.vG), ("grid_grad", self.dG), ("grid_half", self.grid16),
+                        ("records", self.buf[0]), ("valid", self.buf[1]), ("count", self.buf[2]),
+                        ("train_workspace", self.ws), ("loss", self.loss)):
+            setattr(st, name, _dp(t, name))
+        st.train_workspace_bytes = _nbytes(self.ws)
+        if tail:
+            st.self_workspace = _dp(self.ws_self, "self workspace")
+            st.self_workspace_bytes = _nbytes(self.ws_self)
+        fo = drt_nrc_frame_opts()
+        fo.n_paths = self.n_paths
+        fo.self_training = tail
+        fo.step = self.step + 1
+        fo.lr, fo.beta1, fo.beta2, fo.eps = self.lr, 0.9, 0.99, 1e-8
+        ca = _cams(cams)
+        p = _params(scene, textures, roughness)
+        o = _opts(1, max_depth, rr_depth, seed, 0, None)
+        c = nrc_config(self.cfg)
+        _check(lib.drt_nrc_train_frame(scene.handle, ctypes.byref(p), ca, len(cams), ctypes.byref(o),
+                                       ctypes.byref(c), ctypes.byref(fo), ctypes.byref(st),
+                                       _stream(stream)), "drt_nrc_train_frame")
         self.step += 1
-        adam_step(self.W, self.dW, self.mW, self.vW, self.step, lr=self.lr, beta1=0.9, beta2=0.99,
-                  eps=1e-8, zero_grad=True)
-        adam_step(self.grid, self.dG, self.mG, self.vG, self.step, lr=self.lr, beta1=0.9,
-                  beta2=0.99, eps=1e-8, zero_grad=True, half_out=self.grid16)
         return self.loss
 
     def adjoint(self, scene: Scene, textures, roughness, cams, adj_image, spp: int, seed: int,

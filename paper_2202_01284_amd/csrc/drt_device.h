@@ -153,10 +153,13 @@ DEV float diff_of_products(float a, float b, float c, float d) {
 }
 
 // Watertight ray/triangle test (no culling), t in (tmin, tmax] -- the caller
-// decides about t == tmax.  An edge function that comes out exactly zero is
-// evaluated again without the rounding of its two products (the method's
-// fallback for rays through an edge or a vertex), in float32 by Kahan's
-// difference of products rather than in double precision.
+// decides about t == tmax.  Each edge function is Kahan's difference of
+// products, whose sign is exact: two triangles sharing an edge evaluate the
+// same two products in swapped roles, so they always agree on which side of
+// the edge the ray passes (no cracks from the rounding of a fused
+// multiply-add), and a value is zero only when the exact one is -- which is
+// what the method's higher-precision fallback for zero edge functions
+// secures, so none is needed.
 DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float& t_out, float& b1,
                   float& b2) {
   f3 A = mk(T.p0x, T.p0y, T.p0z) - r.o;
@@ -166,25 +169,21 @@ DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float&
   float Ax = comp(A, r.kx) - r.sx * Akz, Ay = comp(A, r.ky) - r.sy * Akz;
   float Bx = comp(B, r.kx) - r.sx * Bkz, By = comp(B, r.ky) - r.sy * Bkz;
   float Cx = comp(C, r.kx) - r.sx * Ckz, Cy = comp(C, r.ky) - r.sy * Ckz;
-  float U = Cx * By - Cy * Bx;
-  float V = Ax * Cy - Ay * Cx;
-  float W = Bx * Ay - By * Ax;
-  if (U == 0.f || V == 0.f || W == 0.f) {
-    U = diff_of_products(Cx, By, Cy, Bx);
-    V = diff_of_products(Ax, Cy, Ay, Cx);
-    W = diff_of_products(Bx, Ay, By, Ax);
-  }
-  if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return false;
-  float det = U + V + W;
-  if (det == 0.f) return false;
-  float T_ = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
-  float inv = 1.0f / det;
-  float t = T_ * inv;
-  if (!(t > tmin && t <= tmax)) return false;
+  const float U = diff_of_products(Cx, By, Cy, Bx);
+  const float V = diff_of_products(Ax, Cy, Ay, Cx);
+  const float W = diff_of_products(Bx, Ay, By, Ax);
+  // the rest is computed whatever the edge functions say and the decision
+  // taken at the end (fewer divergent branches in the triangle loop); with
+  // det = 0 the quotients are not finite and the result is masked
+  const bool mixed = (U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f);
+  const float det = U + V + W;
+  const float T_ = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
+  const float inv = 1.0f / det;
+  const float t = T_ * inv;
   t_out = t;
   b1 = V * inv;
   b2 = W * inv;
-  return true;
+  return !mixed && det != 0.f && t > tmin && t <= tmax;
 }
 
 DEV DTri load_tri(const DScene& s, int i) {
@@ -243,34 +242,40 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       h2 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2) & (cn.z >= 0);
       h3 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3) & (cn.w >= 0);
     }
-    // leaf children: test their triangles now (one loop over the ranges)
+    // leaf children: test their triangles now (one loop over the ranges;
+    // triangle j of the loop is range k's first + j - its start, the offset
+    // picked by selects rather than branches)
     const int e0 = (h0 && cn.x > 0) ? cn.x : 0;
     const int e1 = e0 + ((h1 && cn.y > 0) ? cn.y : 0);
     const int e2 = e1 + ((h2 && cn.z > 0) ? cn.z : 0);
     const int e3 = e2 + ((h3 && cn.w > 0) ? cn.w : 0);
+    const int o1 = ch.y - e0, o2 = ch.z - e1, o3 = ch.w - e2;
     for (int j = 0; j < e3; ++j) {
-      const int i = j < e0 ? ch.x + j : (j < e1 ? ch.y + (j - e0) : (j < e2 ? ch.z + (j - e1) : ch.w + (j - e2)));
-      DTri T = load_tri(s, i);
+      int off = j < e2 ? o2 : o3;
+      off = j < e1 ? o1 : off;
+      off = j < e0 ? ch.x : off;
+      const int i = j + off;
+      const DTri T = load_tri(s, i);
       cnt.tris++;
-      if (any && (T.flags & 1)) continue;
       float t, b1, b2;
-      if (!tri_test(r, T, tmin, tbest, t, b1, b2)) continue;
+      bool ok = tri_test(r, T, tmin, tbest, t, b1, b2);
       if (any) {
-        if (t < tmax) {
+        // shadow rays pass through null surfaces; the flag is tested after
+        // the whole record has been loaded (no second memory round trip)
+        if (ok && !(T.flags & 1) && t < tmax) {
           found = true;
           break;
         }
         continue;
       }
       // closest: strictly nearer, or an exact tie with a lower original id
-      if (t < tbest || (h.tri >= 0 && T.prim < h.prim)) {
-        tbest = t;
-        h.t = t;
-        h.b1 = b1;
-        h.b2 = b2;
-        h.tri = i;
-        h.prim = T.prim;
-      }
+      ok = ok && (t < tbest || (h.tri >= 0 && T.prim < h.prim));
+      tbest = ok ? t : tbest;
+      h.t = ok ? t : h.t;
+      h.b1 = ok ? b1 : h.b1;
+      h.b2 = ok ? b2 : h.b2;
+      h.tri = ok ? i : h.tri;
+      h.prim = ok ? T.prim : h.prim;
     }
     if (found) break;
     if (any) {

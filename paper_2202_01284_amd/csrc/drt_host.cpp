@@ -547,6 +547,8 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   if (o->rr_depth < 1) return fail(DRT_EINVAL, "rr_depth must be >= 1");
   const int W = cams[0].width, H = cams[0].height;
   if (W <= 0 || H <= 0) return fail(DRT_EINVAL, "camera size must be positive");
+  if (tiles_of(H) > kMaxTileRows)
+    return fail(DRT_EUNSUPPORTED, "image height above %d pixels", kMaxTileRows * kTile);
   int64_t samples = n_cams;
   for (const int64_t f : {(int64_t)W, (int64_t)H, (int64_t)o->spp}) {
     if (!prod_le(samples, f, kMaxSamples)) return fail(DRT_EUNSUPPORTED, "sample count too large");
@@ -765,7 +767,7 @@ static int64_t record_slot_bytes(int32_t n_cams, int32_t width, int32_t height, 
       max_depth > kMaxDepth)
     return 0;
   // < 2^5 x 2^28 x 2^28 tiles; their records must stay far from int64's end
-  const int64_t groups = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+  const int64_t groups = (int64_t)n_cams * tiles_of(width) * tiles_of(height);
   const int64_t per_group = (int64_t)max_depth * kBlock * (int64_t)sizeof(int4);
   if (!prod_le(groups, per_group, (int64_t)1 << 60)) return 0;
   return groups * per_group;
@@ -781,7 +783,7 @@ int64_t drt_render_adjoint_hit_bytes(int32_t n_cams, int32_t width, int32_t heig
   if (spp < 1) return 0;
   const int64_t per_tile = record_slot_bytes(n_cams, width, height, max_depth);  // 0 when too large
   if (per_tile <= 0) return 0;
-  const int64_t tiles = (int64_t)n_cams * ((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+  const int64_t tiles = (int64_t)n_cams * tiles_of(width) * tiles_of(height);
   const int64_t units = tiles * adjoint_split(spp);
   const int resident = adjoint_resident_groups();
   const int64_t slots = resident > 0 && resident < units ? resident : units;
@@ -801,8 +803,8 @@ drt_status drt_render_adjoint_hits(const drt_scene* scene, const drt_params* par
   if (!adj_image || !grads || !hit_records)
     return fail(DRT_EINVAL, "adj_image, grads and hit_records are required");
   // the persistent workgroups count work units in 32 bits
-  const int64_t tiles = (int64_t)n_cams * ((cams[0].width + kTile - 1) / kTile) *
-                        ((cams[0].height + kTile - 1) / kTile);
+  const int64_t tiles = (int64_t)n_cams * tiles_of(cams[0].width) *
+                        tiles_of(cams[0].height);
   if (tiles * adjoint_split(opts->spp) > ((int64_t)1 << 31))
     return fail(DRT_EUNSUPPORTED, "image too large for the persistent replay");
   const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
@@ -831,8 +833,8 @@ drt_status drt_render_adjoint_noalloc(const drt_scene* scene, const drt_params* 
   drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
   if (st != DRT_OK) return st;
   if (!adj_image || !grads) return fail(DRT_EINVAL, "adj_image and grads are required");
-  const int64_t tiles = (int64_t)n_cams * ((cams[0].width + kTile - 1) / kTile) *
-                        ((cams[0].height + kTile - 1) / kTile);
+  const int64_t tiles = (int64_t)n_cams * tiles_of(cams[0].width) *
+                        tiles_of(cams[0].height);
   if (tiles * adjoint_split(opts->spp) > ((int64_t)1 << 31))
     return fail(DRT_EUNSUPPORTED, "image too large for the persistent replay");
   const int64_t need = drt_render_adjoint_hit_bytes(n_cams, cams[0].width, cams[0].height,
@@ -1217,6 +1219,73 @@ drt_status drt_nrc_train(const drt_nrc_config* cfg, const float* weights, const 
   if (n == 0) return ok();
   e = launch_nrc_train(net, weights, records, valid, count, n, workspace, dW, dgrid, loss, stream);
   if (e != hipSuccess) return hip_fail(e, "nrc_train launch");
+  return ok();
+}
+
+drt_status drt_nrc_train_frame(const drt_scene* scene, const drt_params* params,
+                               const drt_camera* cams, int32_t n_cams, const drt_render_opts* opts,
+                               const drt_nrc_config* cfg, const drt_nrc_frame_opts* frame,
+                               const drt_nrc_state* S, void* hip_stream) {
+  // every check first: nothing is enqueued on an argument error
+  DParams dp;
+  DCams dc;
+  DRender dr;
+  drt_status st = check_params(scene, params, cams, n_cams, opts, &dp, &dc, &dr);
+  if (st != DRT_OK) return st;
+  if (!frame || !S) return fail(DRT_EINVAL, "frame options and cache state are required");
+  DNrcNet net;
+  st = nrc_net(cfg, S->grid_half, &net);
+  if (st != DRT_OK) return st;
+  const int K = frame->self_training;
+  if (K == 1 || K < 0 || K > 32) return fail(DRT_EINVAL, "self_training must be 0 or in [2, 32]");
+  const int64_t n = frame->n_paths;
+  if (n < 1 || n > INT32_MAX) return fail(DRT_EINVAL, "n_paths must be in [1, 2^31)");
+  const int64_t n_rec = K ? n * (K - 1) : n;
+  if (n_rec > ((int64_t)1 << 31)) return fail(DRT_EINVAL, "too many records");
+  if (frame->step < 1) return fail(DRT_EINVAL, "Adam step must be >= 1");
+  if (!(frame->lr >= 0) || !(frame->beta1 >= 0 && frame->beta1 < 1) ||
+      !(frame->beta2 >= 0 && frame->beta2 < 1) || !(frame->eps > 0))
+    return fail(DRT_EINVAL, "invalid Adam hyper-parameters");
+  if (!S->weights || !S->weights_m || !S->weights_v || !S->weights_grad || !S->grid || !S->grid_m ||
+      !S->grid_v || !S->grid_grad || !S->grid_half || !S->records || !S->valid || !S->count ||
+      !S->loss)
+    return fail(DRT_EINVAL, "cache state has a NULL buffer");
+  if (!S->train_workspace || S->train_workspace_bytes < nrc_train_workspace_bytes(n_rec) ||
+      ((uintptr_t)S->train_workspace & 15) != 0)
+    return fail(DRT_EINVAL, "train workspace missing, misaligned or smaller than "
+                "drt_nrc_train_workspace_bytes(%lld)", (long long)n_rec);
+  if (K && (!S->self_workspace || S->self_workspace_bytes < self_ws(n, K).total))
+    return fail(DRT_EINVAL, "self-training workspace smaller than drt_nrc_collect_self_workspace_bytes");
+  const int64_t n_grid = (int64_t)DRT_NRC_LEVELS << cfg->log2_table << 1;
+  drt_render_opts o = *opts;
+  o.spp = 1;
+  if (K)
+    st = drt_nrc_collect_self(scene, params, cams, n_cams, &o, cfg, S->weights, S->grid_half, K, n,
+                              S->records, S->valid, S->count, S->self_workspace,
+                              S->self_workspace_bytes, hip_stream);
+  else
+    st = drt_nrc_collect(scene, params, cams, n_cams, &o, cfg, n, S->records, S->valid, S->count,
+                         hip_stream);
+  if (st != DRT_OK) return st;
+  st = drt_nrc_train(cfg, S->weights, S->grid_half, S->records, S->valid, S->count, n_rec,
+                     S->train_workspace, S->train_workspace_bytes, S->weights_grad, S->grid_grad,
+                     S->loss, hip_stream);
+  if (st != DRT_OK) return st;
+  drt_adam_opts a = {};
+  a.lr = frame->lr;
+  a.beta1 = frame->beta1;
+  a.beta2 = frame->beta2;
+  a.eps = frame->eps;
+  a.step = frame->step;
+  a.lo = -INFINITY;
+  a.hi = INFINITY;
+  a.zero_grad = 1;
+  st = drt_adam_step(S->weights, S->weights_grad, S->weights_m, S->weights_v, DRT_NRC_WEIGHTS, &a,
+                     hip_stream);
+  if (st != DRT_OK) return st;
+  a.half_out = S->grid_half;
+  st = drt_adam_step(S->grid, S->grid_grad, S->grid_m, S->grid_v, n_grid, &a, hip_stream);
+  if (st != DRT_OK) return st;
   return ok();
 }
 

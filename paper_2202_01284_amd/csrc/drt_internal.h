@@ -21,6 +21,13 @@ constexpr int kStackDepth = 36;
 constexpr int kMaxInteriorDepth = 24;
 constexpr int kBlock = 64;             // threads per workgroup of the megakernels (one wave)
 constexpr int kTile = 8;               // workgroup = 8 x 8 pixel tile
+// Tiles covering n pixels (n up to INT32_MAX: computed in 64 bits).
+__host__ __device__ inline int32_t tiles_of(int32_t n) {
+  return (int32_t)(((int64_t)n + kTile - 1) / kTile);
+}
+// The launch grid's y extent holds the tile rows: images up to 65535 tiles
+// (524,280 pixels) high.
+constexpr int32_t kMaxTileRows = 65535;
 constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
 // The replayed adjoint splits each tile's samples over this many workgroups
 // (contiguous sample ranges): four times more, shorter waves leave less of

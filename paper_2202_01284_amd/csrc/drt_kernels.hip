@@ -112,6 +112,12 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   bool recorded = false;
   f3 beta_at = mk(0, 0, 0), L_at = mk(0, 0, 0);
   uint32_t self_mask = 0;  // records written by this path (MODE_TRAIN_SELF)
+  // The lane's roughness gradient, summed in a register while its slot stays
+  // the same and handed to the workgroup's accumulator when the slot changes
+  // and after the last sample: one accumulator update per lane and work unit
+  // instead of one per vertex.
+  int racc_slot = -1;
+  float racc = 0.f;
 
   auto start = [&]() {
     uint64_t g = g_base + (uint64_t)sidx;
@@ -451,7 +457,14 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     if (RB) {
       // one scatter per vertex for its next-event and continuation terms
       if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
-      if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
+      if (vrslot >= 0 && grough != 0.f) {
+        if (vrslot != racc_slot) {
+          if (racc_slot >= 0) scatter_rough(sink, racc_slot, racc, cnt);
+          racc_slot = vrslot;
+          racc = 0.f;
+        }
+        racc += grough;
+      }
     }
     if constexpr (HWRITE)
       *rec = make_int4(rec_tri, __float_as_int(rec_b1), __float_as_int(rec_b2), rec_vis ? 1 : 0);
@@ -510,6 +523,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     }
     if (++sidx == n_samples) break;
   }
+  if (ADJ && racc_slot >= 0) scatter_rough(sink, racc_slot, racc, cnt);
   out = acc;
 }
 
@@ -602,7 +616,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   constexpr bool PERSIST = HC && MODE == MODE_ADJOINT;
   __shared__ uint32_t unit_s;
   const int W = C.width, H = C.height;
-  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  const int tiles_x = tiles_of(W), tiles_y = tiles_of(H);
   const int split = PERSIST ? adjoint_split(R.spp) : (int)gridDim.z / C.n;
   const int64_t units = PERSIST ? (int64_t)tiles_x * tiles_y * C.n * split : 1;  // < 2^31 (host)
   Counters cnt = {};
@@ -935,7 +949,7 @@ hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams&
     hipError_t e = launch_zero(image, 3 * (int64_t)c.n * c.width * c.height, st);
     if (e != hipSuccess) return e;
   }
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n * split);
+  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n * split);
   DNrcIO none = {};
   if (r.stats)
     hipLaunchKernelGGL((k_render_forward<true, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p, c,
@@ -949,7 +963,7 @@ hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams&
 hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& c,
                                 const DRender& r, float* image, const DNrcIO& io,
                                 hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
   if (io.lsamp && r.hits)
     hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES, true>), grid, dim3(kBlock), 0,
                        st, s, p, c, r, image, io);
@@ -990,7 +1004,7 @@ hipError_t launch_nrc_self_targets(const DNrcIO& io, int64_t n_paths, hipStream_
 hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, const float* adj, const DGrads& g,
                                  hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile,
+  dim3 grid(tiles_of(c.width), tiles_of(c.height),
             c.n * adjoint_split(r.spp));
   DNrcIO none = {};
   if (r.hits) {
@@ -1040,7 +1054,7 @@ int adjoint_resident_groups() {
 hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const DCams& c,
                                         const DRender& r, const float* adj, const DGrads& g,
                                         const DNrcIO& io, hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
   if (r.hits && r.stats)
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED, true>), grid, dim3(kBlock), 0,
                        st, s, p, c, r, adj, g, io);
@@ -1058,7 +1072,7 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
 
 hipError_t launch_render_jvp(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                              const DGrads& t, float* image, hipStream_t st) {
-  dim3 grid((c.width + kTile - 1) / kTile, (c.height + kTile - 1) / kTile, c.n);
+  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
   hipLaunchKernelGGL(k_render_jvp, grid, dim3(kBlock), 0, st, s, p, c, r, t, image);
   return hipGetLastError();
 }

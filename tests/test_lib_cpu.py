@@ -287,6 +287,14 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_nrc_collect_self_workspace_bytes(-1, 5) == 0
     assert drt.lib.drt_nrc_collect_self(h, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(c),
                                         fake, fake, 5, 1000, fake, fake, fake, fake, wsb, None) == -4
+    # the cache's training frame: scene state, then the frame and state structs
+    fo = drt.drt_nrc_frame_opts(n_paths=1000, self_training=0, step=1, lr=1e-2, beta1=0.9, beta2=0.99,
+                                eps=1e-8)
+    stt = drt.drt_nrc_state()
+    assert drt.lib.drt_nrc_train_frame(h, ctypes.byref(p), cams, 1, ctypes.byref(o), ctypes.byref(c),
+                                       ctypes.byref(fo), ctypes.byref(stt), None) == -4
+    assert drt.lib.drt_nrc_train_frame(None, ctypes.byref(p), cams, 1, ctypes.byref(o),
+                                       ctypes.byref(c), ctypes.byref(fo), ctypes.byref(stt), None) == -1
     # the entry point that allocates nothing checks the scene before anything else
     assert drt.lib.drt_render_adjoint_noalloc(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
                                               ctypes.byref(g), None) == -4
