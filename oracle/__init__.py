@@ -420,6 +420,22 @@ def mlp_backward(x, W, dy, emu=False):
     return dW, dx
 
 
+def mlp_term_magnitudes(x, W, dy, emu=False):
+    """(aW, adx, ay): for every weight gradient, input gradient and output
+    entry, the sum of the magnitudes of the terms it is summed from (the
+    scale of a floating-point sum's rounding error), with the activations
+    and backpropagated signals of mlp_backward.  For tolerances only."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 80)
+    W = np.ascontiguousarray(W, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64).reshape(-1, 3)
+    aW = np.zeros_like(W)
+    adx = np.zeros_like(x)
+    ay = np.zeros((x.shape[0], 3))
+    lib().oracle_mlp_term_magnitudes(_c_i64(x.shape[0]), _p(x), _p(W), _p(dy),
+                                     _c_int(1 if emu else 0), _p(aW), _p(adx), _p(ay))
+    return aW, adx, ay
+
+
 def rel_l2(y, t):
     y = np.ascontiguousarray(y, np.float64)
     t = np.ascontiguousarray(t, np.float64)

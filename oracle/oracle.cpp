@@ -1456,6 +1456,57 @@ static void mlp_backward(const double* W, const double* x, const double dy[3], b
   }
 }
 
+// Magnitude sums of the terms of every network output and gradient entry
+// for one sample: ay[r] = sum_c |w_rc| |a_c| over the output layer's inputs,
+// aW += |g_r| |in_c| per weight, adx[c] = sum_r |w_rc| |g_r| -- the scale of a
+// floating-point sum's rounding error (sum over its terms of their
+// magnitudes), with the forward activations and backpropagated signals of
+// mlp_backward.  Test infrastructure: tolerance scales, not estimator work.
+static void mlp_term_magnitudes(const double* W, const double* x, const double dy[3], bool emu,
+                                double* aW, double* adx, double ay[3]) {
+  std::vector<double> acts;
+  double y[3];
+  mlp_forward(W, x, emu, &acts, y);
+  auto act = [&](int l) { return acts.data() + (l == 0 ? 0 : kIn + (l - 1) * kHid); };
+  auto wt = [&](const double* w, int i) { return std::fabs(emu ? bf16_round(w[i]) : w[i]); };
+  {
+    const double* w = W + Mlp::off(4);
+    const double* in = act(4);
+    for (int r = 0; r < kOut; ++r) {
+      double acc = 0;
+      for (int c = 0; c < kHid; ++c) acc += wt(w, r * kHid + c) * std::fabs(in[c]);
+      ay[r] = acc;
+    }
+  }
+  std::vector<double> g(dy, dy + kOut);
+  if (emu) for (auto& v : g) v = bf16_round(v);
+  for (int l = 4; l >= 0; --l) {
+    int R = Mlp::rows(l), C = Mlp::cols(l);
+    const double* w = W + Mlp::off(l);
+    const double* in = act(l);
+    for (int r = 0; r < R; ++r)
+      for (int c = 0; c < C; ++c) aW[Mlp::off(l) + r * C + c] += std::fabs(g[r] * in[c]);
+    std::vector<double> gi(C, 0.0);
+    for (int c = 0; c < C; ++c) {
+      double acc = 0, mag = 0;
+      for (int r = 0; r < R; ++r) {
+        const double wv = emu ? bf16_round(w[r * C + c]) : w[r * C + c];
+        acc += wv * g[r];
+        mag += std::fabs(wv * g[r]);
+      }
+      gi[c] = acc;
+      if (l == 0) adx[c] = mag;
+    }
+    if (l > 0) {
+      for (int c = 0; c < C; ++c) {
+        gi[c] = in[c] > 0 ? gi[c] : 0.0;
+        if (emu) gi[c] = bf16_round(gi[c]);
+      }
+      g = gi;
+    }
+  }
+}
+
 // Relative L2 (Mueller et al., neural radiance caching, 2021): mean over
 // samples and channels of (y - t)^2 / (sg(y)^2 + 0.01).
 static double rel_l2(int64_t n, const double* y, const double* t, double* dy) {
@@ -1973,6 +2024,14 @@ void oracle_mlp_forward(int64_t n, const double* x, const double* W, int emu, in
 void oracle_mlp_backward(int64_t n, const double* x, const double* W, const double* dy, int emu,
                          double* dW, double* dx) {
   for (int64_t i = 0; i < n; ++i) mlp_backward(W, x + kIn * i, dy + 3 * i, emu != 0, dW, dx + kIn * i);
+}
+
+// Term-magnitude sums (mlp_term_magnitudes) for n samples: aW accumulated
+// over the samples, adx [n][80], ay [n][3].
+void oracle_mlp_term_magnitudes(int64_t n, const double* x, const double* W, const double* dy,
+                                int emu, double* aW, double* adx, double* ay) {
+  for (int64_t i = 0; i < n; ++i)
+    mlp_term_magnitudes(W, x + kIn * i, dy + 3 * i, emu != 0, aW, adx + kIn * i, ay + 3 * i);
 }
 
 double oracle_rel_l2(int64_t n, const double* y, const double* t, double* dy) {

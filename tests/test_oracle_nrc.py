@@ -156,6 +156,40 @@ def test_mlp_gradients_against_finite_differences():
         assert math.isclose(dx[i, j], (f(W, xp) - f(W, xm)) / (2 * h), rel_tol=1e-5, abs_tol=1e-8)
 
 
+def test_mlp_term_magnitudes():
+    """The tolerance scales of the network parity tests: for one sample a
+    weight gradient is a single term, so its magnitude sum is |dW|; over
+    samples the sums add; with non-negative weights, inputs and output
+    gradients every term is non-negative, so the sums equal y, dW and dx;
+    otherwise they bound them."""
+    rng = np.random.default_rng(8)
+    n_w = oracle.mlp_num_weights()
+    W = rng.normal(size=n_w) * 0.2
+    x = rng.normal(size=(2, 80))
+    dy = rng.normal(size=(2, 3))
+    for emu in (False, True):
+        single = []
+        for i in range(2):
+            dWi, _ = oracle.mlp_backward(x[i:i + 1], W, dy[i:i + 1], emu=emu)
+            aWi, _, _ = oracle.mlp_term_magnitudes(x[i:i + 1], W, dy[i:i + 1], emu=emu)
+            np.testing.assert_array_equal(aWi, np.abs(dWi))
+            single.append(aWi)
+        dW, dx = oracle.mlp_backward(x, W, dy, emu=emu)
+        aW, adx, ay = oracle.mlp_term_magnitudes(x, W, dy, emu=emu)
+        np.testing.assert_allclose(aW, single[0] + single[1], rtol=1e-15, atol=0)
+        assert np.all(aW >= np.abs(dW) * (1 - 1e-15))
+        assert np.all(adx >= np.abs(dx) * (1 - 1e-12))
+        y = oracle.mlp_forward(x, W, emu=emu)
+        assert np.all(ay >= np.abs(y) * (1 - 1e-12))
+        assert (adx > np.abs(dx) * 1.01).any() and (ay > np.abs(y) * 1.01).any()
+    Wp, xp, dyp = np.abs(W), np.abs(x), np.abs(dy)
+    dW, dx = oracle.mlp_backward(xp, Wp, dyp)
+    aW, adx, ay = oracle.mlp_term_magnitudes(xp, Wp, dyp)
+    np.testing.assert_allclose(aW, dW, rtol=1e-13)
+    np.testing.assert_allclose(adx, dx, rtol=1e-13)
+    np.testing.assert_allclose(ay, oracle.mlp_forward(xp, Wp), rtol=1e-13)
+
+
 def test_mlp_bf16_mode_close_to_fp64():
     rng = np.random.default_rng(7)
     W = rng.normal(size=oracle.mlp_num_weights()) * 0.15
