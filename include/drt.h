@@ -182,7 +182,7 @@ typedef struct {
   int32_t rr_depth;   /* Russian roulette after sampling at vertex k >= rr_depth */
   uint32_t flags;     /* DRT_FLAG_* */
   uint64_t seed;      /* Philox key */
-  uint64_t* stats;    /* device uint64[8] accumulators, or NULL (see drt_stat_*) */
+  uint64_t* stats;    /* device uint64[DRT_STAT_COUNT] accumulators, or NULL (see DRT_STAT_*) */
 } drt_render_opts;
 
 /* Indices into drt_render_opts.stats. */
@@ -196,7 +196,21 @@ enum {
   DRT_STAT_LREM_MAX = 6,  /* adjoint: max over samples of |L_rem| / |L| at the path's end
                              (max norms over channels; |L_rem| itself where L = 0), as
                              float bits: the replay's relative residual */
-  DRT_STAT_SAMPLES = 7    /* samples traced */
+  DRT_STAT_SAMPLES = 7,   /* samples traced */
+  DRT_STAT_TEX_LANES = 8, /* adjoint: lanes that scatter-added a texel gradient */
+  DRT_STAT_TEX_KEYS = 9,  /* adjoint: distinct texels among the lanes of each wave-wide
+                             texel scatter, summed: TEX_LANES / TEX_KEYS is the mean
+                             number of lanes per distinct texel (measurement only;
+                             counting them costs a ballot loop per scatter) */
+  /* SIMD utilisation by phase, counted by the stats kernels of
+     drt_render_forward and drt_render_adjoint (0 elsewhere): each event
+     once per wave, to set beside the per-lane count of the same event */
+  DRT_STAT_WAVE_NODES = 10,  /* node-loop iterations of waves (per lane: NODES) */
+  DRT_STAT_WAVE_TRIS = 11,   /* triangle-loop iterations of waves (per lane: TRIS) */
+  DRT_STAT_LANE_STEPS = 12,  /* vertex steps of live paths, per lane */
+  DRT_STAT_WAVE_STEPS = 13,  /* vertex steps of waves */
+  DRT_STAT_WAVE_SHADE = 14,  /* shading blocks entered by waves (per lane: VERTICES) */
+  DRT_STAT_COUNT = 15
 };
 
 /* Primal rendering (Fig. "prb-structure", megakernel #1): for each pixel

@@ -27,7 +27,9 @@ MAX_TEXTURES = 8
 MAX_CAMERAS = 32
 FLAG_NO_NEE = 1
 FLAG_CACHE_INPUT_GRAD = 2   # cached adjoint: also through the cache's albedo/roughness inputs
-STAT_NAMES = ["rays", "shadow_rays", "nodes", "tris", "vertices", "scatter", "lrem_max", "samples"]
+STAT_NAMES = ["rays", "shadow_rays", "nodes", "tris", "vertices", "scatter", "lrem_max", "samples",
+              "tex_lanes", "tex_keys", "wave_nodes", "wave_tris", "lane_steps", "wave_steps",
+              "wave_shade"]
 
 _c_i32 = ctypes.c_int32
 _c_u32 = ctypes.c_uint32
@@ -750,7 +752,7 @@ def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9
 
 def new_stats():
     torch = _torch()
-    return torch.zeros(8, dtype=torch.int64, device="cuda")
+    return torch.zeros(len(STAT_NAMES), dtype=torch.int64, device="cuda")
 
 
 def read_stats(stats) -> dict:

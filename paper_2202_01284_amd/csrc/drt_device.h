@@ -79,7 +79,22 @@ DEV uint32_t pick(uint32_t r, uint32_t n) { return __umulhi(r, n); }
 struct Counters {
   uint32_t rays, shadow, nodes, tris, verts, scatter, samples;
   float lrem_max;
+  // texel scatter: lanes that scattered, and distinct texels among the
+  // lanes of each wave-wide scatter (their ratio bounds what a wave-level
+  // merge of equal keys could save)
+  uint32_t tex_lanes, tex_keys;
+  // SIMD utilisation by phase (stats kernels only): iterations of the
+  // wave's node loop, triangle loop, vertex steps and shading blocks, each
+  // counted once per wave, beside the per-lane counts (nodes, tris,
+  // lane_steps, verts)
+  uint32_t wave_nodes, wave_tris, wave_steps, lane_steps, wave_shade;
 };
+
+// true on one active lane of the wave (the lowest): counts an event once
+// per wave
+DEV bool first_active_lane() {
+  return __lane_id() == __ffsll((unsigned long long)__ballot(1)) - 1;
+}
 
 // ---------------------------------------------------------------------------
 // BVH traversal.  The per-lane stack lives in LDS at stk[i * kBlock], so the
@@ -203,18 +218,33 @@ DEV DTri load_tri(const DScene& s, int i) {
 // together whatever ray each carries.
 // any = false: closest hit in (tmin, tmax), ties to the lowest original id.
 // any = true: true iff a non-null triangle is hit in (tmin, tmax).
+// compare-exchange by key, written as selects (no divergent branch)
 DEV void cswap(float& ka, int& va, float& kb, int& vb) {
-  if (kb < ka) {
-    float k = ka; ka = kb; kb = k;
-    int v = va; va = vb; vb = v;
-  }
+  const bool sw = kb < ka;
+  const float k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+  const int v0 = sw ? vb : va, v1 = sw ? va : vb;
+  ka = k0;
+  kb = k1;
+  va = v0;
+  vb = v1;
 }
 
 // Closest (any = false) or any hit in (tmin, tmax] over the four-wide BVH.
-// Per node: four slab tests; the triangles of every hit leaf child in one
-// loop; for a closest hit, hit interior children sorted near to far, the
-// nearest visited next and the others pushed far first (an any-hit query
-// takes them in slot order).
+// Per node: four slab tests; for a closest hit, hit interior children
+// sorted near to far, the nearest visited next and the others pushed far
+// first (an any-hit query takes them in slot order); the triangles of the
+// node's hit leaf children form the lane's leaf batch, tested before its
+// next node.
+//
+// Leaf batches are postponed across the wave: a lane that holds one stops
+// visiting nodes until every lane of the wave holds one or has finished,
+// and then all of them test their batches in one loop.  Testing a batch at
+// once after its node (the wave looping over the largest batch while the
+// lanes without one idle) kept only a fifth of the lanes busy in the
+// triangle loop.  Each lane still does exactly what it did before, in the
+// same order (node, its batch, the next node) -- only the interleaving of
+// lanes changes -- so the nodes visited and the hit found are the same.
+template <bool ST = false>
 DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool any, Hit& h,
                   int* stk, Counters& cnt) {
   float tbest = tmax;
@@ -222,41 +252,102 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
   h.prim = 0x7fffffff;
   bool found = false;
   int node = 0, sp = 0;
+  bool live = true;  // the lane has a node to visit
+  // pending leaf batch: triangle j < e3 of the batch is j + the offset of
+  // its range (range k covers [e_{k-1}, e_k); offsets f0..f3)
+  int e0 = 0, e1 = 0, e2 = 0, e3 = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
   for (;;) {
-    const float4* np = reinterpret_cast<const float4*>(s.nodes + node);
-    const int4 ch = reinterpret_cast<const int4*>(np)[6], cn = reinterpret_cast<const int4*>(np)[7];
-    cnt.nodes++;
-    float t0, t1, t2, t3;
-    bool h0, h1, h2, h3;
-    // The slab tests run whatever the counts say and are masked afterwards:
-    // a short-circuit on the count would put the box loads behind the count
-    // load and cost every node a second memory round trip.  Empty slots hold
-    // a zero box, so the test on them is harmless.
-    {  // children 0 and 1: three float4 (fewer live registers than all four boxes)
-      const float4 a = np[0], b = np[1], c = np[2];
-      h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0) & (cn.x >= 0);
-      h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1) & (cn.y >= 0);
+    // node phase: visit nodes until this lane holds a leaf batch or has none left
+    while (live && e3 == 0) {
+      const float4* np = reinterpret_cast<const float4*>(s.nodes + node);
+      const int4 ch = reinterpret_cast<const int4*>(np)[6], cn = reinterpret_cast<const int4*>(np)[7];
+      cnt.nodes++;
+      if constexpr (ST) cnt.wave_nodes += first_active_lane();
+      float t0, t1, t2, t3;
+      bool h0, h1, h2, h3;
+      // The slab tests run whatever the counts say and are masked afterwards:
+      // a short-circuit on the count would put the box loads behind the count
+      // load and cost every node a second memory round trip.  Empty slots hold
+      // a zero box, so the test on them is harmless.
+      {  // children 0 and 1: three float4 (fewer live registers than all four boxes)
+        const float4 a = np[0], b = np[1], c = np[2];
+        h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0) & (cn.x >= 0);
+        h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1) & (cn.y >= 0);
+      }
+      {  // children 2 and 3
+        const float4 a = np[3], b = np[4], c = np[5];
+        h2 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2) & (cn.z >= 0);
+        h3 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3) & (cn.w >= 0);
+      }
+      // the batch: the hit leaf children's ranges, offsets picked by selects
+      e0 = (h0 && cn.x > 0) ? cn.x : 0;
+      e1 = e0 + ((h1 && cn.y > 0) ? cn.y : 0);
+      e2 = e1 + ((h2 && cn.z > 0) ? cn.z : 0);
+      e3 = e2 + ((h3 && cn.w > 0) ? cn.w : 0);
+      f0 = ch.x;
+      f1 = ch.y - e0;
+      f2 = ch.z - e1;
+      f3 = ch.w - e2;
+      // the next node (does not depend on the batch's outcome)
+      if (any) {
+        // whether anything is hit does not depend on the visiting order: the
+        // hit interior children are taken in slot order, with no sort
+        int next = -1;
+        if (h0 && cn.x == 0) next = ch.x;
+        if (h1 && cn.y == 0) {
+          if (next < 0) next = ch.y; else stk[(sp++) * kBlock] = ch.y;
+        }
+        if (h2 && cn.z == 0) {
+          if (next < 0) next = ch.z; else stk[(sp++) * kBlock] = ch.z;
+        }
+        if (h3 && cn.w == 0) {
+          if (next < 0) next = ch.w; else stk[(sp++) * kBlock] = ch.w;
+        }
+        if (next >= 0) {
+          node = next;
+        } else if (sp == 0) {
+          live = false;
+        } else {
+          --sp;
+          node = stk[sp * kBlock];
+        }
+        continue;
+      }
+      // interior children hit: keys finite for them, +inf otherwise
+      float k0 = (h0 && cn.x == 0) ? fminf(t0, 3.0e38f) : INFINITY;
+      float k1 = (h1 && cn.y == 0) ? fminf(t1, 3.0e38f) : INFINITY;
+      float k2 = (h2 && cn.z == 0) ? fminf(t2, 3.0e38f) : INFINITY;
+      float k3 = (h3 && cn.w == 0) ? fminf(t3, 3.0e38f) : INFINITY;
+      int v0 = ch.x, v1 = ch.y, v2 = ch.z, v3 = ch.w;
+      cswap(k0, v0, k1, v1);
+      cswap(k2, v2, k3, v3);
+      cswap(k0, v0, k2, v2);
+      cswap(k1, v1, k3, v3);
+      cswap(k1, v1, k2, v2);
+      if (k0 == INFINITY) {
+        if (sp == 0) {
+          live = false;
+        } else {
+          --sp;
+          node = stk[sp * kBlock];
+        }
+        continue;
+      }
+      node = v0;
+      if (k3 != INFINITY) stk[(sp++) * kBlock] = v3;
+      if (k2 != INFINITY) stk[(sp++) * kBlock] = v2;
+      if (k1 != INFINITY) stk[(sp++) * kBlock] = v1;
     }
-    {  // children 2 and 3
-      const float4 a = np[3], b = np[4], c = np[5];
-      h2 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2) & (cn.z >= 0);
-      h3 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3) & (cn.w >= 0);
-    }
-    // leaf children: test their triangles now (one loop over the ranges;
-    // triangle j of the loop is range k's first + j - its start, the offset
-    // picked by selects rather than branches)
-    const int e0 = (h0 && cn.x > 0) ? cn.x : 0;
-    const int e1 = e0 + ((h1 && cn.y > 0) ? cn.y : 0);
-    const int e2 = e1 + ((h2 && cn.z > 0) ? cn.z : 0);
-    const int e3 = e2 + ((h3 && cn.w > 0) ? cn.w : 0);
-    const int o1 = ch.y - e0, o2 = ch.z - e1, o3 = ch.w - e2;
+    // leaf phase: every lane of the wave holds a batch or has finished
+    if (e3 == 0) break;  // this lane has finished (no node, no batch)
     for (int j = 0; j < e3; ++j) {
-      int off = j < e2 ? o2 : o3;
-      off = j < e1 ? o1 : off;
-      off = j < e0 ? ch.x : off;
+      int off = j < e2 ? f2 : f3;
+      off = j < e1 ? f1 : off;
+      off = j < e0 ? f0 : off;
       const int i = j + off;
       const DTri T = load_tri(s, i);
       cnt.tris++;
+      if constexpr (ST) cnt.wave_tris += first_active_lane();
       float t, b1, b2;
       bool ok = tri_test(r, T, tmin, tbest, t, b1, b2);
       if (any) {
@@ -277,51 +368,8 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       h.tri = ok ? i : h.tri;
       h.prim = ok ? T.prim : h.prim;
     }
+    e3 = 0;
     if (found) break;
-    if (any) {
-      // whether anything is hit does not depend on the visiting order: the
-      // hit interior children are taken in slot order, with no sort
-      int next = -1;
-      if (h0 && cn.x == 0) next = ch.x;
-      if (h1 && cn.y == 0) {
-        if (next < 0) next = ch.y; else stk[(sp++) * kBlock] = ch.y;
-      }
-      if (h2 && cn.z == 0) {
-        if (next < 0) next = ch.z; else stk[(sp++) * kBlock] = ch.z;
-      }
-      if (h3 && cn.w == 0) {
-        if (next < 0) next = ch.w; else stk[(sp++) * kBlock] = ch.w;
-      }
-      if (next >= 0) {
-        node = next;
-      } else {
-        if (sp == 0) break;
-        --sp;
-        node = stk[sp * kBlock];
-      }
-      continue;
-    }
-    // interior children hit: keys finite for them, +inf otherwise
-    float k0 = (h0 && cn.x == 0) ? fminf(t0, 3.0e38f) : INFINITY;
-    float k1 = (h1 && cn.y == 0) ? fminf(t1, 3.0e38f) : INFINITY;
-    float k2 = (h2 && cn.z == 0) ? fminf(t2, 3.0e38f) : INFINITY;
-    float k3 = (h3 && cn.w == 0) ? fminf(t3, 3.0e38f) : INFINITY;
-    int v0 = ch.x, v1 = ch.y, v2 = ch.z, v3 = ch.w;
-    cswap(k0, v0, k1, v1);
-    cswap(k2, v2, k3, v3);
-    cswap(k0, v0, k2, v2);
-    cswap(k1, v1, k3, v3);
-    cswap(k1, v1, k2, v2);
-    if (k0 == INFINITY) {
-      if (sp == 0) break;
-      --sp;
-      node = stk[sp * kBlock];
-      continue;
-    }
-    node = v0;
-    if (k3 != INFINITY) stk[(sp++) * kBlock] = v3;
-    if (k2 != INFINITY) stk[(sp++) * kBlock] = v2;
-    if (k1 != INFINITY) stk[(sp++) * kBlock] = v1;
   }
   return any ? found : h.tri >= 0;
 }
@@ -658,9 +706,30 @@ struct Sink {
   float* rough_global;   // fallback when there are more slots than LDS holds
 };
 
-DEV void scatter_tex(const Sink& k, int tex, int texel, f3 g, Counters& cnt) {
+// Number of distinct values of `key` among the active lanes of the wave
+// (the same on every active lane): leader by leader, each pass retires the
+// lanes that share the leader's key.
+DEV int wave_distinct(int key) {
+  uint64_t todo = __ballot(1);
+  int n = 0;
+  while (todo) {
+    const int key0 = __shfl(key, __ffsll((unsigned long long)todo) - 1, 64);
+    todo &= ~(uint64_t)__ballot(key == key0);
+    ++n;
+  }
+  return n;
+}
+
+DEV void scatter_tex(const Sink& k, int tex, int texel, f3 g, Counters& cnt, bool stats) {
   float* base = k.tab->gtex[tex];
   if (!base) return;
+  if (stats) {
+    // measurement only (stats launches): how often lanes of one wave-wide
+    // scatter share a texel
+    const int n = wave_distinct(tex * 0x01000000 ^ texel);
+    cnt.tex_lanes++;
+    if (__lane_id() == __ffsll((unsigned long long)__ballot(1)) - 1) cnt.tex_keys += n;
+  }
   float* p = base + 3 * (size_t)texel;
   if (g.x != 0.f) { atomicAdd(p + 0, g.x); cnt.scatter++; }
   if (g.y != 0.f) { atomicAdd(p + 1, g.y); cnt.scatter++; }
@@ -670,6 +739,40 @@ DEV void scatter_rough(const Sink& k, int slot, float g, Counters& cnt) {
   if (g == 0.f) return;
   if (k.rough_lds) atomicAdd(k.rough_lds + slot, g);
   else if (k.rough_global) { atomicAdd(k.rough_global + slot, g); cnt.scatter++; }
+}
+
+// A lane's roughness gradient summed in a register while its slot stays the
+// same (slot -1: nothing held).
+struct RoughAcc {
+  int slot;
+  float v;
+};
+
+// Sum of x over the 64 lanes of the wave (butterfly of lane exchanges); all
+// lanes must be active, and every lane receives the same sum.
+DEV float wave_sum(float x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+// Flush of every lane's roughness accumulator, called by all 64 lanes of
+// the wave together: the lanes holding the same slot are summed across the
+// wave and one lane per distinct slot issues the atomic (one atomic per
+// distinct key instead of one per lane).
+DEV void wave_scatter_rough(const Sink& k, RoughAcc& a, Counters& cnt) {
+  const bool want = a.slot >= 0 && a.v != 0.f;
+  uint64_t todo = __ballot(want);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int key = __shfl(a.slot, leader, 64);
+    const bool mine = want && a.slot == key;
+    const float sum = wave_sum(mine ? a.v : 0.f);
+    if (__lane_id() == leader) scatter_rough(k, key, sum, cnt);
+    todo &= ~(uint64_t)__ballot(mine);
+  }
+  a.slot = -1;
+  a.v = 0.f;
 }
 
 DEV void camera_ray(const DCam& c, int W, int H, int x, int y, uint32_t g_lo, uint32_t g_hi,

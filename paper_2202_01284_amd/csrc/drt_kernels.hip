@@ -83,11 +83,11 @@ enum {
   MODE_TRAIN_SELF = 7
 };
 
-template <int MODE, bool HC = false>
+template <int MODE, bool HC = false, bool ST = false>
 DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
                       const LdsTables& tab, int cam, int x, int y, uint64_t g_base, int n_samples,
                       f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
-                      f3& out, int4* hrec = nullptr) {
+                      f3& out, int4* hrec = nullptr, RoughAcc* racc_out = nullptr) {
   constexpr bool ADJ = MODE == MODE_ADJOINT || MODE == MODE_ADJOINT_CACHED;
   constexpr bool JVP = MODE == MODE_JVP;
   // modes with a record vertex (cache queries, training records, cached replay)
@@ -113,9 +113,10 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   f3 beta_at = mk(0, 0, 0), L_at = mk(0, 0, 0);
   uint32_t self_mask = 0;  // records written by this path (MODE_TRAIN_SELF)
   // The lane's roughness gradient, summed in a register while its slot stays
-  // the same and handed to the workgroup's accumulator when the slot changes
-  // and after the last sample: one accumulator update per lane and work unit
-  // instead of one per vertex.
+  // the same and handed to the workgroup's accumulator when the slot changes;
+  // after the last sample it is handed to the caller (racc_out), which
+  // flushes it for the whole wave at once, or else added per lane: one
+  // accumulator update per lane and work unit instead of one per vertex.
   int racc_slot = -1;
   float racc = 0.f;
 
@@ -141,6 +142,10 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
   // other passes compile without them.
   auto step = [&](auto replay) -> bool {
     constexpr bool RB = ADJ && decltype(replay)::value;
+    if constexpr (ST) {
+      cnt.lane_steps++;
+      cnt.wave_steps += first_active_lane();
+    }
     constexpr bool DER = RB || JVP;  // BSDF parameter derivatives needed
     constexpr bool HREAD = HC && ((MODE == MODE_ADJOINT && RB) || MODE == MODE_ADJOINT_CACHED);
     constexpr bool HWRITE = HC && ((MODE == MODE_ADJOINT && !RB) || MODE == MODE_CACHED_SAMPLES);
@@ -169,7 +174,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       } else {
         RayPre rp = ray_pre(o, d);
         cnt.rays++;
-        hit = traverse(s, rp, 0.f, INFINITY, false, h, stk, cnt);
+        hit = traverse<ST>(s, rp, 0.f, INFINITY, false, h, stk, cnt);
       }
       if constexpr (HWRITE) {
         rec_tri = hit ? h.tri : -1;
@@ -225,6 +230,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
             ++k;
           } else {
             cnt.verts++;
+            if constexpr (ST) cnt.wave_shade += first_active_lane();
             // hoisted out of the switch: frame, albedo (texture or constant), roughness
             Frame fr = make_frame(n_g);
             f3 wi = to_local(fr, -d);
@@ -435,7 +441,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
         RayPre rp = ray_pre(so, sd);
         Hit h;
         cnt.shadow++;
-        vis = !traverse(s, rp, 0.f, stmax, true, h, stk, cnt);
+        vis = !traverse<ST>(s, rp, 0.f, stmax, true, h, stk, cnt);
       }
       if constexpr (HWRITE) rec_vis = vis;
       if (vis) {
@@ -456,7 +462,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     }
     if (RB) {
       // one scatter per vertex for its next-event and continuation terms
-      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
+      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt, R.stats != nullptr);
       if (vrslot >= 0 && grough != 0.f) {
         if (vrslot != racc_slot) {
           if (racc_slot >= 0) scatter_rough(sink, racc_slot, racc, cnt);
@@ -470,6 +476,32 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       *rec = make_int4(rec_tri, __float_as_int(rec_b1), __float_as_int(rec_b2), rec_vis ? 1 : 0);
     return done;
   };
+#ifndef DRT_REGEN_ALIVE
+#define DRT_REGEN_ALIVE 0
+#endif
+  if constexpr (MODE == MODE_PRIMAL && DRT_REGEN_ALIVE > 0) {
+    // Lanes whose path has ended start their next sample together, once at
+    // most DRT_REGEN_ALIVE lanes of the wave are still on a path: the idle
+    // lanes of a wave waiting for its longest path are put back to work,
+    // and the new (primary) rays start in a group.  Every lane still takes
+    // its samples in order, so the pixel's sum is the same.
+    bool alive = true;
+    start();
+    for (;;) {
+      if (alive && step(std::false_type{})) {
+        acc = acc + L;
+        ++sidx;
+        alive = false;
+      }
+      if (__popcll(__ballot(alive)) <= DRT_REGEN_ALIVE && !alive && sidx < n_samples) {
+        start();
+        alive = true;
+      }
+      if (__ballot(alive) == 0) break;
+    }
+    out = acc;
+    return;
+  }
   // lanes start each path together (coherent primary rays); a lane whose
   // path ends early waits for the wave
   for (;;) {
@@ -523,7 +555,14 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
     }
     if (++sidx == n_samples) break;
   }
-  if (ADJ && racc_slot >= 0) scatter_rough(sink, racc_slot, racc, cnt);
+  if (ADJ && racc_slot >= 0) {
+    if (racc_out) {
+      racc_out->slot = racc_slot;
+      racc_out->v = racc;
+    } else {
+      scatter_rough(sink, racc_slot, racc, cnt);
+    }
+  }
   out = acc;
 }
 
@@ -536,6 +575,13 @@ DEV void flush_counters(const DRender& R, Counters& c) {
   atomicAdd((unsigned long long*)&R.stats[DRT_STAT_VERTICES], (unsigned long long)c.verts);
   atomicAdd((unsigned long long*)&R.stats[DRT_STAT_SCATTER], (unsigned long long)c.scatter);
   atomicAdd((unsigned long long*)&R.stats[DRT_STAT_SAMPLES], (unsigned long long)c.samples);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_TEX_LANES], (unsigned long long)c.tex_lanes);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_TEX_KEYS], (unsigned long long)c.tex_keys);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_WAVE_NODES], (unsigned long long)c.wave_nodes);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_WAVE_TRIS], (unsigned long long)c.wave_tris);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_LANE_STEPS], (unsigned long long)c.lane_steps);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_WAVE_STEPS], (unsigned long long)c.wave_steps);
+  atomicAdd((unsigned long long*)&R.stats[DRT_STAT_WAVE_SHADE], (unsigned long long)c.wave_shade);
   atomicMax((unsigned long long*)&R.stats[DRT_STAT_LREM_MAX],
             (unsigned long long)__float_as_uint(c.lrem_max));
 }
@@ -574,8 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
       const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
       hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
     }
-    render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
-                           mk(0, 0, 0), stack + threadIdx.x, cnt, none, io, acc, hrec);
+    render_pixel<MODE, HC, STATS>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
+                                  mk(0, 0, 0), stack + threadIdx.x, cnt, none, io, acc, hrec);
     if (MODE != MODE_CACHED_SAMPLES) {
       const float inv = 1.0f / (float)R.spp;
       float* out = image + 3 * (((size_t)cam * H + y) * W + x);
@@ -620,6 +666,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int split = PERSIST ? adjoint_split(R.spp) : (int)gridDim.z / C.n;
   const int64_t units = PERSIST ? (int64_t)tiles_x * tiles_y * C.n * split : 1;  // < 2^31 (host)
   Counters cnt = {};
+  const Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
   for (int round = 0;; ++round) {
     int bx, by, cam, part;
     if constexpr (PERSIST) {
@@ -643,12 +690,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int x = bx * kTile + (threadIdx.x % kTile);
     const int y = by * kTile + (threadIdx.x / kTile);
     const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
+    RoughAcc racc{-1, 0.f};
     if (x < W && y < H && s1 > s0) {
       const size_t pix = ((size_t)cam * H + y) * W + x;
       const float inv = 1.0f / (float)R.spp;
       f3 dL = mk(adj[3 * pix] * inv, adj[3 * pix + 1] * inv, adj[3 * pix + 2] * inv);
       if (nonzero(dL)) {
-        Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
         f3 unused;
         int4* hrec = nullptr;
         if (PERSIST) {
@@ -659,10 +706,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
           const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
           hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
         }
-        render_pixel<MODE, HC>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0, dL,
-                               stack + threadIdx.x, cnt, sink, io, unused, hrec);
+        render_pixel<MODE, HC, STATS>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
+                                      s1 - s0, dL, stack + threadIdx.x, cnt, sink, io, unused, hrec,
+                                      &racc);
       }
     }
+    // all 64 lanes again (the unit is the workgroup's): the lanes' roughness
+    // sums, reduced across the wave per slot
+    wave_scatter_rough(sink, racc, cnt);
   }
   __syncthreads();
   if (lds_rough && threadIdx.x < s.n_rough) {

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_resolve(DScene s, DParams P, DG
         grough += gr.x + gr.y + gr.z;
       }
       Sink sink{&tab, lds_rough ? rough_acc : nullptr, lds_rough ? nullptr : G.rough};
-      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt);
+      if (vtex >= 0) scatter_tex(sink, vtex, vtexel, gtex, cnt, false);
       if (vrslot >= 0) scatter_rough(sink, vrslot, grough, cnt);
       if (CK) Lrem = Lrem + xyz(S.pe4[g]) + add;
       S.L4[g] = f4(Lrem, 0.f);
