@@ -50,12 +50,17 @@ def main():
     ap.add_argument("--no-aux", action="store_true", help="skip the 1M-triangle primal figure")
     ap.add_argument("--no-cache", action="store_true",
                     help="skip the radiance-cache comparison (equal RMSE, cached gradient step)")
+    ap.add_argument("--no-recovery", action="store_true",
+                    help="skip the 200-step texture recovery, cache vs plain at matched time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--strategies-only", action="store_true",
                     help="only the image + gradient strategies (PRB megakernel, PRB wavefront, "
                          "checkpointed) on the gradient-step workload, once each; prints their JSON")
+    ap.add_argument("--scene-1m-only", action="store_true",
+                    help="only the ~1M-triangle scene's primal (megakernel and wavefront, once "
+                         "each after a warm-up) and its replayed adjoint; prints their JSON")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -69,6 +74,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.scene_1m_only:
+        print(json.dumps(aux_primal_1m(drt, scenes, torch, reps=1)), flush=True)
+        return
     if args.calib_copy:
         # a plain copy of known size: 256 MiB read + 256 MiB written
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -106,14 +114,15 @@ def main():
     hits = drt.adjoint_hit_records(cams, SPP, D)
     ev = []
 
-    def step(k, timed):
+    def step(k, timed, records=True):
         drt.render_forward(gs, [tex], rough, cams, SPP, D, seed=2 * k + 1, out=img)
         drt.loss_l2(img, target, adj=adj)
         if timed:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
         drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * k + 2,
-                           grad_textures=[gtex], grad_roughness=grough, hit_records=hits)
+                           grad_textures=[gtex], grad_roughness=grough,
+                           hit_records=hits if records else None)
         if timed:
             e1.record()
             ev.append((e0, e1))
@@ -132,6 +141,15 @@ def main():
     samples = R * R * SPP
     value = samples / (ms * 1e-3) / 1e6
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # the same steps with the replay tracing its rays again (no records)
+    k0 = args.warmup + args.steps
+    step(k0, False, records=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(k0 + 1, k0 + 1 + args.steps):
+        step(k, False, records=False)
+    torch.cuda.synchronize()
+    ms_retrace = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # the primal of the same step by the wavefront variant (comparison only)
     ws = torch.empty(int(drt.lib.drt_render_wavefront_workspace_bytes(R * R * SPP)), dtype=torch.uint8,
@@ -192,7 +210,11 @@ def main():
                 "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
                 "traffic": measured_traffic(), "launch_ms": round(adj_ms, 3),
                 "units_per_launch": {k: st[k] for k in ("rays", "shadow_rays", "nodes", "tris",
-                                                         "vertices", "scatter", "samples")}}
+                                                         "vertices", "scatter", "samples")},
+                # lanes of a wave-wide texel scatter per distinct texel: the
+                # most a wave-level merge of equal keys could cut the atomics by
+                "texel_lanes_per_key": round(st["tex_lanes"] / max(st["tex_keys"], 1), 4),
+                "simd_utilisation": simd_utilisation(st)}
 
     aux = None
     checkpointed = None
@@ -206,6 +228,10 @@ def main():
                  "gradient_step": cache_gradient_step(drt, scenes, torch, R=args.res, SPP=args.spp,
                                                       tex_size=args.tex),
                  "gradient_bias": cache_gradient_bias(drt, scenes, torch, tex_size=args.tex)}
+
+    recovery = None
+    if not args.no_recovery:
+        recovery = texture_recovery(drt, scenes, torch, tex_size=args.tex)
 
     cpu = None
     if not args.no_cpu:
@@ -225,27 +251,41 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded procedural scene and textures)",
         "config": {"workload": "cornell-box + GGX conductor, 4096^2x3 texture + 1 roughness, "
-                               "primal+L2+replayed adjoint+Adam",
+                               "primal + L2 + replayed adjoint (replay from intersection records) "
+                               "+ Adam",
                    "width": R, "height": R, "spp": SPP, "max_depth": D, "russian_roulette": False,
                    "texture": [args.tex, args.tex, 3], "triangles": sc.n_triangles,
                    "target_spp": args.target_spp},
+        "retrace_step": {"ms_per_step": round(ms_retrace, 3),
+                         "msamples_s": round(samples / (ms_retrace * 1e-3) / 1e6, 3),
+                         "what": "the same gradient step with the replay tracing its rays again"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cache": cache,
         "wavefront": wavefront,
         "checkpointed": checkpointed,
         "aux": aux,
+        "texture_recovery": recovery,
     }
     print(json.dumps(line), flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per adjoint launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when
-    the kernel source has changed since the counters were taken."""
+def simd_utilisation(st):
+    """Mean fraction of a wave's 64 lanes taking part in each phase, from a
+    stats launch: node visits, triangle tests, vertex steps of live paths
+    and shading blocks, each per-lane count over 64 x the wave's count."""
+    def f(lanes, waves):
+        return round(st[lanes] / (64.0 * st[waves]), 4) if st[waves] else None
+    return {"node_loop": f("nodes", "wave_nodes"), "triangle_loop": f("tris", "wave_tris"),
+            "vertex_steps": f("lane_steps", "wave_steps"), "shading": f("vertices", "wave_shade")}
+
+
+def counter_record(name):
+    """A committed counter summary (profiles/<name>), or None when the
+    kernel source has changed since the counters were taken."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "adjoint_traffic.json")))
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
         h = hashlib.sha256()
         for f in rec["sources"]:  # every file the kernel is compiled from, in order
             h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -253,7 +293,15 @@ def measured_traffic():
         return None
     if h.hexdigest() != rec.get("source_sha256"):
         return None
-    return int(rec["hbm_bytes"])
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per adjoint launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    rec = counter_record("adjoint_traffic.json")
+    return int(rec["hbm_bytes"]) if rec else None
 
 
 def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
@@ -327,7 +375,7 @@ def checkpoint_compare(drt, scenes, torch, sc, tex, rough, adj, R, SPP, D,
             "gradient_step_workload": head, "by_depth": rows}
 
 
-def aux_primal_1m(drt, scenes, torch):
+def aux_primal_1m(drt, scenes, torch, reps=2):
     """Primal Msamples/s on the ~1M-triangle procedural scene (1024^2, 64 spp,
     depth 6, Russian roulette from 3): reported beside the headline."""
     t = time.perf_counter()
@@ -339,7 +387,6 @@ def aux_primal_1m(drt, scenes, torch):
     img = torch.empty((1, 1024, 1024, 3), dtype=torch.float32, device="cuda")
     drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=1, out=img)
     torch.cuda.synchronize()
-    reps = 2
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(reps):
@@ -351,6 +398,20 @@ def aux_primal_1m(drt, scenes, torch):
     drt.render_forward(gs, tex, rough, sc.cameras, 64, 6, 3, seed=2, out=img, stats=stats)
     st = drt.read_stats(stats)
     rays = st["rays"] + st["shadow_rays"]
+    # traversal roofline: the nodes and triangles a ray must read (128 B per
+    # four-wide node, 48 B per triangle) at the achieved ray rate, against
+    # HBM; the bytes that reached L2 and HBM per ray from the committed
+    # counter summary of this launch
+    bpr = (st["nodes"] * 128.0 + st["tris"] * 48.0) / max(rays, 1)
+    rec = counter_record("traversal_1m_counters.json")
+    traversal = {"algorithmic_bytes_per_ray": round(bpr, 1),
+                 "achieved_GBps": round(bpr * rays / (ms * 1e-3) / 1e9, 1),
+                 "hbm_peak_GBps": 8000.0,
+                 "frac_of_hbm_peak": round(bpr * rays / (ms * 1e-3) / 8e12, 4),
+                 "hbm_bytes_per_ray": rec["hbm_bytes_per_ray"] if rec else None,
+                 "l2_bytes_per_ray": rec["l2_bytes_per_ray"] if rec else None,
+                 "valu_busy": rec["valu_busy"] if rec else None,
+                 "valu_lane_utilisation": rec["valu_lane_utilisation"] if rec else None}
     # the same image by the wavefront variant (state through HBM between kernels)
     ws = torch.empty(int(drt.lib.drt_render_wavefront_workspace_bytes(1024 * 1024 * 64)),
                      dtype=torch.uint8, device="cuda")
@@ -399,13 +460,15 @@ def aux_primal_1m(drt, scenes, torch):
             "adjoint_16spp_ms": {"megakernel": round(adj_mk, 2), "megakernel_records": round(adj_rec, 2),
                                  "wavefront": round(adj_wf, 2)},
             "mrays_s": round(rays / ms / 1e3, 1),
+            "simd_utilisation": simd_utilisation(st),
+            "traversal": traversal,
             "nodes_per_ray": round(st["nodes"] / max(rays, 1), 2),
             "tris_per_ray": round(st["tris"] / max(rays, 1), 2),
             "bvh": {k: gs.info[k] for k in ("n_nodes", "max_depth", "forced_leaves")},
             "host_build_s": round(build_s, 2)}
 
 
-def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), ref_spp=4096):
+def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8, 16, 32, 64), ref_spp=4096):
     """Radiance cache vs plain path tracing at equal RMSE (Cornell box with
     the random back-wall texture, D = 6, RR from 3, truncation at v3).
 
@@ -483,6 +546,7 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
         spp_eq, sp, sp_t = equal(m_cache, cache_ms, train_ms)
         spp_eq_s, sp_s, sp_t_s = equal(m_self, self_ms, train_self_ms)
         rows.append({"spp": s, "plain_ms": round(plain_ms, 3), "cache_ms": round(cache_ms, 3),
+                     "self_ms": round(self_ms, 3),
                      "rmse_plain": round(m_plain ** 0.5, 6), "rmse_cache": round(m_cache ** 0.5, 6),
                      "plain_spp_at_equal_rmse": round(spp_eq, 3),
                      "speedup_at_equal_rmse": round(sp, 3),
@@ -491,8 +555,12 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
                                        "plain_spp_at_equal_rmse": round(spp_eq_s, 3),
                                        "speedup_at_equal_rmse": round(sp_s, 3),
                                        "speedup_incl_training": round(sp_t_s, 3)}})
+    at_target = {"cache": at_target_rmse(rows, "rmse_cache", "cache_ms", train_ms),
+                 "self_training": at_target_rmse(rows, ("self_training", "rmse_cache"), "self_ms",
+                                                 train_self_ms)}
     return {"workload": f"cornell-box, random 64^2 texture, {R}^2, D6 RR3, cache at v3, "
                         f"hash grid 16x2^19x2 fp16, 80-64x4-3 bf16 network",
+            "at_target": at_target,
             "reference_spp": ref_spp, "train_frames": frames, "train_paths_per_frame": 65536,
             "train_ms_per_frame": round(train_ms, 3),
             "final_train_loss": round(float(cache.loss.item()), 4),
@@ -500,6 +568,41 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8), 
                               "train_ms_per_frame": round(train_self_ms, 3),
                               "final_train_loss": round(float(cache_self.loss.item()), 4)},
             "by_spp": rows}
+
+
+def at_target_rmse(rows, rmse_key, ms_key, train_ms):
+    """Time for an estimator to reach the RMSE that plain path tracing
+    reaches at the largest spp of `rows` (the target), against the plain
+    render at that spp.  The estimator's spp at the target is interpolated
+    between the two measured rows around the crossing (log RMSE linear in
+    log spp), its time linearly in spp; one training frame per image is
+    charged for 'incl_training'.  None where the estimator's RMSE at the
+    largest spp is still above the target (bias dominates)."""
+    import math
+
+    def rm(r):
+        return r[rmse_key[0]][rmse_key[1]] if isinstance(rmse_key, tuple) else r[rmse_key]
+    last = rows[-1]
+    target = last["rmse_plain"]
+    out = {"target_rmse": target, "plain_spp": last["spp"], "plain_ms": last["plain_ms"]}
+    if rm(last) > target:
+        out.update({"spp": None, "ms": None, "speedup": None, "speedup_incl_training": None,
+                    "note": "RMSE above the target at the largest spp"})
+        return out
+    lo = next((i for i in range(len(rows) - 1) if rm(rows[i]) > target >= rm(rows[i + 1])), None)
+    if lo is None:  # already below the target at the smallest spp
+        a = rows[0]
+        spp = a["spp"] * (rm(a) / target) ** 2
+        ms = a[ms_key] * spp / a["spp"]
+    else:
+        a, b = rows[lo], rows[lo + 1]
+        f = (math.log(target) - math.log(rm(a))) / (math.log(rm(b)) - math.log(rm(a)))
+        spp = math.exp(math.log(a["spp"]) + f * (math.log(b["spp"]) - math.log(a["spp"])))
+        ms = a[ms_key] + (b[ms_key] - a[ms_key]) * (spp - a["spp"]) / (b["spp"] - a["spp"])
+    out.update({"spp": round(spp, 2), "ms": round(ms, 3),
+                "speedup": round(last["plain_ms"] / ms, 3),
+                "speedup_incl_training": round(last["plain_ms"] / (ms + train_ms), 3)})
+    return out
 
 
 def cache_gradient_step(drt, scenes, torch, R=1024, SPP=16, tex_size=4096, steps=3):
@@ -647,6 +750,119 @@ def cache_gradient_bias(drt, scenes, torch, n_cams=16, R=512, spp=32, ref_spp=25
             "train_frames": train_frames}
 
 
+def texture_recovery(drt, scenes, torch, n_cams=16, R=512, spp=32, steps=200, tex_size=4096,
+                     lr=1e-2, every=10, target_spp=256, warmup_frames=100):
+    """Differentiable optimisation with the radiance cache (16 seeded views
+    at 512^2 in one launch, depth 6, RR from 3): 200 Adam steps (lr 1e-2)
+    recover the 4096^2x3 back-wall texture and the conductor roughness from
+    target renders (roughness 0.2 and a random texture of 64x64 cells --
+    scenes.cell_texture -- which the 512^2 views resolve; plain at
+    target_spp).  Run twice from the same start (texture 0.5, roughness 0.3):
+    with the cache in the primal and in the replay at `spp` (first trained
+    for `warmup_frames` frames, then one 65,536-path frame per step on the
+    current parameters; the warm-up's time is charged to the first step),
+    and plain at the spp whose step costs the same wall time as the cached
+    step.  Every `every` steps: the image loss, the texture error against the
+    target (relative L2 per texel and of 64x64-texel cell means) and the
+    roughness, with the accumulated HIP-event time."""
+    D, RR = 6, 3
+    dev = "cuda"
+    sc = scenes.cornell(tex_size=tex_size, width=R, height=R, conductor=True)
+    cams = scenes.ring_cameras(n_cams, R, R)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    tex_t = torch.from_numpy(scenes.cell_texture(tex_size)).to(dev)
+    target = drt.render_forward(gs, [tex_t], torch.tensor([0.2], device=dev), cams, target_spp, D, RR,
+                                seed=1284)
+    b = tex_size // 64
+    blk = lambda x: x.double().reshape(b, 64, b, 64, 3).mean((1, 3))  # noqa: E731
+    t_blk = blk(tex_t)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def run(cached, s, n_steps, record=True, warm=warmup_frames):
+        tex = torch.full((tex_size, tex_size, 3), 0.5, dtype=torch.float32, device=dev)
+        rough = torch.tensor([0.3], dtype=torch.float32, device=dev)
+        gtex, grough = torch.zeros_like(tex), torch.zeros_like(rough)
+        m_t, v_t, m_r, v_r = (torch.zeros_like(tex), torch.zeros_like(tex), torch.zeros_like(rough),
+                              torch.zeros_like(rough))
+        img = torch.empty((n_cams, R, R, 3), dtype=torch.float32, device=dev)
+        adj = torch.empty_like(img)
+        n = n_cams * R * R * s
+        curve, total_ms = [], 0.0
+        if cached:
+            cache = drt.NrcCache(cfg, W0, grid0, n_paths=65536, lr=1e-2)
+            work = drt.cached_work(n, dev, sample_radiance=True)
+            hits = drt.cached_hit_records(cams, s, D)
+            a, e = ev(), ev()
+            a.record()
+            for f in range(warm):
+                cache.train_frame(gs, [tex], rough, cams, seed=40000 + f)
+            e.record()
+            torch.cuda.synchronize()
+            total_ms += a.elapsed_time(e)
+        else:
+            hits = drt.adjoint_hit_records(cams, s, D)
+        warm_ms = total_ms
+        for k in range(n_steps):
+            a, e = ev(), ev()
+            a.record()
+            if cached:
+                cache.train_frame(gs, [tex], rough, cams, seed=50000 + k)
+                cache.render(gs, [tex], rough, cams, s, seed=2 * k + 1, out=img, work=work[:3])
+            else:
+                drt.render_forward(gs, [tex], rough, cams, s, D, RR, seed=2 * k + 1, out=img)
+            loss, _ = drt.loss_l2(img, target, adj=adj)
+            if cached:
+                cache.adjoint(gs, [tex], rough, cams, adj, s, seed=2 * k + 2, grad_textures=[gtex],
+                              grad_roughness=grough, work=work, hit_records=hits)
+            else:
+                drt.render_adjoint(gs, [tex], rough, cams, adj, s, D, RR, seed=2 * k + 2,
+                                   grad_textures=[gtex], grad_roughness=grough, hit_records=hits)
+            drt.adam_step(tex, gtex, m_t, v_t, k + 1, lr=lr, lo=0.0, hi=1.0, zero_grad=True)
+            drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=lr, lo=0.01, hi=1.0, zero_grad=True)
+            e.record()
+            torch.cuda.synchronize()
+            total_ms += a.elapsed_time(e)
+            if record and ((k + 1) % every == 0 or k == 0):
+                d = (tex - tex_t).double()
+                curve.append({"step": k + 1, "ms": round(total_ms, 1),
+                              "image_loss": float(loss.item()),
+                              "tex_rel_err_texel": round(float(d.norm() / tex_t.double().norm()), 5),
+                              "tex_rel_err_64x64_blocks": round(float((blk(tex) - t_blk).norm()
+                                                                      / t_blk.norm()), 5),
+                              "roughness": round(float(rough.item()), 5)})
+        del hits
+        return (total_ms - warm_ms) / n_steps, curve
+
+    # per-step cost of each method (a few steps, not recorded), then the
+    # plain spp whose step costs what the cached step costs
+    run(True, spp, 2, record=False, warm=0)
+    ms_cache, _ = run(True, spp, 4, record=False, warm=0)
+    ms_plain_s, _ = run(False, spp, 4, record=False)
+    spp_p = max(1, int(round(spp * ms_cache / ms_plain_s)))
+    ms_c, curve_c = run(True, spp, steps)
+    ms_p, curve_p = run(False, spp_p, steps)
+    return {"workload": f"{n_cams} views x {R}^2 in one launch, depth {D} RR{RR}, {tex_size}^2x3 "
+                        f"texture + roughness, {steps} Adam steps lr {lr}; target: random texture "
+                        f"of 64x64 cells, roughness 0.2, {target_spp} spp",
+            "cache": {"spp": spp, "ms_per_step": round(ms_c, 2), "warmup_frames": warmup_frames,
+                      "train_paths_per_step": 65536, "curve": curve_c},
+            "plain_matched_time": {"spp": spp_p, "ms_per_step": round(ms_p, 2), "curve": curve_p}}
+
+
+def cpu_model():
+    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sc, R, SPP, D, budget_s):
     """FP64 oracle on a bounded, seeded sample of the workload's pixels:
     primal (seed A) + adjoint (seed B) per pixel, all host threads."""
@@ -671,7 +887,7 @@ def cpu_baseline(sc, R, SPP, D, budget_s):
         # next batch sized to land near the budget
         n = int(max(256, n * (budget_s - total_t) / max(dt, 1e-3)))
     return {"value": round(total_pix * SPP / total_t / 1e6, 5), "unit": "Msamples/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{total_pix} random pixels x {SPP} spp of the same scene/texture "
                       f"(primal + reverse-sweep adjoint), {total_t:.1f} s"}
 

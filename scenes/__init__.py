@@ -289,6 +289,16 @@ def random_texture(size: int, seed: int = SEED_MATERIALS) -> np.ndarray:
     return rng.uniform(0.05, 0.95, size=(size, size, 3)).astype(np.float32)
 
 
+def cell_texture(size: int, cells: int = 64, seed: int = SEED_MATERIALS) -> np.ndarray:
+    """random_texture(cells) with each texel widened to a (size / cells)^2
+    block: a target whose structure the views can resolve (an i.i.d. texel
+    pattern at 4096^2 averages out over the texels one pixel covers)."""
+    if size % cells:
+        raise ValueError("size must be a multiple of cells")
+    k = size // cells
+    return np.repeat(np.repeat(random_texture(cells, seed), k, axis=0), k, axis=1)
+
+
 def cornell(tex_size: int = 64, width: int = 64, height: int = 64, *,
             conductor: bool = False, texture: Optional[np.ndarray] = None,
             roughness: Optional[float] = None, seed: int = SEED_GEOMETRY,
