@@ -145,12 +145,9 @@ DEV void sh16_sel(float x, float y, float z, int g, float o[4]) {
     o[j] = g == 0 ? v[j] : (g == 1 ? v[4 + j] : (g == 2 ? v[8 + j] : v[12 + j]));
 }
 
-// Trilinear corners of one level: index (entry of 2 features) and weight.
-DEV void level_corners(const DNrcNet& net, const GridLds& gl, int l, const float xn[3],
-                       uint32_t idx[8], float w[8]) {
+// Cell of one level: lowest corner c0 and the position's fractions in the cell.
+DEV void level_cell(const GridLds& gl, int l, const float xn[3], int c0[3], float fr[3]) {
   const int N = gl.res[l];
-  int c0[3];
-  float fr[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float pos = xn[a] * (float)N;
@@ -159,15 +156,35 @@ DEV void level_corners(const DNrcNet& net, const GridLds& gl, int l, const float
     c0[a] = c;
     fr[a] = pos - (float)c;
   }
+}
+// Entry of corner k (bit 0: +x, bit 1: +y, bit 2: +z) of the cell: dense
+// index while the level fits the table, else the spatial hash -- both
+// computed and one selected, so lanes on dense and on hashed levels take
+// no divergent branch.
+DEV uint32_t corner_entry(const DNrcNet& net, const GridLds& gl, int l, const int c0[3], int k) {
+  const uint32_t n1 = (uint32_t)(gl.res[l] + 1);
   const uint32_t mask = (1u << net.log2_table) - 1u;
-  const uint32_t n1 = (uint32_t)(N + 1);
+  const uint32_t cx = c0[0] + (k & 1), cy = c0[1] + ((k >> 1) & 1), cz = c0[2] + ((k >> 2) & 1);
+  const uint32_t dense = cx + cy * n1 + cz * n1 * n1;
+  const uint32_t hashed = (cx ^ (cy * 2654435761u) ^ (cz * 805459861u)) & mask;
+  return gl.dense[l] ? dense : hashed;
+}
+// Trilinear weight of corner k.
+DEV float corner_weight(const float fr[3], int k) {
+  return ((k & 1) ? fr[0] : 1.f - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.f - fr[1]) *
+         (((k >> 2) & 1) ? fr[2] : 1.f - fr[2]);
+}
+
+// Trilinear corners of one level: index (entry of 2 features) and weight.
+DEV void level_corners(const DNrcNet& net, const GridLds& gl, int l, const float xn[3],
+                       uint32_t idx[8], float w[8]) {
+  int c0[3];
+  float fr[3];
+  level_cell(gl, l, xn, c0, fr);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    uint32_t cx = c0[0] + (k & 1), cy = c0[1] + ((k >> 1) & 1), cz = c0[2] + ((k >> 2) & 1);
-    w[k] = ((k & 1) ? fr[0] : 1.f - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.f - fr[1]) *
-           (((k >> 2) & 1) ? fr[2] : 1.f - fr[2]);
-    idx[k] = gl.dense[l] ? cx + cy * n1 + cz * n1 * n1
-                         : ((cx * 1u) ^ (cy * 2654435761u) ^ (cz * 805459861u)) & mask;
+    w[k] = corner_weight(fr, k);
+    idx[k] = corner_entry(net, gl, l, c0, k);
   }
 }
 
@@ -176,45 +193,66 @@ DEV void normalise(const DNrcNet& net, const float* rec, float xn[3]) {
   for (int a = 0; a < 3; ++a) xn[a] = fminf(fmaxf((rec[a] - net.lo[a]) * net.inv_ext[a], 0.f), 1.f);
 }
 
-DEV void level_features(const DNrcNet& net, const GridLds& gl, int l, const float xn[3],
-                        float& f0, float& f1) {
-  uint32_t idx[8];
-  float w[8];
-  level_corners(net, gl, l, xn, idx, w);
-  const uint32_t* tab = net.grid + ((size_t)l << net.log2_table);
-  f0 = 0.f;
-  f1 = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint32_t e = tab[idx[k]];
-    f0 += w[k] * __half2float(__ushort_as_half((unsigned short)(e & 0xFFFFu)));
-    f1 += w[k] * __half2float(__ushort_as_half((unsigned short)(e >> 16)));
-  }
+// The 20 inputs of lane group g of a sample (B chunks s = 0..4), FP32.
+// Chunk 0: hash features 4g..4g+3 = levels 2g, 2g+1; chunk 1: levels 8+2g,
+// 9+2g.  The record (64 B, 16-byte aligned) is read whole, and the 32 corner
+// entries of the lane's four levels are all requested before any of them
+// is used: one memory round trip for the record and one for the grid.
+struct Rec {
+  float4 a, b, c, d;  // record floats 0..3, 4..7, 8..11, 12..15
+};
+DEV Rec load_rec(const float* rec) {
+  const float4* r4 = reinterpret_cast<const float4*>(rec);
+  return Rec{r4[0], r4[1], r4[2], r4[3]};
 }
 
-// The 20 inputs of lane group g of a sample (B chunks s = 0..4), FP32.
+// (An invalid lane -- past the last record -- encodes whatever record it
+// holds and gets zeros, selected at the end rather than branched around.)
+DEV void encode_rec(const DNrcNet& net, const GridLds& gl, const Rec& R, bool valid, int g,
+                    float in[5][4]) {
+  const float4 ra = R.a, rb = R.b, rc = R.c, rd = R.d;
+  const float p[3] = {ra.x, ra.y, ra.z};
+  float xn[3];
+  normalise(net, p, xn);
+  const int lv[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
+  uint32_t e[4][8];
+  float fr[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int c0[3];
+    level_cell(gl, lv[q], xn, c0, fr[q]);
+    const uint32_t* tab = net.grid + ((size_t)lv[q] << net.log2_table);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[q][k] = tab[corner_entry(net, gl, lv[q], c0, k)];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float w = corner_weight(fr[q], k);
+      f0 += w * __half2float(__ushort_as_half((unsigned short)(e[q][k] & 0xFFFFu)));
+      f1 += w * __half2float(__ushort_as_half((unsigned short)(e[q][k] >> 16)));
+    }
+    in[q >> 1][2 * (q & 1)] = f0;
+    in[q >> 1][2 * (q & 1) + 1] = f1;
+  }
+  // record: p 0..2, w_o 3..5, n 6..8, roughness 9, albedo 10..12
+  sh16_sel(ra.w, rb.x, rb.y, g, in[2]);
+  sh16_sel(rb.z, rb.w, rc.x, g, in[3]);
+  in[4][0] = g == 0 ? rc.y : 0.f;
+  in[4][1] = g == 0 ? rc.z : 0.f;
+  in[4][2] = g == 0 ? rc.w : 0.f;
+  in[4][3] = g == 0 ? rd.x : 0.f;
+#pragma unroll
+  for (int s = 0; s < 5; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) in[s][j] = valid ? in[s][j] : 0.f;
+}
+// rec must point at a readable record also for an invalid lane
 DEV void encode_lane(const DNrcNet& net, const GridLds& gl, const float* rec, bool valid, int g,
                      float in[5][4]) {
-  if (!valid) {
-#pragma unroll
-    for (int s = 0; s < 5; ++s)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) in[s][j] = 0.f;
-    return;
-  }
-  float xn[3];
-  normalise(net, rec, xn);
-  // chunk 0: hash features 4g..4g+3 = levels 2g, 2g+1; chunk 1: levels 8+2g, 9+2g
-  level_features(net, gl, 2 * g, xn, in[0][0], in[0][1]);
-  level_features(net, gl, 2 * g + 1, xn, in[0][2], in[0][3]);
-  level_features(net, gl, 8 + 2 * g, xn, in[1][0], in[1][1]);
-  level_features(net, gl, 9 + 2 * g, xn, in[1][2], in[1][3]);
-  sh16_sel(rec[3], rec[4], rec[5], g, in[2]);
-  sh16_sel(rec[6], rec[7], rec[8], g, in[3]);
-  in[4][0] = g == 0 ? rec[9] : 0.f;
-  in[4][1] = g == 0 ? rec[10] : 0.f;
-  in[4][2] = g == 0 ? rec[11] : 0.f;
-  in[4][3] = g == 0 ? rec[12] : 0.f;
+  encode_rec(net, gl, load_rec(rec), valid, g, in);
 }
 
 DEV void load_grid_tables(GridLds& gl, const DNrcNet& net) {
@@ -457,26 +495,46 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_infer(DNrcNet net, const float*
   const int64_t n = min((int64_t)*count, capacity);
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const TileRange tr = xcd_tiles((n + 15) / 16);
+  if (tr.first >= tr.end) return;
+  // Software pipeline over the wave's tiles: the next tile's query index is
+  // requested before this tile's grid gathers and its record before this
+  // tile's network, so only the gathers' round trip is exposed per tile.
+  // Slot indices are below 2^31 (the host bounds the capacity); an invalid
+  // lane reads slot 0 (n >= 1 here) and is masked.  The loads are
+  // unconditional so that no wait is placed at them.
+  auto slot_of = [&](int64_t tile, bool& valid) -> int {
+    const int64_t slot = tile * 16 + (lane & 15);
+    valid = tile < tr.end && slot < n;
+    return valid ? (int)slot : 0;
+  };
+  auto query_of = [&](int slot) -> int { return order ? order[slot] : slot; };
+  bool valid;
+  int qi = query_of(slot_of(tr.first, valid));
+  Rec rec = load_rec(q + (int64_t)qi * NRC_REC);
+  int pix = qpix[qi];
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-    int64_t slot = tile * 16 + (lane & 15);
-    bool valid = slot < n;
-    int64_t qi = valid ? (order ? (int64_t)order[slot] : slot) : 0;
-    const float* rec = q + qi * NRC_REC;
+    bool valid_n;
+    const int qi_n = query_of(slot_of(tile + tr.step, valid_n));
     float in[5][4];
-    encode_lane(net, gl, rec, valid, g, in);
+    encode_rec(net, gl, rec, valid, g, in);
+    const Rec rec_n = load_rec(q + (int64_t)qi_n * NRC_REC);
+    const int pix_n = qpix[qi_n];
     Acts A;
 #pragma unroll
     for (int s = 0; s < 5; ++s) A.h0[s] = pack4(in[s][0], in[s][1], in[s][2], in[s][3]);
     f32x4 y = forward_tile(wl, A, lane);
     if (g == 0 && valid) {
-      float* px = image + 3 * (size_t)qpix[qi];
-      float c0 = rec[13] * fmaxf(y[0], 0.f) * inv_spp;
-      float c1 = rec[14] * fmaxf(y[1], 0.f) * inv_spp;
-      float c2 = rec[15] * fmaxf(y[2], 0.f) * inv_spp;
+      float* px = image + 3 * (size_t)pix;
+      float c0 = rec.d.y * fmaxf(y[0], 0.f) * inv_spp;
+      float c1 = rec.d.z * fmaxf(y[1], 0.f) * inv_spp;
+      float c2 = rec.d.w * fmaxf(y[2], 0.f) * inv_spp;
       if (c0 != 0.f) atomicAdd(px, c0);
       if (c1 != 0.f) atomicAdd(px + 1, c1);
       if (c2 != 0.f) atomicAdd(px + 2, c2);
     }
+    valid = valid_n;
+    rec = rec_n;
+    pix = pix_n;
   }
 }
 
