@@ -476,32 +476,6 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       *rec = make_int4(rec_tri, __float_as_int(rec_b1), __float_as_int(rec_b2), rec_vis ? 1 : 0);
     return done;
   };
-#ifndef DRT_REGEN_ALIVE
-#define DRT_REGEN_ALIVE 0
-#endif
-  if constexpr (MODE == MODE_PRIMAL && DRT_REGEN_ALIVE > 0) {
-    // Lanes whose path has ended start their next sample together, once at
-    // most DRT_REGEN_ALIVE lanes of the wave are still on a path: the idle
-    // lanes of a wave waiting for its longest path are put back to work,
-    // and the new (primary) rays start in a group.  Every lane still takes
-    // its samples in order, so the pixel's sum is the same.
-    bool alive = true;
-    start();
-    for (;;) {
-      if (alive && step(std::false_type{})) {
-        acc = acc + L;
-        ++sidx;
-        alive = false;
-      }
-      if (__popcll(__ballot(alive)) <= DRT_REGEN_ALIVE && !alive && sidx < n_samples) {
-        start();
-        alive = true;
-      }
-      if (__ballot(alive) == 0) break;
-    }
-    out = acc;
-    return;
-  }
   // lanes start each path together (coherent primary rays); a lane whose
   // path ends early waits for the wave
   for (;;) {

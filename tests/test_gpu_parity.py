@@ -461,3 +461,43 @@ def test_binding_refuses_host_and_strided_tensors():
     # the same calls with proper buffers go through
     out = drt.philox(ctr.contiguous(), keys)
     assert out.shape == (16, 4)
+
+
+def test_stats_counters_are_consistent():
+    """The stats launches' per-phase counters: each wave-level count is at
+    least one active lane and at most 64 per event; the texel scatter counts
+    at least one distinct texel per wave-wide scatter; counting changes no
+    result (image and gradients bit-identical to the launch without it)."""
+    drt = _drt()
+    sc = scenes.bsdf_zoo(width=48, height=40)
+    gs = drt.Scene(sc)
+    tex, rough = _params(sc)
+    kw = dict(spp=3, max_depth=6, rr_depth=3)
+    st_f = drt.new_stats()
+    img_s = drt.render_forward(gs, tex, rough, sc.cameras, kw["spp"], kw["max_depth"], kw["rr_depth"],
+                               seed=4, stats=st_f)
+    img = drt.render_forward(gs, tex, rough, sc.cameras, kw["spp"], kw["max_depth"], kw["rr_depth"],
+                             seed=4)
+    assert torch.equal(img_s, img)
+    c = sc.cameras[0]
+    adj = torch.from_numpy(np.random.default_rng(6).normal(size=(1, c.height, c.width, 3))
+                           .astype(np.float32)).cuda()
+    st_a = drt.new_stats()
+    for hits in (None, drt.adjoint_hit_records(sc.cameras, kw["spp"], kw["max_depth"])):
+        st_a.zero_()
+        gt_s, gr_s = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, kw["spp"], kw["max_depth"],
+                                        kw["rr_depth"], seed=5, stats=st_a, hit_records=hits)
+        gt, gr = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, kw["spp"], kw["max_depth"],
+                                    kw["rr_depth"], seed=5, hit_records=hits)
+        for a, b in zip(gt_s, gt):
+            # float atomics: the same terms, possibly added in another order
+            np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-5, atol=1e-9)
+        for st, what in ((drt.read_stats(st_f), "primal"), (drt.read_stats(st_a), "adjoint")):
+            print(what, hits is not None, st, flush=True)
+            for lanes, waves in (("nodes", "wave_nodes"), ("tris", "wave_tris"),
+                                 ("lane_steps", "wave_steps"), ("vertices", "wave_shade")):
+                assert st[waves] <= st[lanes] <= 64 * st[waves], (what, lanes, st)
+            assert st["wave_nodes"] > 0 and st["wave_steps"] > 0 and st["wave_shade"] > 0
+        st = drt.read_stats(st_a)
+        assert 0 < st["tex_keys"] <= st["tex_lanes"], st
+        assert drt.read_stats(st_f)["tex_lanes"] == 0
