@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--scene-1m-only", action="store_true",
                     help="only the ~1M-triangle scene's primal (megakernel and wavefront, once "
                          "each after a warm-up) and its replayed adjoint; prints their JSON")
+    ap.add_argument("--cache-render-only", action="store_true",
+                    help="only the radiance cache's render at 1024^2, 64 spp (after 100 training "
+                         "frames) and the plain render beside it, twice each; prints their times")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -76,6 +79,9 @@ def main():
     dev = "cuda"
     if args.scene_1m_only:
         print(json.dumps(aux_primal_1m(drt, scenes, torch, reps=1)), flush=True)
+        return
+    if args.cache_render_only:
+        print(json.dumps(cache_render_only(drt, scenes, torch, R=args.res)), flush=True)
         return
     if args.calib_copy:
         # a plain copy of known size: 256 MiB read + 256 MiB written
@@ -400,8 +406,8 @@ def aux_primal_1m(drt, scenes, torch, reps=2):
     rays = st["rays"] + st["shadow_rays"]
     # traversal roofline: the nodes and triangles a ray must read (128 B per
     # four-wide node, 48 B per triangle) at the achieved ray rate, against
-    # HBM; the bytes that reached L2 and HBM per ray from the committed
-    # counter summary of this launch
+    # HBM; the HBM bytes and L2 requests per ray, VALU busy and lane
+    # utilisation from the committed counter summary of this launch
     bpr = (st["nodes"] * 128.0 + st["tris"] * 48.0) / max(rays, 1)
     rec = counter_record("traversal_1m_counters.json")
     traversal = {"algorithmic_bytes_per_ray": round(bpr, 1),
@@ -409,7 +415,8 @@ def aux_primal_1m(drt, scenes, torch, reps=2):
                  "hbm_peak_GBps": 8000.0,
                  "frac_of_hbm_peak": round(bpr * rays / (ms * 1e-3) / 8e12, 4),
                  "hbm_bytes_per_ray": rec["hbm_bytes_per_ray"] if rec else None,
-                 "l2_bytes_per_ray": rec["l2_bytes_per_ray"] if rec else None,
+                 "l2_requests_per_ray": rec["l2_requests_per_ray"] if rec else None,
+                 "l2_hit_rate": rec["l2_hit_rate"] if rec else None,
                  "valu_busy": rec["valu_busy"] if rec else None,
                  "valu_lane_utilisation": rec["valu_lane_utilisation"] if rec else None}
     # the same image by the wavefront variant (state through HBM between kernels)
@@ -568,6 +575,38 @@ def cache_equal_rmse(drt, scenes, torch, R=1024, frames=300, spps=(1, 2, 4, 8, 1
                               "train_ms_per_frame": round(train_self_ms, 3),
                               "final_train_loss": round(float(cache_self.loss.item()), 4)},
             "by_spp": rows}
+
+
+def cache_render_only(drt, scenes, torch, R=1024, spp=64, frames=100, reps=2):
+    """The cached render of the equal-RMSE comparison at its target spp
+    (a cache trained for `frames` frames) and the plain render beside it,
+    HIP-event times of `reps` launches each (for kernel traces and counters)."""
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=R, height=R)
+    cfg = scenes.nrc_config(sc)
+    W0, grid0 = scenes.nrc_init(cfg, seed=16)
+    gs = drt.Scene(sc)
+    tex = [torch.from_numpy(sc.textures[0]).cuda()]
+    cache = drt.NrcCache(cfg, W0, grid0, lr=1e-2)
+    for f in range(frames):
+        cache.train_frame(gs, tex, None, sc.cameras, seed=1000 + f)
+    work = drt.cached_work(R * R * spp, "cuda")
+    img = torch.empty((1, R, R, 3), dtype=torch.float32, device="cuda")
+    out = {}
+    for name, fn in (("cache", lambda k: cache.render(gs, tex, None, sc.cameras, spp, seed=7 + k, out=img,
+                                                      work=work)),
+                     ("plain", lambda k: drt.render_forward(gs, tex, None, sc.cameras, spp, 6, 3,
+                                                            seed=7 + k, out=img))):
+        fn(0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(reps):
+            fn(k + 1)
+        b.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round(a.elapsed_time(b) / reps, 3)
+    out["queries"] = int(work[2].item())
+    out["workload"] = f"cornell-box, random 64^2 texture, {R}^2, {spp} spp, D6 RR3, cache at v3"
+    return out
 
 
 def at_target_rmse(rows, rmse_key, ms_key, train_ms):
