@@ -554,13 +554,13 @@ drt_status drt_nrc_train_frame(const drt_scene* scene, const drt_params* params,
 
 /* Entries of the int32 query scratch of the cached calls for `capacity`
  * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
- * parameter references [capacity][2] | bin histogram [4096]; 0 for
+ * parameter references [capacity][2] | bin histogram [32768]; 0 for
  * capacity < 0 or > 2^40, which the cached calls reject. */
 int64_t drt_nrc_query_ints(int64_t capacity);
 
 /* Primal render with the cache: image = (1/spp) sum over samples of the
  * path radiance up to the record vertex plus beta * max(C, 0) there.  The
- * queries are sorted by a 16^3 Morton cell of their position before the
+ * queries are sorted by a 32^3 Morton cell of their position before the
  * network answers them (hash-table gathers of nearby queries share cache
  * lines).  Scratch (device, overwritten): queries float [capacity][16],
  * query_ints int32 [drt_nrc_query_ints(capacity)], query_count int32 [1];

@@ -177,9 +177,12 @@ __host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int ro
   q[1] = (tex & 0xff) | ((rough_slot + 1) << 8);
 }
 
-// Spatial binning of cache queries: 16 cells per axis of the cache's box,
-// Morton order (12 bits), so that bin-sorted queries gather nearby table entries.
-constexpr int kQueryBinBits = 4;
+// Spatial binning of cache queries: 32 cells per axis of the cache's box,
+// Morton order (15 bits), so that bin-sorted queries gather nearby table
+// entries (16 cells per axis measured 1.3 ms slower on a 40M-query
+// inference at 1024^2, 64 spp; 32^3 bins are as many as one workgroup's LDS
+// histogram holds).
+constexpr int kQueryBinBits = 5;
 constexpr int kQueryBins = 1 << (3 * kQueryBinBits);
 __host__ __device__ inline uint32_t query_bin(float x, float y, float z, const float lo[3],
                                               const float inv_ext[3]) {

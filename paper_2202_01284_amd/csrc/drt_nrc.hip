@@ -452,9 +452,14 @@ __global__ __launch_bounds__(kBlockN) void k_query_scatter(BinSrc src, uint32_t*
 static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hipStream_t st) {
   hipError_t e = launch_zero(hist, kQueryBins, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_query_hist, dim3(kSortBlocks), dim3(kBlockN), 0, st, src, hist);
+  // up to kSortBlocks workgroups, each with at least 4096 queries: every
+  // workgroup clears and flushes a whole LDS histogram, which a small sort
+  // (a training frame's records) should not pay 256 times
+  const int64_t want = (src.capacity + 4095) / 4096;
+  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > kSortBlocks ? kSortBlocks : want));
+  hipLaunchKernelGGL(k_query_hist, dim3(blocks), dim3(kBlockN), 0, st, src, hist);
   hipLaunchKernelGGL(k_query_scan, dim3(1), dim3(1024), 0, st, hist);
-  hipLaunchKernelGGL(k_query_scatter, dim3(kSortBlocks), dim3(kBlockN), 0, st, src, hist, order);
+  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kBlockN), 0, st, src, hist, order);
   return hipGetLastError();
 }
 

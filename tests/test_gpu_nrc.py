@@ -353,7 +353,7 @@ def test_cached_render_vs_oracle():
 
 def test_query_sort_is_a_bin_ordered_permutation():
     """After a cached render the int scratch holds, per query, its spatial bin
-    (16^3 Morton cell of the cache box) and the bin-sorted order: a
+    (32^3 Morton cell of the cache box) and the bin-sorted order: a
     permutation of the query slots with non-decreasing bins."""
     drt = _drt()
     sc = scenes.cornell(texture=scenes.random_texture(64), width=96, height=80)
@@ -373,12 +373,12 @@ def test_query_sort_is_a_bin_ordered_permutation():
     bins = ints[2 * cap:2 * cap + n].view(np.uint32)
     np.testing.assert_array_equal(np.sort(order), np.arange(n))
     assert np.all(np.diff(bins[order].astype(np.int64)) >= 0)
-    # bins agree with the positions: Morton code of the 16^3 cell
+    # bins agree with the positions: Morton code of the 32^3 cell
     lo, hi = np.array(cfg["bbox_lo"], np.float32), np.array(cfg["bbox_hi"], np.float32)
     inv = (1.0 / (hi.astype(np.float64) - lo)).astype(np.float32)
-    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(16)).astype(np.int64), 0, 15)
+    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(32)).astype(np.int64), 0, 31)
     m = np.zeros(n, np.int64)
-    for b in range(4):
+    for b in range(5):
         for a in range(3):
             m |= ((c[:, a] >> b) & 1) << (3 * b + a)
     agree = (m == bins).mean()
