@@ -365,8 +365,13 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float
 // LDS histograms added to hist; one-block exclusive scan of hist; per-block
 // ranges reserved in the scanned cursors and filled through LDS atomics.  The
 // order inside a bin is arbitrary.  Blocks take the same grid-stride subsets
-// in the first and last launch.
+// in the first and last launch.  The 128 KB LDS histogram allows one block
+// per CU, so the histogram and scatter blocks have 1024 threads (16 waves)
+// and each thread requests kSortUnroll bins before it updates any: the
+// passes are bound by the latency of those reads.
 constexpr int kSortBlocks = 256;
+constexpr int kSortThreads = 1024;
+constexpr int kSortUnroll = 4;
 
 // What is sorted: cache queries with precomputed bins (qbin, first *count
 // of capacity), or training records binned from their positions (valid ones
@@ -391,17 +396,34 @@ DEV bool bin_of(const BinSrc& b, int64_t i, uint32_t& bin) {
   return true;
 }
 
-__global__ __launch_bounds__(kBlockN) void k_query_hist(BinSrc src, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kQueryBins];
-  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN) h[i] = 0;
-  __syncthreads();
-  const int64_t n = bin_n(src);
-  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlockN) {
-    uint32_t b;
-    if (bin_of(src, i, b)) atomicAdd(&h[b], 1u);
+// Items of one block (same in the histogram and the scatter pass): rounds
+// of kSortThreads x kSortUnroll consecutive items, the block's rounds
+// gridDim.x rounds apart; fn(bin) per valid item, the bins of a thread's
+// kSortUnroll items read before any is used.
+template <class F>
+DEV void for_block_bins(const BinSrc& src, int64_t n, F fn) {
+  constexpr int64_t kRound = (int64_t)kSortThreads * kSortUnroll;
+  for (int64_t r = (int64_t)blockIdx.x * kRound; r < n; r += (int64_t)gridDim.x * kRound) {
+    uint32_t b[kSortUnroll];
+    bool ok[kSortUnroll];
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      const int64_t i = r + (int64_t)u * kSortThreads + threadIdx.x;
+      ok[u] = i < n && bin_of(src, i, b[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u)
+      if (ok[u]) fn(b[u], r + (int64_t)u * kSortThreads + threadIdx.x);
   }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_query_hist(BinSrc src, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kQueryBins];
+  for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN)
+  for_block_bins(src, bin_n(src), [&](uint32_t b, int64_t) { atomicAdd(&h[b], 1u); });
+  __syncthreads();
+  for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads)
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
@@ -428,25 +450,18 @@ __global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist
   }
 }
 
-__global__ __launch_bounds__(kBlockN) void k_query_scatter(BinSrc src, uint32_t* __restrict__ cursor,
-                                                          int* __restrict__ order) {
+__global__ __launch_bounds__(kSortThreads) void k_query_scatter(BinSrc src, uint32_t* __restrict__ cursor,
+                                                               int* __restrict__ order) {
   __shared__ uint32_t h[kQueryBins];
-  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN) h[i] = 0;
+  for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
   const int64_t n = bin_n(src);
-  const int64_t stride = (int64_t)gridDim.x * kBlockN;
-  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += stride) {
-    uint32_t b;
-    if (bin_of(src, i, b)) atomicAdd(&h[b], 1u);
-  }
+  for_block_bins(src, n, [&](uint32_t b, int64_t) { atomicAdd(&h[b], 1u); });
   __syncthreads();
-  for (int i = threadIdx.x; i < kQueryBins; i += kBlockN)
+  for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads)
     if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * kBlockN + threadIdx.x; i < n; i += stride) {
-    uint32_t b;
-    if (bin_of(src, i, b)) order[atomicAdd(&h[b], 1u)] = (int)i;
-  }
+  for_block_bins(src, n, [&](uint32_t b, int64_t i) { order[atomicAdd(&h[b], 1u)] = (int)i; });
 }
 
 static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hipStream_t st) {
@@ -457,9 +472,9 @@ static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hip
   // (a training frame's records) should not pay 256 times
   const int64_t want = (src.capacity + 4095) / 4096;
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > kSortBlocks ? kSortBlocks : want));
-  hipLaunchKernelGGL(k_query_hist, dim3(blocks), dim3(kBlockN), 0, st, src, hist);
+  hipLaunchKernelGGL(k_query_hist, dim3(blocks), dim3(kSortThreads), 0, st, src, hist);
   hipLaunchKernelGGL(k_query_scan, dim3(1), dim3(1024), 0, st, hist);
-  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kBlockN), 0, st, src, hist, order);
+  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, order);
   return hipGetLastError();
 }
 
