@@ -118,22 +118,29 @@ def main():
                      device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     hits = drt.adjoint_hit_records(cams, SPP, D)
-    ev = []
+    ev, step_ev = [], []
 
     def step(k, timed, records=True):
+        # timed steps carry four HIP events (start, after the loss, after the
+        # adjoint, end) on the launch stream: per-step parts and medians
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if timed else None
+        if timed:
+            e[0].record()
         drt.render_forward(gs, [tex], rough, cams, SPP, D, seed=2 * k + 1, out=img)
         drt.loss_l2(img, target, adj=adj)
         if timed:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
+            e[1].record()
         drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * k + 2,
                            grad_textures=[gtex], grad_roughness=grough,
                            hit_records=hits if records else None)
         if timed:
-            e1.record()
-            ev.append((e0, e1))
+            e[2].record()
+            ev.append((e[1], e[2]))
         drt.adam_step(tex, gtex, m_t, v_t, k + 1, lr=1e-2, lo=0.0, hi=1.0, zero_grad=True)
         drt.adam_step(rough, grough, m_r, v_r, k + 1, lr=1e-2, lo=0.01, hi=1.0, zero_grad=True)
+        if timed:
+            e[3].record()
+            step_ev.append(e)
 
     for k in range(args.warmup):
         step(k, False)
@@ -147,6 +154,9 @@ def main():
     samples = R * R * SPP
     value = samples / (ms * 1e-3) / 1e6
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    med = lambda i, j: round(float(np.median([e[i].elapsed_time(e[j]) for e in step_ev])), 3)  # noqa: E731
+    step_parts = {"step_median": med(0, 3), "primal_and_loss_median": med(0, 1),
+                  "adjoint_median": med(1, 2), "adam_median": med(2, 3)}
     # the same steps with the replay tracing its rays again (no records)
     k0 = args.warmup + args.steps
     step(k0, False, records=False)
@@ -251,6 +261,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 3),
+        "step_ms_hip_events": step_parts,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
