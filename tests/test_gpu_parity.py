@@ -213,6 +213,9 @@ FWD_CASES = {
     # odd spp: the primal's two sample halves are 2 + 3 samples
     "cornell_spp5": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=40,
                                             height=24), dict(spp=5, max_depth=3)),
+    # long paths: up to 48 vertices, no roulette (paths end by escaping the open front)
+    "cornell_deep48": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=16,
+                                              height=16), dict(spp=2, max_depth=48)),
 }
 
 
@@ -261,6 +264,9 @@ ADJ_CASES = {
     # three ranges of one sample each, two scattering bounces past the first
     "cornell_spp3_d4": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64),
                                                width=32, height=20), dict(spp=3, max_depth=4)),
+    # long paths (up to 48 vertices, 48 records per lane and sample)
+    "cornell_deep48": (lambda: scenes.cornell(conductor=True, texture=scenes.random_texture(64),
+                                              width=16, height=16), dict(spp=2, max_depth=48)),
 }
 
 
