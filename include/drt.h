@@ -553,16 +553,18 @@ drt_status drt_nrc_train_frame(const drt_scene* scene, const drt_params* params,
                                const drt_nrc_state* state, void* hip_stream);
 
 /* Entries of the int32 query scratch of the cached calls for `capacity`
- * queries: ids [capacity] | order [capacity] | spatial bins [capacity] |
- * parameter references [capacity][2] | bin histogram [32768]; 0 for
- * capacity < 0 or > 2^40, which the cached calls reject. */
+ * queries: ids [capacity] | order [capacity] | spatial keys [capacity] |
+ * parameter references [capacity][2] | one padding entry if capacity is
+ * odd | sort pairs [capacity][2] | bin histogram [32768]; 0 for
+ * capacity < 0 or > 2^40, which the cached calls reject.  The scratch must
+ * be 8-byte aligned (the calls reject it otherwise). */
 int64_t drt_nrc_query_ints(int64_t capacity);
 
 /* Primal render with the cache: image = (1/spp) sum over samples of the
  * path radiance up to the record vertex plus beta * max(C, 0) there.  The
- * queries are sorted by a 32^3 Morton cell of their position before the
- * network answers them (hash-table gathers of nearby queries share cache
- * lines).  Scratch (device, overwritten): queries float [capacity][16],
+ * queries are sorted by the Morton code of their position's cell among
+ * 256^3 cells of the cache's box before the network answers them
+ * (hash-table gathers of nearby queries share cache lines).  Scratch (device, overwritten): queries float [capacity][16],
  * query_ints int32 [drt_nrc_query_ints(capacity)], query_count int32 [1];
  * capacity >= n_cams*W*H*spp <= INT32_MAX.  The cache terms are added with
  * float atomics (summation order not deterministic). */

@@ -600,9 +600,12 @@ drt_status check_params(const drt_scene* s, const drt_params* p, const drt_camer
   return DRT_OK;
 }
 
-// Query buffers of the cached calls: the int32 scratch holds ids | order |
-// bins | parameter references (2 per query) | histogram (drt_nrc_query_ints).
-// The references are written only when io.qref is set.
+// Query buffers of the cached calls: the int32 scratch (8-byte aligned)
+// holds ids | order | spatial keys | parameter references (2 per query) |
+// one padding entry when the capacity is odd | sort pairs (2 per query,
+// 8-byte aligned) | histogram (drt_nrc_query_ints).  The references are
+// written only when io.qref is set.
+static int64_t query_pairs_offset(int64_t capacity) { return (5 * capacity + 1) & ~(int64_t)1; }
 static DNrcIO query_io(const DNrcNet& net, const drt_nrc_config* cfg, float* queries,
                        int32_t* ints, int32_t* count, int64_t capacity) {
   DNrcIO io = {};
@@ -619,12 +622,13 @@ static DNrcIO query_io(const DNrcNet& net, const drt_nrc_config* cfg, float* que
   return io;
 }
 
-// Sort the queries by spatial bin, then let the network answer them.
+// Sort the queries by spatial key, then let the network answer them.
 static hipError_t answer_queries(const DNrcNet& net, const float* weights, const DNrcIO& io,
                                  int64_t need, float scale, float* out, hipStream_t st) {
   int* order = io.qpix + io.capacity;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(io.qpix + 5 * io.capacity);
-  hipError_t e = launch_query_sort(io.qbin, io.count, need, hist, order, st);
+  int* pairs = io.qpix + query_pairs_offset(io.capacity);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(pairs + 2 * io.capacity);
+  hipError_t e = launch_query_sort(io.qbin, io.count, need, hist, pairs, order, st);
   if (e != hipSuccess) return e;
   return launch_nrc_infer(net, weights, io.rec, io.qpix, order, io.count, need, scale, out, st);
 }
@@ -1290,7 +1294,8 @@ drt_status drt_nrc_train_frame(const drt_scene* scene, const drt_params* params,
 }
 
 int64_t drt_nrc_query_ints(int64_t capacity) {
-  return capacity < 0 || capacity > ((int64_t)1 << 40) ? 0 : 5 * capacity + kQueryBins;
+  return capacity < 0 || capacity > ((int64_t)1 << 40) ? 0
+                                                       : query_pairs_offset(capacity) + 2 * capacity + kQueryBins;
 }
 
 drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* params,
@@ -1313,6 +1318,7 @@ drt_status drt_render_forward_cached(const drt_scene* scene, const drt_params* p
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
   if (drt_nrc_query_ints(capacity) == 0) return fail(DRT_EINVAL, "query capacity out of range");
+  if ((uintptr_t)query_ints & 7) return fail(DRT_EINVAL, "query_ints must be 8-byte aligned");
   hipStream_t stream = (hipStream_t)hip_stream;
   DNrcIO io = query_io(net, cfg, queries, query_ints, query_count, capacity);
   hipError_t e = launch_zero(query_count, 1, stream);
@@ -1354,6 +1360,7 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   if (capacity < need || need > INT32_MAX)
     return fail(DRT_EINVAL, "query capacity %lld < %lld samples", (long long)capacity, (long long)need);
   if (drt_nrc_query_ints(capacity) == 0) return fail(DRT_EINVAL, "query capacity out of range");
+  if ((uintptr_t)query_ints & 7) return fail(DRT_EINVAL, "query_ints must be 8-byte aligned");
   if (hit_records) {
     const int64_t hneed = drt_render_adjoint_cached_hit_bytes(n_cams, cams[0].width, cams[0].height,
                                                               opts->spp, opts->max_depth);

@@ -160,7 +160,7 @@ struct DNrcIO {
   int64_t capacity; // queries the buffer holds
   int K;            // record vertex index
   float* lsamp;     // per-sample radiance [n_samples][3] (cached adjoint), else null
-  uint32_t* qbin;   // queries: spatial bin of each query (null: not binned)
+  uint32_t* qbin;   // queries: spatial key of each query (null: not sorted)
   int* qref;        // queries: [2] per query, the parameters its inputs were read
                     // from (query_ref_put), or null (not recorded)
   float* trec;      // self-training: records [n_paths * (K - 1)][NRC_REC]
@@ -177,22 +177,27 @@ __host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int ro
   q[1] = (tex & 0xff) | ((rough_slot + 1) << 8);
 }
 
-// Spatial binning of cache queries: 32 cells per axis of the cache's box,
-// Morton order (15 bits), so that bin-sorted queries gather nearby table
-// entries (16 cells per axis measured 1.3 ms slower on a 40M-query
-// inference at 1024^2, 64 spp; 32^3 bins are as many as one workgroup's LDS
-// histogram holds).
-constexpr int kQueryBinBits = 5;
+// Spatial key of cache queries: the Morton code (24 bits) of the query's
+// cell among 256 cells per axis of the cache's box, so that key-sorted
+// queries gather nearby table entries.  The sort takes two passes: a
+// counting sort by the top 15 bits (32^3 bins, as many as one workgroup's
+// LDS histogram holds), then each bin's queries by the low 9 bits (its 8^3
+// sub-cells).  Measured on a 40M-query inference at 1024^2, 64 spp: 16^3
+// bins 14.5 ms, 32^3 12.6 ms, 256^3 cells 8.1 ms (1024^3: 7.2 ms).
+constexpr int kQueryKeyBits = 8;                                    // per axis
+constexpr int kQueryBinBits = 5;                                    // first pass, per axis
 constexpr int kQueryBins = 1 << (3 * kQueryBinBits);
-__host__ __device__ inline uint32_t query_bin(float x, float y, float z, const float lo[3],
+constexpr int kQuerySubBits = 3 * (kQueryKeyBits - kQueryBinBits);  // second pass
+constexpr int kQuerySubs = 1 << kQuerySubBits;
+__host__ __device__ inline uint32_t query_key(float x, float y, float z, const float lo[3],
                                               const float inv_ext[3]) {
   const float v[3] = {x, y, z};
   uint32_t m = 0;
   for (int a = 0; a < 3; ++a) {
-    float t = (v[a] - lo[a]) * inv_ext[a] * (float)(1 << kQueryBinBits);
+    float t = (v[a] - lo[a]) * inv_ext[a] * (float)(1 << kQueryKeyBits);
     int c = (int)t;
-    c = c < 0 ? 0 : (c > (1 << kQueryBinBits) - 1 ? (1 << kQueryBinBits) - 1 : c);
-    for (int b = 0; b < kQueryBinBits; ++b) m |= (uint32_t)((c >> b) & 1) << (3 * b + a);
+    c = c < 0 ? 0 : (c > (1 << kQueryKeyBits) - 1 ? (1 << kQueryKeyBits) - 1 : c);
+    for (int b = 0; b < kQueryKeyBits; ++b) m |= (uint32_t)((c >> b) & 1) << (3 * b + a);
   }
   return m;
 }
@@ -266,14 +271,15 @@ hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, fl
                              hipStream_t st);
 // Counting sort of the queries by spatial bin: order[] = query indices, bin
 // by bin.  hist: kQueryBins words of scratch.
+// pairs: 8-byte aligned scratch of capacity 8-byte entries
 hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t capacity,
-                             uint32_t* hist, int* order, hipStream_t st);
+                             uint32_t* hist, void* pairs, int* order, hipStream_t st);
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
                             const int* order, const int* count, int64_t capacity, float inv_spp,
                             float* image, hipStream_t st);
 // Gradient of the cache term through the network's albedo and roughness
 // inputs: queries q with sample ids qsample (pixel = id / spp), references
-// qref, in the bin order of launch_query_sort; adj: image adjoint.
+// qref, in the key order of launch_query_sort; adj: image adjoint.
 hipError_t launch_nrc_input_grad(const DNrcNet& net, const float* W, const float* q,
                                  const int* qsample, const int* qref, const int* order,
                                  const int* count, int64_t capacity, int spp, const float* adj,

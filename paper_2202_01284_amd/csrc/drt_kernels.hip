@@ -293,7 +293,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
                 if (slot < io.capacity) {
                   rec = io.rec + (size_t)NRC_REC * slot;
                   io.qpix[slot] = MODE == MODE_CACHED ? (int)pix : (int)glo;
-                  if (io.qbin) io.qbin[slot] = query_bin(p.x, p.y, p.z, io.lo, io.inv_ext);
+                  if (io.qbin) io.qbin[slot] = query_key(p.x, p.y, p.z, io.lo, io.inv_ext);
                   if (io.qref) {
                     const bool tex_in = vtex >= 0 && type != DRT_BSDF_CONDUCTOR &&
                                         type != DRT_BSDF_DIELECTRIC;

@@ -361,20 +361,26 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float
   }
 }
 
-// Counting sort of cache queries by spatial bin (three launches): per-block
-// LDS histograms added to hist; one-block exclusive scan of hist; per-block
-// ranges reserved in the scanned cursors and filled through LDS atomics.  The
-// order inside a bin is arbitrary.  Blocks take the same grid-stride subsets
-// in the first and last launch.  The 128 KB LDS histogram allows one block
-// per CU, so the histogram and scatter blocks have 1024 threads (16 waves)
-// and each thread requests kSortUnroll bins before it updates any: the
-// passes are bound by the latency of those reads.
+// Sort of cache queries by spatial key (four launches).  Pass 1, a counting
+// sort by the key's top bits (its 32^3 bin): per-block LDS histograms added
+// to hist; one-block exclusive scan of hist; per-block ranges reserved in
+// the scanned cursors and filled through LDS atomics with (sub-key, item)
+// pairs.  Blocks take the same grid-stride subsets in the first and last of
+// these launches.  The 128 KB LDS histogram allows one block per CU, so the
+// histogram and scatter blocks have 1024 threads (16 waves) and each thread
+// requests kSortUnroll keys before it updates any: the passes are bound by
+// the latency of those reads.  After the scatter each cursor holds the end
+// of its bin.  Pass 2: each bin's pairs counting-sorted by the sub-key (the
+// bin's 8^3 sub-cells) in LDS, one bin per workgroup at a time, into the
+// final order.  The order among equal keys is arbitrary.
 constexpr int kSortBlocks = 256;
 constexpr int kSortThreads = 1024;
 constexpr int kSortUnroll = 4;
+constexpr int kRefineBlocks = 512;
+constexpr int kRefineThreads = 1024;
 
-// What is sorted: cache queries with precomputed bins (qbin, first *count
-// of capacity), or training records binned from their positions (valid ones
+// What is sorted: cache queries with precomputed keys (qbin, first *count
+// of capacity), or training records keyed by their positions (valid ones
 // of n, qbin null).
 struct BinSrc {
   const uint32_t* qbin;
@@ -385,35 +391,35 @@ struct BinSrc {
   float lo[3], inv_ext[3];
 };
 DEV int64_t bin_n(const BinSrc& b) { return b.count ? min((int64_t)*b.count, b.capacity) : b.capacity; }
-DEV bool bin_of(const BinSrc& b, int64_t i, uint32_t& bin) {
+DEV bool key_of(const BinSrc& b, int64_t i, uint32_t& key) {
   if (b.qbin) {
-    bin = b.qbin[i];
+    key = b.qbin[i];
     return true;
   }
   if (!b.valid[i]) return false;
   const float* r = b.rec + i * NRC_REC;
-  bin = query_bin(r[0], r[1], r[2], b.lo, b.inv_ext);
+  key = query_key(r[0], r[1], r[2], b.lo, b.inv_ext);
   return true;
 }
 
 // Items of one block (same in the histogram and the scatter pass): rounds
 // of kSortThreads x kSortUnroll consecutive items, the block's rounds
-// gridDim.x rounds apart; fn(bin) per valid item, the bins of a thread's
-// kSortUnroll items read before any is used.
+// gridDim.x rounds apart; fn(key, item) per valid item, the keys of a
+// thread's kSortUnroll items read before any is used.
 template <class F>
-DEV void for_block_bins(const BinSrc& src, int64_t n, F fn) {
+DEV void for_block_keys(const BinSrc& src, int64_t n, F fn) {
   constexpr int64_t kRound = (int64_t)kSortThreads * kSortUnroll;
   for (int64_t r = (int64_t)blockIdx.x * kRound; r < n; r += (int64_t)gridDim.x * kRound) {
-    uint32_t b[kSortUnroll];
+    uint32_t k[kSortUnroll];
     bool ok[kSortUnroll];
 #pragma unroll
     for (int u = 0; u < kSortUnroll; ++u) {
       const int64_t i = r + (int64_t)u * kSortThreads + threadIdx.x;
-      ok[u] = i < n && bin_of(src, i, b[u]);
+      ok[u] = i < n && key_of(src, i, k[u]);
     }
 #pragma unroll
     for (int u = 0; u < kSortUnroll; ++u)
-      if (ok[u]) fn(b[u], r + (int64_t)u * kSortThreads + threadIdx.x);
+      if (ok[u]) fn(k[u], r + (int64_t)u * kSortThreads + threadIdx.x);
   }
 }
 
@@ -421,7 +427,7 @@ __global__ __launch_bounds__(kSortThreads) void k_query_hist(BinSrc src, uint32_
   __shared__ uint32_t h[kQueryBins];
   for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
-  for_block_bins(src, bin_n(src), [&](uint32_t b, int64_t) { atomicAdd(&h[b], 1u); });
+  for_block_keys(src, bin_n(src), [&](uint32_t k, int64_t) { atomicAdd(&h[k >> kQuerySubBits], 1u); });
   __syncthreads();
   for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads)
     if (h[i]) atomicAdd(&hist[i], h[i]);
@@ -450,21 +456,76 @@ __global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist
   }
 }
 
+// pairs[pos] = (sub-key, item) at the item's place in its bin
 __global__ __launch_bounds__(kSortThreads) void k_query_scatter(BinSrc src, uint32_t* __restrict__ cursor,
-                                                               int* __restrict__ order) {
+                                                               uint2* __restrict__ pairs) {
   __shared__ uint32_t h[kQueryBins];
   for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
   const int64_t n = bin_n(src);
-  for_block_bins(src, n, [&](uint32_t b, int64_t) { atomicAdd(&h[b], 1u); });
+  for_block_keys(src, n, [&](uint32_t k, int64_t) { atomicAdd(&h[k >> kQuerySubBits], 1u); });
   __syncthreads();
   for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads)
     if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
   __syncthreads();
-  for_block_bins(src, n, [&](uint32_t b, int64_t i) { order[atomicAdd(&h[b], 1u)] = (int)i; });
+  for_block_keys(src, n, [&](uint32_t k, int64_t i) {
+    pairs[atomicAdd(&h[k >> kQuerySubBits], 1u)] = make_uint2(k & (kQuerySubs - 1), (uint32_t)i);
+  });
 }
 
-static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hipStream_t st) {
+// The pairs [s, e) of one bin over the block's threads, kSortUnroll reads
+// requested before any is used (an out-of-range thread reads pair s).
+template <class F>
+DEV void for_bin_pairs(const uint2* __restrict__ pairs, uint32_t s, uint32_t e, F fn) {
+  for (uint32_t i0 = s + threadIdx.x; i0 < e; i0 += kSortUnroll * kRefineThreads) {
+    uint2 p[kSortUnroll];
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      const uint32_t i = i0 + u * kRefineThreads;
+      p[u] = pairs[i < e ? i : s];
+    }
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u)
+      if (i0 + u * kRefineThreads < e) fn(p[u]);
+  }
+}
+
+// Pass 2: bin b holds pairs [end[b-1], end[b]) (end[-1] = 0); its items are
+// written to order in sub-key order.
+__global__ __launch_bounds__(kRefineThreads) void k_query_refine(const uint2* __restrict__ pairs,
+                                                                const uint32_t* __restrict__ end,
+                                                                int* __restrict__ order) {
+  // scan: thread t < kQuerySubs owns sub-key t
+  static_assert(kQuerySubs <= kRefineThreads, "scan layout");
+  __shared__ uint32_t h[kQuerySubs];
+  __shared__ uint32_t part[kQuerySubs];
+  const int t = threadIdx.x;
+  for (int b = blockIdx.x; b < kQueryBins; b += gridDim.x) {
+    const uint32_t s = b ? end[b - 1] : 0u, e = end[b];
+    if (s >= e) continue;  // the same for the whole block
+    if (t < kQuerySubs) h[t] = 0;
+    __syncthreads();
+    for_bin_pairs(pairs, s, e, [&](uint2 p) { atomicAdd(&h[p.x], 1u); });
+    __syncthreads();
+    const uint32_t c = t < kQuerySubs ? h[t] : 0u;
+    if (t < kQuerySubs) part[t] = c;
+    __syncthreads();
+    for (int off = 1; off < kQuerySubs; off <<= 1) {
+      const uint32_t v = (t < kQuerySubs && t >= off) ? part[t - off] : 0u;
+      __syncthreads();
+      if (t < kQuerySubs) part[t] += v;
+      __syncthreads();
+    }
+    if (t < kQuerySubs) h[t] = s + part[t] - c;  // exclusive
+    __syncthreads();
+    for_bin_pairs(pairs, s, e, [&](uint2 p) { order[atomicAdd(&h[p.x], 1u)] = (int)p.y; });
+    __syncthreads();
+  }
+}
+
+// hist: kQueryBins counters; pairs: 8-byte aligned, as many as items.
+static hipError_t sort_by_key(const BinSrc& src, uint32_t* hist, uint2* pairs, int* order,
+                              hipStream_t st) {
   hipError_t e = launch_zero(hist, kQueryBins, st);
   if (e != hipSuccess) return e;
   // up to kSortBlocks workgroups, each with at least 4096 queries: every
@@ -474,7 +535,10 @@ static hipError_t sort_by_bin(const BinSrc& src, uint32_t* hist, int* order, hip
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > kSortBlocks ? kSortBlocks : want));
   hipLaunchKernelGGL(k_query_hist, dim3(blocks), dim3(kSortThreads), 0, st, src, hist);
   hipLaunchKernelGGL(k_query_scan, dim3(1), dim3(1024), 0, st, hist);
-  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, order);
+  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, pairs);
+  const int64_t rb = (src.capacity + 4095) / 4096;
+  const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > kRefineBlocks ? kRefineBlocks : rb));
+  hipLaunchKernelGGL(k_query_refine, dim3(rblocks), dim3(kRefineThreads), 0, st, pairs, hist, order);
   return hipGetLastError();
 }
 
@@ -976,12 +1040,12 @@ hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, fl
   return hipGetLastError();
 }
 hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t capacity,
-                             uint32_t* hist, int* order, hipStream_t st) {
+                             uint32_t* hist, void* pairs, int* order, hipStream_t st) {
   BinSrc src = {};
   src.qbin = qbin;
   src.count = count;
   src.capacity = capacity;
-  return sort_by_bin(src, hist, order, st);
+  return sort_by_key(src, hist, static_cast<uint2*>(pairs), order, st);
 }
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,
                             const int* order, const int* count, int64_t capacity, float inv_spp,
@@ -1000,12 +1064,13 @@ hipError_t launch_nrc_input_grad(const DNrcNet& net, const float* W, const float
   return hipGetLastError();
 }
 // workspace: operand chunks of every record tile | phase-2 partials |
-// sorted record order [n] | bin histogram
+// sort pairs [n] (8 bytes each) | sorted record order [n] | bin histogram
 static int64_t dw_blocks(int64_t n) { return ((n + 15) / 16 + kDwBlockTiles - 1) / kDwBlockTiles; }
 static int64_t ws_chunk_bytes(int64_t n) { return ((n + 15) / 16) * kChunks * 64 * 8; }
 static int64_t ws_part_bytes(int64_t n) { return dw_blocks(n) * (kW4 + 3 * 64) * 4; }
+static int64_t ws_pairs_offset(int64_t n) { return (ws_chunk_bytes(n) + ws_part_bytes(n) + 7) & ~(int64_t)7; }
 int64_t nrc_train_workspace_bytes(int64_t n) {
-  return ws_chunk_bytes(n) + ws_part_bytes(n) + n * 4 + kQueryBins * 4;
+  return ws_pairs_offset(n) + n * 8 + n * 4 + kQueryBins * 4;
 }
 
 hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, int64_t n, void* ws,
@@ -1032,7 +1097,8 @@ hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec
   if (n_tiles == 0) return hipSuccess;
   char* base = static_cast<char*>(ws);
   float* part = reinterpret_cast<float*>(base + ws_chunk_bytes(n));
-  int* order = reinterpret_cast<int*>(base + ws_chunk_bytes(n) + ws_part_bytes(n));
+  uint2* pairs = reinterpret_cast<uint2*>(base + ws_pairs_offset(n));
+  int* order = reinterpret_cast<int*>(pairs + n);
   uint32_t* hist = reinterpret_cast<uint32_t*>(order + n);
   BinSrc src = {};
   src.capacity = n;
@@ -1042,7 +1108,7 @@ hipError_t launch_nrc_train(const DNrcNet& net, const float* W, const float* rec
     src.lo[a] = net.lo[a];
     src.inv_ext[a] = net.inv_ext[a];
   }
-  hipError_t e = sort_by_bin(src, hist, order, st);
+  hipError_t e = sort_by_key(src, hist, pairs, order, st);
   if (e != hipSuccess) return e;
   // 2 workgroups per CU fit in registers; waves loop over tiles
   hipLaunchKernelGGL(k_nrc_train_fb, dim3(grid_for(n, 1024)), dim3(kBlockN), 0, st, net, W, rec,

@@ -351,10 +351,13 @@ def test_cached_render_vs_oracle():
     check_image(img.cpu().numpy(), ref, "cached render", amb)
 
 
-def test_query_sort_is_a_bin_ordered_permutation():
-    """After a cached render the int scratch holds, per query, its spatial bin
-    (32^3 Morton cell of the cache box) and the bin-sorted order: a
-    permutation of the query slots with non-decreasing bins."""
+def test_query_sort_is_a_key_ordered_permutation():
+    """After a cached render the int scratch holds, per query, its spatial key
+    (Morton code of its cell among 256^3 cells of the cache box) and the
+    key-sorted order: a permutation of the query slots with non-decreasing
+    keys -- the two-pass sort (32^3 bins, then 8^3 sub-cells per bin)
+    orders by the whole key.  A scratch that is not 8-byte aligned is
+    refused."""
     drt = _drt()
     sc = scenes.cornell(texture=scenes.random_texture(64), width=96, height=80)
     cfg = scenes.nrc_config(sc)
@@ -362,28 +365,33 @@ def test_query_sort_is_a_bin_ordered_permutation():
     gs = drt.Scene(sc)
     tex = [torch.from_numpy(sc.textures[0]).cuda()]
     spp = 3
-    cap = 96 * 80 * spp + 17
+    cap = 96 * 80 * spp + 17          # odd: the sort pairs follow a padding entry
     work = drt.cached_work(cap)
-    drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, torch.from_numpy(W).cuda(),
-                              torch.from_numpy(grid.reshape(-1)).cuda(), spp=spp, seed=5, work=work)
+    Wg, gg = torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda()
+    drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wg, gg, spp=spp, seed=5, work=work)
     q, ints, count = (t.cpu().numpy() for t in work)
     n = int(count[0])
     assert 0 < n <= 96 * 80 * spp
     order = ints[cap:cap + n]
-    bins = ints[2 * cap:2 * cap + n].view(np.uint32)
+    keys = ints[2 * cap:2 * cap + n].view(np.uint32)
     np.testing.assert_array_equal(np.sort(order), np.arange(n))
-    assert np.all(np.diff(bins[order].astype(np.int64)) >= 0)
-    # bins agree with the positions: Morton code of the 32^3 cell
+    assert np.all(np.diff(keys[order].astype(np.int64)) >= 0)
+    # keys agree with the positions: Morton code of the 256^3 cell
     lo, hi = np.array(cfg["bbox_lo"], np.float32), np.array(cfg["bbox_hi"], np.float32)
     inv = (1.0 / (hi.astype(np.float64) - lo)).astype(np.float32)
-    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(32)).astype(np.int64), 0, 31)
+    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(256)).astype(np.int64), 0, 255)
     m = np.zeros(n, np.int64)
-    for b in range(5):
+    for b in range(8):
         for a in range(3):
             m |= ((c[:, a] >> b) & 1) << (3 * b + a)
-    agree = (m == bins).mean()
-    print("queries", n, "bins used", len(np.unique(bins)), "bin agreement", agree, flush=True)
+    agree = (m == keys).mean()
+    print("queries", n, "keys used", len(np.unique(keys)), "bins used", len(np.unique(keys >> 9)),
+          "key agreement", agree, flush=True)
     assert agree >= 0.999          # float32 rounding at cell faces may differ
+    big = torch.empty(int(drt.lib.drt_nrc_query_ints(cap)) + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(drt.DrtError):
+        drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wg, gg, spp=spp, seed=5,
+                                  work=(work[0], big[1:], work[2]))
 
 
 def _cached_adjoint_case(zero_network=False):

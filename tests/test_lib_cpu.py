@@ -228,7 +228,8 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     bad = drt.nrc_config(dict(cfg, log2_table=30))
     assert drt.lib.drt_nrc_train(ctypes.byref(bad), fake, fake, fake, fake, fake, n, fake, need,
                                  fake, fake, fake, None) != 0
-    assert drt.lib.drt_nrc_query_ints(10) == 5 * 10 + 32768
+    assert drt.lib.drt_nrc_query_ints(10) == 7 * 10 + 32768
+    assert drt.lib.drt_nrc_query_ints(11) == 7 * 11 + 1 + 32768  # pairs start 8-byte aligned
     assert drt.lib.drt_nrc_query_ints(-3) == 0
     # scenes packed on the host are rejected by every rendering entry point
     desc = drt.make_desc(sc)
