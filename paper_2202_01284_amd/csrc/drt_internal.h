@@ -181,8 +181,8 @@ __host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int ro
 // cell among 256 cells per axis of the cache's box, so that key-sorted
 // queries gather nearby table entries.  The sort takes two passes: a
 // counting sort by the top 15 bits (32^3 bins, as many as one workgroup's
-// LDS histogram holds), then each bin's queries by the low 9 bits (its 8^3
-// sub-cells).  Measured on a 40M-query inference at 1024^2, 64 spp: 16^3
+// LDS histogram holds), then, for sorts of 2^20 items or more, each bin's
+// queries by the low 9 bits (its 8^3 sub-cells).  Measured on a 40M-query inference at 1024^2, 64 spp: 16^3
 // bins 14.5 ms, 32^3 12.6 ms, 256^3 cells 8.1 ms (1024^3: 7.2 ms).
 constexpr int kQueryKeyBits = 8;                                    // per axis
 constexpr int kQueryBinBits = 5;                                    // first pass, per axis

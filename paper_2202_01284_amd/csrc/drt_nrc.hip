@@ -372,12 +372,14 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float
 // the latency of those reads.  After the scatter each cursor holds the end
 // of its bin.  Pass 2: each bin's pairs counting-sorted by the sub-key (the
 // bin's 8^3 sub-cells) in LDS, one bin per workgroup at a time, into the
-// final order.  The order among equal keys is arbitrary.
+// final order -- for sorts of at least kRefineMin items; smaller ones are
+// ordered by bin only.  The order among equal keys is arbitrary.
 constexpr int kSortBlocks = 256;
 constexpr int kSortThreads = 1024;
 constexpr int kSortUnroll = 4;
 constexpr int kRefineBlocks = 512;
 constexpr int kRefineThreads = 1024;
+constexpr int64_t kRefineMin = (int64_t)1 << 20;  // items
 
 // What is sorted: cache queries with precomputed keys (qbin, first *count
 // of capacity), or training records keyed by their positions (valid ones
@@ -456,9 +458,12 @@ __global__ __launch_bounds__(1024) void k_query_scan(uint32_t* __restrict__ hist
   }
 }
 
-// pairs[pos] = (sub-key, item) at the item's place in its bin
+// PAIRS: pairs[pos] = (sub-key, item) at the item's place in its bin (for
+// the second pass); else order[pos] = item (bin order only).
+template <bool PAIRS>
 __global__ __launch_bounds__(kSortThreads) void k_query_scatter(BinSrc src, uint32_t* __restrict__ cursor,
-                                                               uint2* __restrict__ pairs) {
+                                                               uint2* __restrict__ pairs,
+                                                               int* __restrict__ order) {
   __shared__ uint32_t h[kQueryBins];
   for (int i = threadIdx.x; i < kQueryBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
@@ -469,7 +474,11 @@ __global__ __launch_bounds__(kSortThreads) void k_query_scatter(BinSrc src, uint
     if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
   __syncthreads();
   for_block_keys(src, n, [&](uint32_t k, int64_t i) {
-    pairs[atomicAdd(&h[k >> kQuerySubBits], 1u)] = make_uint2(k & (kQuerySubs - 1), (uint32_t)i);
+    const uint32_t pos = atomicAdd(&h[k >> kQuerySubBits], 1u);
+    if (PAIRS)
+      pairs[pos] = make_uint2(k & (kQuerySubs - 1), (uint32_t)i);
+    else
+      order[pos] = (int)i;
   });
 }
 
@@ -535,10 +544,16 @@ static hipError_t sort_by_key(const BinSrc& src, uint32_t* hist, uint2* pairs, i
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > kSortBlocks ? kSortBlocks : want));
   hipLaunchKernelGGL(k_query_hist, dim3(blocks), dim3(kSortThreads), 0, st, src, hist);
   hipLaunchKernelGGL(k_query_scan, dim3(1), dim3(1024), 0, st, hist);
-  hipLaunchKernelGGL(k_query_scatter, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, pairs);
-  const int64_t rb = (src.capacity + 4095) / 4096;
-  const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > kRefineBlocks ? kRefineBlocks : rb));
-  hipLaunchKernelGGL(k_query_refine, dim3(rblocks), dim3(kRefineThreads), 0, st, pairs, hist, order);
+  if (src.capacity < kRefineMin) {
+    // a small sort (a training frame's records) stops at the bins: its few
+    // items per bin would not pay for the second pass's per-bin work
+    hipLaunchKernelGGL(k_query_scatter<false>, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, pairs,
+                       order);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_query_scatter<true>, dim3(blocks), dim3(kSortThreads), 0, st, src, hist, pairs,
+                     order);
+  hipLaunchKernelGGL(k_query_refine, dim3(kRefineBlocks), dim3(kRefineThreads), 0, st, pairs, hist, order);
   return hipGetLastError();
 }
 

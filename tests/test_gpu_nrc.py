@@ -351,31 +351,33 @@ def test_cached_render_vs_oracle():
     check_image(img.cpu().numpy(), ref, "cached render", amb)
 
 
-def test_query_sort_is_a_key_ordered_permutation():
+@pytest.mark.parametrize("size", ["small", "large"])
+def test_query_sort_is_a_key_ordered_permutation(size):
     """After a cached render the int scratch holds, per query, its spatial key
     (Morton code of its cell among 256^3 cells of the cache box) and the
-    key-sorted order: a permutation of the query slots with non-decreasing
-    keys -- the two-pass sort (32^3 bins, then 8^3 sub-cells per bin)
-    orders by the whole key.  A scratch that is not 8-byte aligned is
-    refused."""
+    sorted order: a permutation of the query slots.  A render of at least
+    2^20 samples is ordered by the whole key (32^3 bins, then 8^3 sub-cells
+    per bin), a smaller one by the bin (the key's top 15 bits).  A scratch
+    that is not 8-byte aligned is refused."""
     drt = _drt()
-    sc = scenes.cornell(texture=scenes.random_texture(64), width=96, height=80)
+    w, h, spp, extra = (96, 80, 3, 17) if size == "small" else (1024, 1024, 1, 0)
+    sc = scenes.cornell(texture=scenes.random_texture(64), width=w, height=h)
     cfg = scenes.nrc_config(sc)
     W, grid = scenes.nrc_init(cfg, seed=10)
     gs = drt.Scene(sc)
     tex = [torch.from_numpy(sc.textures[0]).cuda()]
-    spp = 3
-    cap = 96 * 80 * spp + 17          # odd: the sort pairs follow a padding entry
+    cap = w * h * spp + extra         # small: odd, the sort pairs follow a padding entry
     work = drt.cached_work(cap)
     Wg, gg = torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda()
     drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wg, gg, spp=spp, seed=5, work=work)
     q, ints, count = (t.cpu().numpy() for t in work)
     n = int(count[0])
-    assert 0 < n <= 96 * 80 * spp
+    assert 0 < n <= w * h * spp
     order = ints[cap:cap + n]
     keys = ints[2 * cap:2 * cap + n].view(np.uint32)
     np.testing.assert_array_equal(np.sort(order), np.arange(n))
-    assert np.all(np.diff(keys[order].astype(np.int64)) >= 0)
+    sorted_by = keys[order].astype(np.int64) if size == "large" else keys[order].astype(np.int64) >> 9
+    assert np.all(np.diff(sorted_by) >= 0)
     # keys agree with the positions: Morton code of the 256^3 cell
     lo, hi = np.array(cfg["bbox_lo"], np.float32), np.array(cfg["bbox_hi"], np.float32)
     inv = (1.0 / (hi.astype(np.float64) - lo)).astype(np.float32)
@@ -388,10 +390,11 @@ def test_query_sort_is_a_key_ordered_permutation():
     print("queries", n, "keys used", len(np.unique(keys)), "bins used", len(np.unique(keys >> 9)),
           "key agreement", agree, flush=True)
     assert agree >= 0.999          # float32 rounding at cell faces may differ
-    big = torch.empty(int(drt.lib.drt_nrc_query_ints(cap)) + 1, dtype=torch.int32, device="cuda")
-    with pytest.raises(drt.DrtError):
-        drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wg, gg, spp=spp, seed=5,
-                                  work=(work[0], big[1:], work[2]))
+    if size == "small":
+        big = torch.empty(int(drt.lib.drt_nrc_query_ints(cap)) + 1, dtype=torch.int32, device="cuda")
+        with pytest.raises(drt.DrtError):
+            drt.render_forward_cached(gs, tex, None, sc.cameras, cfg, Wg, gg, spp=spp, seed=5,
+                                      work=(work[0], big[1:], work[2]))
 
 
 def _cached_adjoint_case(zero_network=False):
