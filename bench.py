@@ -297,18 +297,48 @@ def simd_utilisation(st):
             "vertex_steps": f("lane_steps", "wave_steps"), "shading": f("vertices", "wave_shade")}
 
 
+def source_code_digest(paths):
+    """SHA-256 of C/C++/HIP sources with their comments removed and runs of
+    whitespace collapsed (string and character literals kept whole): it
+    changes when the code does, not when a comment does."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in paths:
+        text = open(os.path.join(ROOT, f), encoding="utf-8").read()
+        out, i, n = [], 0, len(text)
+        while i < n:
+            c = text[i]
+            if text.startswith("//", i):
+                j = text.find("\n", i)
+                i = n if j < 0 else j
+                out.append(" ")
+            elif text.startswith("/*", i):
+                j = text.find("*/", i + 2)
+                i = n if j < 0 else j + 2
+                out.append(" ")
+            elif c in "\"'":
+                j = i + 1
+                while j < n and text[j] != c:
+                    j += 2 if text[j] == "\\" else 1
+                out.append(text[i:j + 1])
+                i = j + 1
+            else:
+                out.append(c)
+                i += 1
+        h.update(" ".join("".join(out).split()).encode())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def counter_record(name):
     """A committed counter summary (profiles/<name>), or None when the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel code has changed since the counters were taken."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
-        h = hashlib.sha256()
-        for f in rec["sources"]:  # every file the kernel is compiled from, in order
-            h.update(open(os.path.join(ROOT, f), "rb").read())
+        digest = source_code_digest(rec["sources"])  # every file the kernel is compiled from
     except (OSError, ValueError, KeyError, TypeError):
         return None
-    if h.hexdigest() != rec.get("source_sha256"):
+    if digest != rec.get("source_code_sha256"):
         return None
     return rec
 

@@ -182,8 +182,9 @@ __host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int ro
 // queries gather nearby table entries.  The sort takes two passes: a
 // counting sort by the top 15 bits (32^3 bins, as many as one workgroup's
 // LDS histogram holds), then, for sorts of 2^20 items or more, each bin's
-// queries by the low 9 bits (its 8^3 sub-cells).  Measured on a 40M-query inference at 1024^2, 64 spp: 16^3
-// bins 14.5 ms, 32^3 12.6 ms, 256^3 cells 8.1 ms (1024^3: 7.2 ms).
+// queries by the low 9 bits (its 8^3 sub-cells).  Inference of 40M queries
+// (1024^2, 64 spp) measured by the order's cells: 32^3 12.6 ms, 64^3
+// 10.7 ms, 128^3 9.2 ms, 256^3 8.1 ms, 1024^3 7.2 ms; unsorted 26.4 ms.
 constexpr int kQueryKeyBits = 8;                                    // per axis
 constexpr int kQueryBinBits = 5;                                    // first pass, per axis
 constexpr int kQueryBins = 1 << (3 * kQueryBinBits);
