@@ -563,7 +563,7 @@ int64_t drt_nrc_query_ints(int64_t capacity);
 /* Primal render with the cache: image = (1/spp) sum over samples of the
  * path radiance up to the record vertex plus beta * max(C, 0) there.  The
  * queries are sorted by the Morton code of their position's cell among
- * 256^3 cells of the cache's box (by its 32^3 bin alone when capacity <
+ * 512^3 cells of the cache's box (by its 32^3 bin alone when capacity <
  * 2^20) before the network answers them (hash-table gathers of nearby
  * queries share cache lines).  Scratch (device, overwritten): queries float [capacity][16],
  * query_ints int32 [drt_nrc_query_ints(capacity)], query_count int32 [1];

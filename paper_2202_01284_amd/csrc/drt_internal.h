@@ -177,15 +177,16 @@ __host__ __device__ inline void query_ref_put(int* q, int texel, int tex, int ro
   q[1] = (tex & 0xff) | ((rough_slot + 1) << 8);
 }
 
-// Spatial key of cache queries: the Morton code (24 bits) of the query's
-// cell among 256 cells per axis of the cache's box, so that key-sorted
+// Spatial key of cache queries: the Morton code (27 bits) of the query's
+// cell among 512 cells per axis of the cache's box, so that key-sorted
 // queries gather nearby table entries.  The sort takes two passes: a
 // counting sort by the top 15 bits (32^3 bins, as many as one workgroup's
 // LDS histogram holds), then, for sorts of 2^20 items or more, each bin's
-// queries by the low 9 bits (its 8^3 sub-cells).  Inference of 40M queries
+// queries by the low 12 bits (its 16^3 sub-cells).  Inference of 40M queries
 // (1024^2, 64 spp) measured by the order's cells: 32^3 12.6 ms, 64^3
-// 10.7 ms, 128^3 9.2 ms, 256^3 8.1 ms, 1024^3 7.2 ms; unsorted 26.4 ms.
-constexpr int kQueryKeyBits = 8;                                    // per axis
+// 10.7 ms, 128^3 9.2 ms, 256^3 8.1-8.4 ms, 512^3 7.7 ms, 1024^3 7.2 ms;
+// unsorted 26.4 ms.
+constexpr int kQueryKeyBits = 9;                                    // per axis
 constexpr int kQueryBinBits = 5;                                    // first pass, per axis
 constexpr int kQueryBins = 1 << (3 * kQueryBinBits);
 constexpr int kQuerySubBits = 3 * (kQueryKeyBits - kQueryBinBits);  // second pass

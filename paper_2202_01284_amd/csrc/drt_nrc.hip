@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_encode(DNrcNet net, const float
 // requests kSortUnroll keys before it updates any: the passes are bound by
 // the latency of those reads.  After the scatter each cursor holds the end
 // of its bin.  Pass 2: each bin's pairs counting-sorted by the sub-key (the
-// bin's 8^3 sub-cells) in LDS, one bin per workgroup at a time, into the
+// bin's 16^3 sub-cells) in LDS, one bin per workgroup at a time, into the
 // final order -- for sorts of at least kRefineMin items; smaller ones are
 // ordered by bin only.  The order among equal keys is arbitrary.
 constexpr int kSortBlocks = 256;
@@ -504,28 +504,39 @@ DEV void for_bin_pairs(const uint2* __restrict__ pairs, uint32_t s, uint32_t e, 
 __global__ __launch_bounds__(kRefineThreads) void k_query_refine(const uint2* __restrict__ pairs,
                                                                 const uint32_t* __restrict__ end,
                                                                 int* __restrict__ order) {
-  // scan: thread t < kQuerySubs owns sub-key t
-  static_assert(kQuerySubs <= kRefineThreads, "scan layout");
+  // scan: thread t < kScanThreads owns sub-keys [t kPer, (t + 1) kPer)
+  constexpr int kPer = kQuerySubs > kRefineThreads ? kQuerySubs / kRefineThreads : 1;
+  constexpr int kScanThreads = kQuerySubs / kPer;
+  static_assert(kPer * kScanThreads == kQuerySubs && kScanThreads <= kRefineThreads, "scan layout");
   __shared__ uint32_t h[kQuerySubs];
-  __shared__ uint32_t part[kQuerySubs];
+  __shared__ uint32_t part[kScanThreads];
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < kQueryBins; b += gridDim.x) {
     const uint32_t s = b ? end[b - 1] : 0u, e = end[b];
     if (s >= e) continue;  // the same for the whole block
-    if (t < kQuerySubs) h[t] = 0;
+    for (int i = t; i < kQuerySubs; i += kRefineThreads) h[i] = 0;
     __syncthreads();
     for_bin_pairs(pairs, s, e, [&](uint2 p) { atomicAdd(&h[p.x], 1u); });
     __syncthreads();
-    const uint32_t c = t < kQuerySubs ? h[t] : 0u;
-    if (t < kQuerySubs) part[t] = c;
+    uint32_t c = 0;
+    if (t < kScanThreads)
+      for (int k = 0; k < kPer; ++k) c += h[kPer * t + k];
+    if (t < kScanThreads) part[t] = c;
     __syncthreads();
-    for (int off = 1; off < kQuerySubs; off <<= 1) {
-      const uint32_t v = (t < kQuerySubs && t >= off) ? part[t - off] : 0u;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const uint32_t v = (t < kScanThreads && t >= off) ? part[t - off] : 0u;
       __syncthreads();
-      if (t < kQuerySubs) part[t] += v;
+      if (t < kScanThreads) part[t] += v;
       __syncthreads();
     }
-    if (t < kQuerySubs) h[t] = s + part[t] - c;  // exclusive
+    if (t < kScanThreads) {  // exclusive offsets of the thread's sub-keys
+      uint32_t run = s + part[t] - c;
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t n = h[kPer * t + k];
+        h[kPer * t + k] = run;
+        run += n;
+      }
+    }
     __syncthreads();
     for_bin_pairs(pairs, s, e, [&](uint2 p) { order[atomicAdd(&h[p.x], 1u)] = (int)p.y; });
     __syncthreads();

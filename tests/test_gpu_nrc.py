@@ -354,9 +354,9 @@ def test_cached_render_vs_oracle():
 @pytest.mark.parametrize("size", ["small", "large"])
 def test_query_sort_is_a_key_ordered_permutation(size):
     """After a cached render the int scratch holds, per query, its spatial key
-    (Morton code of its cell among 256^3 cells of the cache box) and the
+    (Morton code of its cell among 512^3 cells of the cache box) and the
     sorted order: a permutation of the query slots.  A render of at least
-    2^20 samples is ordered by the whole key (32^3 bins, then 8^3 sub-cells
+    2^20 samples is ordered by the whole key (32^3 bins, then 16^3 sub-cells
     per bin), a smaller one by the bin (the key's top 15 bits).  A scratch
     that is not 8-byte aligned is refused."""
     drt = _drt()
@@ -376,18 +376,18 @@ def test_query_sort_is_a_key_ordered_permutation(size):
     order = ints[cap:cap + n]
     keys = ints[2 * cap:2 * cap + n].view(np.uint32)
     np.testing.assert_array_equal(np.sort(order), np.arange(n))
-    sorted_by = keys[order].astype(np.int64) if size == "large" else keys[order].astype(np.int64) >> 9
+    sorted_by = keys[order].astype(np.int64) if size == "large" else keys[order].astype(np.int64) >> 12
     assert np.all(np.diff(sorted_by) >= 0)
-    # keys agree with the positions: Morton code of the 256^3 cell
+    # keys agree with the positions: Morton code of the 512^3 cell
     lo, hi = np.array(cfg["bbox_lo"], np.float32), np.array(cfg["bbox_hi"], np.float32)
     inv = (1.0 / (hi.astype(np.float64) - lo)).astype(np.float32)
-    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(256)).astype(np.int64), 0, 255)
+    c = np.clip(((q[:n, :3] - lo) * inv * np.float32(512)).astype(np.int64), 0, 511)
     m = np.zeros(n, np.int64)
-    for b in range(8):
+    for b in range(9):
         for a in range(3):
             m |= ((c[:, a] >> b) & 1) << (3 * b + a)
     agree = (m == keys).mean()
-    print("queries", n, "keys used", len(np.unique(keys)), "bins used", len(np.unique(keys >> 9)),
+    print("queries", n, "keys used", len(np.unique(keys)), "bins used", len(np.unique(keys >> 12)),
           "key agreement", agree, flush=True)
     assert agree >= 0.999          # float32 rounding at cell faces may differ
     if size == "small":
