@@ -1385,7 +1385,7 @@ drt_status drt_render_adjoint_cached(const drt_scene* scene, const drt_params* p
   e = answer_queries(net, weights, io, need, 1.0f, sample_radiance, stream);
   if (e != hipSuccess) return hip_fail(e, "cache query launch");
   if (input_grad) {
-    // the queries are in bin order now (answer_queries sorted them)
+    // the queries are in key order now (answer_queries sorted them)
     e = launch_nrc_input_grad(net, weights, io.rec, io.qpix, io.qref, io.qpix + capacity, io.count,
                               need, opts->spp, adj_image, dg, stream);
     if (e != hipSuccess) return hip_fail(e, "cache input-gradient launch");

@@ -271,9 +271,9 @@ hipError_t launch_nrc_backward(const float* W, const float* x, const float* dy, 
                                float* dW, float* dx, hipStream_t st);
 hipError_t launch_nrc_encode(const DNrcNet& net, const float* rec, int64_t n, float* x,
                              hipStream_t st);
-// Counting sort of the queries by spatial bin: order[] = query indices, bin
-// by bin.  hist: kQueryBins words of scratch.
-// pairs: 8-byte aligned scratch of capacity 8-byte entries
+// Sort of the queries by spatial key (qbin): order[] = query indices in key
+// order (for fewer than 2^20 queries, in bin order).  hist: kQueryBins words
+// of scratch; pairs: 8-byte aligned scratch of capacity 8-byte entries.
 hipError_t launch_query_sort(const uint32_t* qbin, const int* count, int64_t capacity,
                              uint32_t* hist, void* pairs, int* order, hipStream_t st);
 hipError_t launch_nrc_infer(const DNrcNet& net, const float* W, const float* q, const int* qpix,

@@ -860,7 +860,7 @@ __global__ __launch_bounds__(kBlockN) void k_nrc_backward(const float* __restric
 // ---------------------------------------------------------------------------
 // gradient of the cache term through the network's inputs
 // ---------------------------------------------------------------------------
-// Per query (bin order, tiles as in xcd_tiles): forward pass, output gradient
+// Per query (key order, tiles as in xcd_tiles): forward pass, output gradient
 // dy = dL * beta * [y > 0] with dL = adj[pixel] / spp, the masked deltas back
 // to layer 0, and the input gradient of inputs 64..67 (roughness, albedo),
 // added to the roughness slot and albedo texel the query's vertex read them
