@@ -78,9 +78,12 @@ enum {
 
 /* Render flags. */
 enum {
-  DRT_FLAG_NO_NEE = 1,         /* BSDF sampling only (no next-event estimation, no MIS) */
-  DRT_FLAG_CACHE_INPUT_GRAD = 2 /* drt_render_adjoint_cached: differentiate the cache's
-                                   output through its albedo and roughness inputs too */
+  DRT_FLAG_NO_NEE = 1,          /* BSDF sampling only (no next-event estimation, no MIS) */
+  DRT_FLAG_CACHE_INPUT_GRAD = 2, /* drt_render_adjoint_cached: differentiate the cache's
+                                    output through its albedo and roughness inputs too */
+  DRT_FLAG_GLOBAL_SCENE = 4      /* read the tree and triangles from device memory even where
+                                    the scene fits the megakernels' per-workgroup LDS copy
+                                    (same results; for comparisons) */
 };
 
 typedef struct {

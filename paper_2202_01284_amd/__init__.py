@@ -27,6 +27,7 @@ MAX_TEXTURES = 8
 MAX_CAMERAS = 32
 FLAG_NO_NEE = 1
 FLAG_CACHE_INPUT_GRAD = 2   # cached adjoint: also through the cache's albedo/roughness inputs
+FLAG_GLOBAL_SCENE = 4       # tree and triangles read from device memory even where they fit the LDS copy
 STAT_NAMES = ["rays", "shadow_rays", "nodes", "tris", "vertices", "scatter", "lrem_max", "samples",
               "tex_lanes", "tex_keys", "wave_nodes", "wave_tris", "lane_steps", "wave_steps",
               "wave_shade"]

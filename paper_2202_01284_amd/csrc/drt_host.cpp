@@ -350,16 +350,18 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
   };
   std::vector<int> dn_of(b.nodes.size(), -1);
   std::vector<int> order;
-  std::vector<int> stack{root};
+  std::vector<std::pair<int, int>> stack{{root, 0}};  // (binary node, four-wide level)
+  int levels = 0;
   while (!stack.empty()) {
-    int id = stack.back();
+    const auto [id, level] = stack.back();
     stack.pop_back();
+    levels = std::max(levels, level + 1);
     dn_of[id] = (int)order.size();
     order.push_back(id);
     int sl[4];
     int n = slots_of(id, sl);
     for (int k = n - 1; k >= 0; --k)
-      if (b.nodes[sl[k]].child[0] >= 0) stack.push_back(sl[k]);
+      if (b.nodes[sl[k]].child[0] >= 0) stack.push_back({sl[k], level + 1});
   }
   DNode* nodes = (DNode*)&P->bytes[off[0]];
   int n_leaves = 0;
@@ -513,6 +515,14 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
   L.n_rough = d->n_roughness;
   L.n_tex = d->n_textures;
   L.eps = info.eps;
+  // the megakernels' LDS copy of the tree and triangles: a traversal visits
+  // at most 3 x levels stacked nodes (three of a node's four children wait
+  // on the stack per level)
+  L.n_nodes = info.n_nodes;
+  L.n_tris = nt;
+  L.lds_scene = 3 * levels <= kStackDepthSmall &&
+                (int64_t)info.n_nodes * (int64_t)sizeof(DNode) + (int64_t)nt * (int64_t)sizeof(DTri) <=
+                    kLdsSceneBytes;
   for (int t = 0; t < d->n_textures; ++t) {
     L.tex_w[t] = d->textures[t].width;
     L.tex_h[t] = d->textures[t].height;

@@ -18,6 +18,14 @@ namespace drt {
 // more than 3 x 12 = 36 = kStackDepth entries.  36 entries x 64 lanes keep
 // sixteen one-wave workgroups per CU within the 160 KB of LDS.
 constexpr int kStackDepth = 36;
+// Small scenes: the megakernels that render (primal, adjoint, cached modes)
+// copy the whole tree and its triangles into each workgroup's LDS, beside a
+// traversal stack of kStackDepthSmall entries (trees of up to 5 four-wide
+// levels), when they fit in kLdsSceneBytes: node and triangle reads then
+// come from LDS instead of the L1.  Stack, copy and the kernels' other LDS
+// stay within 10 KB per one-wave workgroup, 16 per CU as without the copy.
+constexpr int kStackDepthSmall = 16;
+constexpr int kLdsSceneBytes = 5120;
 constexpr int kMaxInteriorDepth = 24;
 constexpr int kBlock = 64;             // threads per workgroup of the megakernels (one wave)
 constexpr int kTile = 8;               // workgroup = 8 x 8 pixel tile
@@ -95,7 +103,9 @@ struct DScene {
   const float* env_cdf_row;  // [h+1]
   const float* env_cdf_col;  // [h][w+1]
   int32_t n_ems, env_w, env_h, env_emitter;
-  int32_t n_mats, n_rough, n_tex, pad;
+  int32_t n_mats, n_rough, n_tex;
+  int32_t lds_scene;         // the tree and triangles fit the megakernels' LDS copy
+  int32_t n_nodes, n_tris;
   float eps;
   int32_t tex_w[DRT_MAX_TEXTURES], tex_h[DRT_MAX_TEXTURES];
 };

@@ -560,6 +560,27 @@ DEV void flush_counters(const DRender& R, Counters& c) {
             (unsigned long long)__float_as_uint(c.lrem_max));
 }
 
+// The scene as a megakernel reads it.  LS: the tree and its triangles from
+// the workgroup's LDS copy, filled here (the caller synchronizes before the
+// first read); the host sets s.lds_scene only where they fit kLdsSceneBytes
+// and the tree needs at most kStackDepthSmall stack entries.
+template <bool LS>
+DEV DScene scene_view(const DScene& s, float4* lds) {
+  if constexpr (!LS) {
+    return s;
+  } else {
+    const int nn = 8 * s.n_nodes, nt = 3 * s.n_tris;  // float4 per node / triangle
+    const float4* gn = reinterpret_cast<const float4*>(s.nodes);
+    const float4* gt = reinterpret_cast<const float4*>(s.tris);
+    for (int i = threadIdx.x; i < nn; i += kBlock) lds[i] = gn[i];
+    for (int i = threadIdx.x; i < nt; i += kBlock) lds[nn + i] = gt[i];
+    DScene v = s;
+    v.nodes = reinterpret_cast<const DNode*>(lds);
+    v.tris = reinterpret_cast<const DTri*>(lds + nn);
+    return v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // megakernels: one 8x8 pixel tile per workgroup (one wave)
 // ---------------------------------------------------------------------------
@@ -567,12 +588,14 @@ DEV void flush_counters(const DRender& R, Counters& c) {
 // MODE: MODE_PRIMAL, MODE_CACHED (paths stop at their record vertex and
 // append cache queries) or MODE_CACHED_SAMPLES (per-sample radiance, no image;
 // with HC also the intersection records of every sample).
-template <bool STATS, int MODE, bool HC = false>
+template <bool STATS, int MODE, bool HC = false, bool LS = false>
 __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, DCams C, DRender R,
                                                            float* __restrict__ image, DNrcIO io) {
-  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ int stack[(LS ? kStackDepthSmall : kStackDepth) * kBlock];
   __shared__ LdsTables tab;
+  __shared__ float4 lds_scene[LS ? kLdsSceneBytes / 16 : 1];
   load_tables(tab, s, P, nullptr);
+  const DScene sv = scene_view<LS>(s, lds_scene);
   __syncthreads();
   const int W = C.width, H = C.height;
   const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
@@ -594,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
       const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
       hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
     }
-    render_pixel<MODE, HC, STATS>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
+    render_pixel<MODE, HC, STATS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
                                   mk(0, 0, 0), stack + threadIdx.x, cnt, none, io, acc, hrec);
     if (MODE != MODE_CACHED_SAMPLES) {
       const float inv = 1.0f / (float)R.spp;
@@ -622,16 +645,18 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
 // workgroups (as many as are resident at once) that take the units from the
 // counter R.items until none is left, each with one record slot; otherwise
 // the grid has one workgroup per unit (blockIdx.z = camera x split + part).
-template <bool STATS, int MODE, bool HC = false>
+template <bool STATS, int MODE, bool HC = false, bool LS = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_adjoint(DScene s, DParams P, DCams C, DRender R,
                                                            const float* __restrict__ adj,
                                                            DGrads G, DNrcIO io) {
-  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ int stack[(LS ? kStackDepthSmall : kStackDepth) * kBlock];
   __shared__ LdsTables tab;
   __shared__ float rough_acc[kMaxRoughLds];
+  __shared__ float4 lds_scene[LS ? kLdsSceneBytes / 16 : 1];
   const bool lds_rough = G.rough && s.n_rough <= kMaxRoughLds;
   load_tables(tab, s, P, &G);
   if (threadIdx.x < kMaxRoughLds) rough_acc[threadIdx.x] = 0.f;
+  const DScene sv = scene_view<LS>(s, lds_scene);
   __syncthreads();
   constexpr bool PERSIST = HC && MODE == MODE_ADJOINT;
   __shared__ uint32_t unit_s;
@@ -680,7 +705,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
           const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
           hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
         }
-        render_pixel<MODE, HC, STATS>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
+        render_pixel<MODE, HC, STATS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
                                       s1 - s0, dL, stack + threadIdx.x, cnt, sink, io, unused, hrec,
                                       &racc);
       }
@@ -966,6 +991,13 @@ __global__ __launch_bounds__(256) void k_adam4(float4* __restrict__ p, float4* _
 // launchers
 
 // ---------------------------------------------------------------------------
+// The megakernels read the tree and triangles from a per-workgroup LDS copy
+// where the scene fits (not for the counting runs, nor when the caller asks
+// for device-memory reads).
+static bool use_lds_scene(const DScene& s, const DRender& r) {
+  return s.lds_scene && !r.stats && !(r.flags & DRT_FLAG_GLOBAL_SCENE);
+}
+
 hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams& c,
                                  const DRender& r, float* image, hipStream_t st) {
   // two workgroups per tile (sample halves) adding onto a zeroed image
@@ -979,6 +1011,9 @@ hipError_t launch_render_forward(const DScene& s, const DParams& p, const DCams&
   if (r.stats)
     hipLaunchKernelGGL((k_render_forward<true, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p, c,
                        r, image, none);
+  else if (use_lds_scene(s, r))
+    hipLaunchKernelGGL((k_render_forward<false, MODE_PRIMAL, false, true>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, image, none);
   else
     hipLaunchKernelGGL((k_render_forward<false, MODE_PRIMAL>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, image, none);
@@ -989,11 +1024,21 @@ hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& 
                                 const DRender& r, float* image, const DNrcIO& io,
                                 hipStream_t st) {
   dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
-  if (io.lsamp && r.hits)
+  const bool ls = use_lds_scene(s, r);
+  if (io.lsamp && r.hits && ls)
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES, true, true>), grid, dim3(kBlock),
+                       0, st, s, p, c, r, image, io);
+  else if (io.lsamp && r.hits)
     hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES, true>), grid, dim3(kBlock), 0,
                        st, s, p, c, r, image, io);
+  else if (io.lsamp && ls)
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES, false, true>), grid, dim3(kBlock),
+                       0, st, s, p, c, r, image, io);
   else if (io.lsamp)
     hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED_SAMPLES>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, image, io);
+  else if (ls)
+    hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED, false, true>), grid, dim3(kBlock), 0, st,
                        s, p, c, r, image, io);
   else
     hipLaunchKernelGGL((k_render_forward<false, MODE_CACHED>), grid, dim3(kBlock), 0, st, s, p,
@@ -1043,12 +1088,18 @@ hipError_t launch_render_adjoint(const DScene& s, const DParams& p, const DCams&
     if (r.stats)
       hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT, true>), dim3(groups), dim3(kBlock), 0,
                          st, s, p, c, r, adj, g, none);
+    else if (use_lds_scene(s, r))
+      hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, true, true>), dim3(groups),
+                         dim3(kBlock), 0, st, s, p, c, r, adj, g, none);
     else
       hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, true>), dim3(groups), dim3(kBlock), 0,
                          st, s, p, c, r, adj, g, none);
   } else if (r.stats) {
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, adj, g, none);
+  } else if (use_lds_scene(s, r)) {
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT, false, true>), grid, dim3(kBlock), 0, st,
+                       s, p, c, r, adj, g, none);
   } else {
     hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT>), grid, dim3(kBlock), 0, st, s, p,
                        c, r, adj, g, none);
@@ -1080,12 +1131,19 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
                                         const DRender& r, const float* adj, const DGrads& g,
                                         const DNrcIO& io, hipStream_t st) {
   dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
+  const bool ls = use_lds_scene(s, r);
   if (r.hits && r.stats)
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED, true>), grid, dim3(kBlock), 0,
                        st, s, p, c, r, adj, g, io);
+  else if (r.hits && ls)
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED, true, true>), grid, dim3(kBlock),
+                       0, st, s, p, c, r, adj, g, io);
   else if (r.hits)
     hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED, true>), grid, dim3(kBlock), 0,
                        st, s, p, c, r, adj, g, io);
+  else if (ls)
+    hipLaunchKernelGGL((k_render_adjoint<false, MODE_ADJOINT_CACHED, false, true>), grid, dim3(kBlock),
+                       0, st, s, p, c, r, adj, g, io);
   else if (r.stats)
     hipLaunchKernelGGL((k_render_adjoint<true, MODE_ADJOINT_CACHED>), grid, dim3(kBlock), 0, st,
                        s, p, c, r, adj, g, io);

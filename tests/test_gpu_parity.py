@@ -550,3 +550,35 @@ def test_stats_counters_are_consistent():
         st = drt.read_stats(st_a)
         assert 0 < st["tex_keys"] <= st["tex_lanes"], st
         assert drt.read_stats(st_f)["tex_lanes"] == 0
+
+
+def test_lds_scene_copy_equals_device_memory_reads():
+    """Scenes that fit the megakernels' per-workgroup LDS copy of the tree
+    and triangles (the Cornell scenes) render from it; with
+    DRT_FLAG_GLOBAL_SCENE the same kernels read device memory.  The same
+    arithmetic on the same data: the primal image is bit-identical, the
+    gradients equal up to the order of the float atomics, and the cached
+    render equal up to that of its cache terms."""
+    drt = _drt()
+    sc = scenes.cornell(conductor=True, texture=scenes.random_texture(64), width=40, height=24)
+    gs = drt.Scene(sc)
+    assert gs.info["n_nodes"] * 128 + gs.info["n_triangles"] * 48 <= 5120
+    tex, rough = _params(sc)
+    G = drt.FLAG_GLOBAL_SCENE
+    a = drt.render_forward(gs, tex, rough, sc.cameras, 5, 4, seed=3).cpu().numpy()
+    b = drt.render_forward(gs, tex, rough, sc.cameras, 5, 4, seed=3, flags=G).cpu().numpy()
+    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    adj = torch.from_numpy(np.random.default_rng(4).normal(size=(1, 24, 40, 3)).astype(np.float32)).cuda()
+    for hits in (None, drt.adjoint_hit_records(sc.cameras, 5, 4)):
+        ga, ra = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 5, 4, seed=6, hit_records=hits)
+        gb, rb = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 5, 4, seed=6, flags=G, hit_records=hits)
+        x, y = ga[0].cpu().numpy().astype(np.float64), gb[0].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(y)
+        assert abs(ra.item() - rb.item()) <= 1e-5 * abs(rb.item())
+    cfg = scenes.nrc_config(sc)
+    W, grid = scenes.nrc_init(cfg, seed=10)
+    Wg, gg = torch.from_numpy(W).cuda(), torch.from_numpy(grid.reshape(-1)).cuda()
+    ca = drt.render_forward_cached(gs, tex, rough, sc.cameras, cfg, Wg, gg, spp=4, seed=5).cpu().numpy()
+    cb = drt.render_forward_cached(gs, tex, rough, sc.cameras, cfg, Wg, gg, spp=4, seed=5,
+                                   flags=G).cpu().numpy()
+    np.testing.assert_allclose(ca, cb, rtol=1e-5, atol=1e-7)
