@@ -520,9 +520,11 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
   // on the stack per level)
   L.n_nodes = info.n_nodes;
   L.n_tris = nt;
-  L.lds_scene = 3 * levels <= kStackDepthSmall &&
-                (int64_t)info.n_nodes * (int64_t)sizeof(DNode) + (int64_t)nt * (int64_t)sizeof(DTri) <=
-                    kLdsSceneBytes;
+  const int64_t lds_bytes = (int64_t)info.n_nodes * (int64_t)sizeof(DNode) +
+                            (int64_t)nt * (int64_t)(sizeof(DTri) + sizeof(DShade)) +
+                            (int64_t)d->n_materials * (int64_t)sizeof(DMaterial) +
+                            (int64_t)d->n_emitters * (int64_t)sizeof(DEmitter);
+  L.lds_scene = 3 * levels <= kStackDepthSmall && lds_bytes <= kLdsSceneBytes;
   for (int t = 0; t < d->n_textures; ++t) {
     L.tex_w[t] = d->textures[t].width;
     L.tex_h[t] = d->textures[t].height;

@@ -560,23 +560,35 @@ DEV void flush_counters(const DRender& R, Counters& c) {
             (unsigned long long)__float_as_uint(c.lrem_max));
 }
 
-// The scene as a megakernel reads it.  LS: the tree and its triangles from
-// the workgroup's LDS copy, filled here (the caller synchronizes before the
-// first read); the host sets s.lds_scene only where they fit kLdsSceneBytes
-// and the tree needs at most kStackDepthSmall stack entries.
+// The scene as a megakernel reads it.  LS: the tree, the triangles, their
+// shading records, the materials and the emitters from the workgroup's LDS
+// copy, filled here (the caller synchronizes before the first read); the
+// host sets s.lds_scene only where they fit kLdsSceneBytes and the tree
+// needs at most kStackDepthSmall stack entries.
+DEV void lds_fill(float4* dst, const void* src, int n) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  for (int i = threadIdx.x; i < n; i += kBlock) dst[i] = s4[i];
+}
 template <bool LS>
 DEV DScene scene_view(const DScene& s, float4* lds) {
   if constexpr (!LS) {
     return s;
   } else {
-    const int nn = 8 * s.n_nodes, nt = 3 * s.n_tris;  // float4 per node / triangle
-    const float4* gn = reinterpret_cast<const float4*>(s.nodes);
-    const float4* gt = reinterpret_cast<const float4*>(s.tris);
-    for (int i = threadIdx.x; i < nn; i += kBlock) lds[i] = gn[i];
-    for (int i = threadIdx.x; i < nt; i += kBlock) lds[nn + i] = gt[i];
+    // float4 per node / triangle / shading record / material / emitter: 8 / 3 / 2 / 4 / 6
+    const int nn = 8 * s.n_nodes, nt = 3 * s.n_tris, ns = 2 * s.n_tris, nm = 4 * s.n_mats;
+    const int ne = 6 * s.n_ems;
+    float4* p = lds;
+    lds_fill(p, s.nodes, nn);
+    lds_fill(p + nn, s.tris, nt);
+    lds_fill(p + nn + nt, s.shade, ns);
+    lds_fill(p + nn + nt + ns, s.mats, nm);
+    lds_fill(p + nn + nt + ns + nm, s.ems, ne);
     DScene v = s;
-    v.nodes = reinterpret_cast<const DNode*>(lds);
-    v.tris = reinterpret_cast<const DTri*>(lds + nn);
+    v.nodes = reinterpret_cast<const DNode*>(p);
+    v.tris = reinterpret_cast<const DTri*>(p + nn);
+    v.shade = reinterpret_cast<const DShade*>(p + nn + nt);
+    v.mats = reinterpret_cast<const DMaterial*>(p + nn + nt + ns);
+    v.ems = reinterpret_cast<const DEmitter*>(p + nn + nt + ns + nm);
     return v;
   }
 }
