@@ -222,7 +222,9 @@ def main():
     st = drt.read_stats(stats)
     flops = st["nodes"] * FLOP_PER_NODE + st["tris"] * FLOP_PER_TRI + st["vertices"] * FLOP_PER_VERTEX
     achieved = flops / (adj_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_render_adjoint<false, 1, true>", "bound": "alu", "achieved": round(achieved, 4),
+    # the replay from intersection records; <.., true> when the scene fits the LDS copy
+    kname = "k_render_adjoint<false, 1, true, true>" if gs.info["lds_copy"] else "k_render_adjoint<false, 1, true>"
+    roofline = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 4),
                 "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
                 "traffic": measured_traffic(), "launch_ms": round(adj_ms, 3),
                 "units_per_launch": {k: st[k] for k in ("rays", "shadow_rays", "nodes", "tris",

@@ -138,6 +138,10 @@ typedef struct {
   float eps;                     /* ray-spawn offset: 1e-4 x largest extent of the scene box */
   float bounds_lo[3], bounds_hi[3];
   uint64_t device_bytes;         /* bytes of the scene's device buffer actually used */
+  int32_t lds_copy;              /* 1: the rendering megakernels read the tree, triangles,
+                                    shading records, materials and emitters from a copy in
+                                    each workgroup's LDS (the scene fits 5 KB and its tree
+                                    at most 5 four-wide levels); 0: from device memory */
 } drt_scene_info;
 
 /* Upper bound of the device bytes a scene needs (no BVH build). */

@@ -69,7 +69,8 @@ class drt_scene_info(ctypes.Structure):
                 ("forced_leaves", _c_i32), ("n_triangles", _c_i32), ("n_materials", _c_i32),
                 ("n_emitters", _c_i32), ("n_textures", _c_i32), ("n_roughness", _c_i32),
                 ("env_width", _c_i32), ("env_height", _c_i32), ("eps", _c_f),
-                ("bounds_lo", _c_f * 3), ("bounds_hi", _c_f * 3), ("device_bytes", _c_u64)]
+                ("bounds_lo", _c_f * 3), ("bounds_hi", _c_f * 3), ("device_bytes", _c_u64),
+                ("lds_copy", _c_i32)]
 
 
 class drt_camera(ctypes.Structure):

@@ -525,6 +525,7 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
                             (int64_t)d->n_materials * (int64_t)sizeof(DMaterial) +
                             (int64_t)d->n_emitters * (int64_t)sizeof(DEmitter);
   L.lds_scene = 3 * levels <= kStackDepthSmall && lds_bytes <= kLdsSceneBytes;
+  info.lds_copy = L.lds_scene;
   for (int t = 0; t < d->n_textures; ++t) {
     L.tex_w[t] = d->textures[t].width;
     L.tex_h[t] = d->textures[t].height;

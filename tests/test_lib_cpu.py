@@ -300,3 +300,26 @@ def test_cache_and_jvp_arguments_rejected_before_launch():
     assert drt.lib.drt_render_adjoint_noalloc(h, ctypes.byref(p), cams, 1, ctypes.byref(o), fake,
                                               ctypes.byref(g), None) == -4
     drt.lib.drt_scene_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["cornell", "cornell_conductor", "zoo", "soup40", "soup200", "one"])
+def test_lds_copy_decision(name):
+    """The megakernels keep a per-workgroup LDS copy of a scene's tree,
+    triangles, shading records, materials and emitters when they take at
+    most 5120 bytes and the tree needs at most 16 traversal-stack entries
+    (3 per four-wide level)."""
+    sc = {"cornell": scenes.cornell, "cornell_conductor": lambda: scenes.cornell(conductor=True),
+          "zoo": scenes.bsdf_zoo, "soup40": lambda: scenes.triangle_soup(40, seed=3),
+          "soup200": lambda: scenes.triangle_soup(200, seed=3),
+          "one": lambda: scenes.triangle_soup(1, seed=1)}[name]()
+    nodes, tris, info = _unpack(sc)
+    levels = max(_depths(nodes).values()) + 1
+    size = (info["n_nodes"] * 128 + info["n_triangles"] * (48 + 32) + info["n_materials"] * 64 +
+            info["n_emitters"] * 96)
+    want = int(size <= 5120 and 3 * levels <= 16)
+    print(name, size, levels, info["lds_copy"], flush=True)
+    assert info["lds_copy"] == want
+    if name.startswith("cornell"):
+        assert want == 1          # the gradient-step scenes take the LDS copy
+    if name in ("zoo", "soup200"):
+        assert want == 0
