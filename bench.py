@@ -223,7 +223,7 @@ def main():
     flops = st["nodes"] * FLOP_PER_NODE + st["tris"] * FLOP_PER_TRI + st["vertices"] * FLOP_PER_VERTEX
     achieved = flops / (adj_ms * 1e-3) / 1e12
     # the replay from intersection records; <.., true> when the scene fits the LDS copy
-    kname = "k_render_adjoint<false, 1, true, true>" if gs.info["lds_copy"] else "k_render_adjoint<false, 1, true>"
+    kname = "k_render_adjoint<false, 1, true, %s>" % ("true" if gs.info["lds_copy"] else "false")
     roofline = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 4),
                 "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 5),
                 "traffic": measured_traffic(), "launch_ms": round(adj_ms, 3),
