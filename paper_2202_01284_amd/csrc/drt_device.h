@@ -105,6 +105,7 @@ struct RayPre {
   f3 idir, ooi;  // 1/d (finite) and o/d for the slab test
   int kx, ky, kz;
   float sx, sy, sz;
+  float okx, oky, okz;  // o's components along kx, ky, kz
 };
 
 DEV RayPre ray_pre(f3 o, f3 d) {
@@ -135,6 +136,9 @@ DEV RayPre ray_pre(f3 o, f3 d) {
   r.sx = comp(d, kx) / dkz;
   r.sy = comp(d, ky) / dkz;
   r.sz = 1.0f / dkz;
+  r.okx = comp(o, kx);
+  r.oky = comp(o, ky);
+  r.okz = comp(o, kz);
   return r;
 }
 
@@ -168,22 +172,24 @@ DEV float diff_of_products(float a, float b, float c, float d) {
 }
 
 // Watertight ray/triangle test (no culling), t in (tmin, tmax] -- the caller
-// decides about t == tmax.  Each edge function is Kahan's difference of
-// products, whose sign is exact: two triangles sharing an edge evaluate the
-// same two products in swapped roles, so they always agree on which side of
-// the edge the ray passes (no cracks from the rounding of a fused
-// multiply-add), and a value is zero only when the exact one is -- which is
-// what the method's higher-precision fallback for zero edge functions
-// secures, so none is needed.
-DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float& t_out, float& b1,
-                  float& b2) {
-  f3 A = mk(T.p0x, T.p0y, T.p0z) - r.o;
-  f3 B = mk(T.p1x, T.p1y, T.p1z) - r.o;
-  f3 C = mk(T.p2x, T.p2y, T.p2z) - r.o;
-  float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
-  float Ax = comp(A, r.kx) - r.sx * Akz, Ay = comp(A, r.ky) - r.sy * Akz;
-  float Bx = comp(B, r.kx) - r.sx * Bkz, By = comp(B, r.ky) - r.sy * Bkz;
-  float Cx = comp(C, r.kx) - r.sx * Ckz, Cy = comp(C, r.ky) - r.sy * Ckz;
+// decides about t == tmax.  tp is the triangle's record (vertex v's
+// component c at tp[3 v + c]); the coordinates are read along the ray's
+// permuted axes kx, ky, kz directly, so the permutation costs three address
+// offsets per ray instead of selects per test.  Each edge function is
+// Kahan's difference of products, whose sign is exact: two triangles
+// sharing an edge evaluate the same two products in swapped roles, so they
+// always agree on which side of the edge the ray passes (no cracks from the
+// rounding of a fused multiply-add), and a value is zero only when the exact
+// one is -- which is what the method's higher-precision fallback for zero
+// edge functions secures, so none is needed.
+DEV bool tri_test(const RayPre& r, const float* tp, float tmin, float tmax, float& t_out,
+                  float& b1, float& b2) {
+  const float Akx = tp[r.kx] - r.okx, Aky = tp[r.ky] - r.oky, Akz = tp[r.kz] - r.okz;
+  const float Bkx = tp[3 + r.kx] - r.okx, Bky = tp[3 + r.ky] - r.oky, Bkz = tp[3 + r.kz] - r.okz;
+  const float Ckx = tp[6 + r.kx] - r.okx, Cky = tp[6 + r.ky] - r.oky, Ckz = tp[6 + r.kz] - r.okz;
+  const float Ax = Akx - r.sx * Akz, Ay = Aky - r.sy * Akz;
+  const float Bx = Bkx - r.sx * Bkz, By = Bky - r.sy * Bkz;
+  const float Cx = Ckx - r.sx * Ckz, Cy = Cky - r.sy * Ckz;
   const float U = diff_of_products(Cx, By, Cy, Bx);
   const float V = diff_of_products(Ax, Cy, Ay, Cx);
   const float W = diff_of_products(Bx, Ay, By, Ax);
@@ -345,28 +351,29 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       off = j < e1 ? f1 : off;
       off = j < e0 ? f0 : off;
       const int i = j + off;
-      const DTri T = load_tri(s, i);
+      const float* tp = reinterpret_cast<const float*>(s.tris + i);
+      const int prim = __float_as_int(tp[9]), flags = __float_as_int(tp[10]);
       cnt.tris++;
       if constexpr (ST) cnt.wave_tris += first_active_lane();
       float t, b1, b2;
-      bool ok = tri_test(r, T, tmin, tbest, t, b1, b2);
+      bool ok = tri_test(r, tp, tmin, tbest, t, b1, b2);
       if (any) {
         // shadow rays pass through null surfaces; the flag is tested after
         // the whole record has been loaded (no second memory round trip)
-        if (ok && !(T.flags & 1) && t < tmax) {
+        if (ok && !(flags & 1) && t < tmax) {
           found = true;
           break;
         }
         continue;
       }
       // closest: strictly nearer, or an exact tie with a lower original id
-      ok = ok && (t < tbest || (h.tri >= 0 && T.prim < h.prim));
+      ok = ok && (t < tbest || (h.tri >= 0 && prim < h.prim));
       tbest = ok ? t : tbest;
       h.t = ok ? t : h.t;
       h.b1 = ok ? b1 : h.b1;
       h.b2 = ok ? b2 : h.b2;
       h.tri = ok ? i : h.tri;
-      h.prim = ok ? T.prim : h.prim;
+      h.prim = ok ? prim : h.prim;
     }
     e3 = 0;
     if (found) break;

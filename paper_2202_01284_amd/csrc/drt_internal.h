@@ -3,6 +3,7 @@
 // in one caller-owned device buffer, addressed through the pointers of
 // DScene, which is passed to every kernel by value.
 #pragma once
+#include <cstddef>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -65,6 +66,10 @@ struct alignas(16) DTri {
   int32_t pad;
 };
 static_assert(sizeof(DTri) == 48, "DTri");
+// the traversal reads vertex v's component c at float 3 v + c, prim at 9, flags at 10
+static_assert(offsetof(DTri, p2z) == 8 * sizeof(float) && offsetof(DTri, prim) == 9 * sizeof(float) &&
+                  offsetof(DTri, flags) == 10 * sizeof(float),
+              "DTri layout");
 
 // Shading attributes by original triangle id, 32 bytes.
 struct alignas(16) DShade {
