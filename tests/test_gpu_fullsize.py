@@ -287,7 +287,11 @@ def test_cache_config_render_sampled_pixels():
     print("queries", n, flush=True)
     assert n > 30_000_000
     img = img.cpu().numpy().reshape(-1, 3)
-    ids = np.random.default_rng(5).choice(1024 * 1024, 1024, replace=False)
+    # 16,384 pixels: with ~1,000 the 99.9% criterion would admit no failing
+    # pixel at all, and the trained cache (hash-grid gradients summed by
+    # float atomics) differs from run to run, moving the pixels whose
+    # BF16 network output sits at the tolerance
+    ids = np.random.default_rng(5).choice(1024 * 1024, 16384, replace=False)
     ref, amb = oracle.OracleScene(sc).render_cached(cfg, grid, W, K=3, spp=64, max_depth=6, rr_depth=3,
                                                     seed=7, pixel_ids=ids, emu=True, ambiguity=True)
     check_image(img[ids], ref, "cached render 1024^2 64spp sampled", amb)
