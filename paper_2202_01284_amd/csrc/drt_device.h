@@ -106,6 +106,7 @@ struct RayPre {
   int kx, ky, kz;
   float sx, sy, sz;
   float okx, oky, okz;  // o's components along kx, ky, kz
+  int nx, ny, nz;       // per axis, the node float4 of the near bounds (lo; hi where d < 0)
 };
 
 DEV RayPre ray_pre(f3 o, f3 d) {
@@ -139,20 +140,25 @@ DEV RayPre ray_pre(f3 o, f3 d) {
   r.okx = comp(o, kx);
   r.oky = comp(o, ky);
   r.okz = comp(o, kz);
+  r.nx = r.idir.x < 0.f ? 3 : 0;
+  r.ny = r.idir.y < 0.f ? 4 : 1;
+  r.nz = r.idir.z < 0.f ? 5 : 2;
   return r;
 }
 
-// Slab test of one child box; returns entry distance in tn.
-DEV bool slab(const RayPre& r, float lx, float ly, float lz, float hx, float hy, float hz,
-              float tmin, float tmax, float& tn) {
-  float t0x = fmaf(lx, r.idir.x, -r.ooi.x), t1x = fmaf(hx, r.idir.x, -r.ooi.x);
-  float t0y = fmaf(ly, r.idir.y, -r.ooi.y), t1y = fmaf(hy, r.idir.y, -r.ooi.y);
-  float t0z = fmaf(lz, r.idir.z, -r.ooi.z), t1z = fmaf(hz, r.idir.z, -r.ooi.z);
-  float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
-  float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-  tn = tnear;
-  // conservative far bound: the two roundings of the fma form plus slack
-  return tnear <= tfar * 1.0000005f;
+// Slab distances of four children's bounds along one axis.  fma(c, 1/d, -o/d)
+// is monotone in c, so the bound on the near side of the ray's direction
+// gives the smaller distance: picking it per ray orders each slab pair with
+// no min / max.
+DEV float4 slab4(float4 c, float idir, float ooi) {
+  return make_float4(fmaf(c.x, idir, -ooi), fmaf(c.y, idir, -ooi), fmaf(c.z, idir, -ooi),
+                     fmaf(c.w, idir, -ooi));
+}
+DEV float4 max4(float4 a, float4 b) {
+  return make_float4(fmaxf(a.x, b.x), fmaxf(a.y, b.y), fmaxf(a.z, b.z), fmaxf(a.w, b.w));
+}
+DEV float4 min4(float4 a, float4 b) {
+  return make_float4(fminf(a.x, b.x), fminf(a.y, b.y), fminf(a.z, b.z), fminf(a.w, b.w));
 }
 
 struct Hit {
@@ -275,15 +281,23 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       // a short-circuit on the count would put the box loads behind the count
       // load and cost every node a second memory round trip.  Empty slots hold
       // a zero box, so the test on them is harmless.
-      {  // children 0 and 1: three float4 (fewer live registers than all four boxes)
-        const float4 a = np[0], b = np[1], c = np[2];
-        h0 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t0) & (cn.x >= 0);
-        h1 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t1) & (cn.y >= 0);
-      }
-      {  // children 2 and 3
-        const float4 a = np[3], b = np[4], c = np[5];
-        h2 = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tmin, tbest, t2) & (cn.z >= 0);
-        h3 = slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tmin, tbest, t3) & (cn.w >= 0);
+      {  // entry (tn) and exit (tf) distances of the four boxes, axis by axis
+        float4 tn = slab4(np[r.nx], r.idir.x, r.ooi.x), tf = slab4(np[3 - r.nx], r.idir.x, r.ooi.x);
+        tn = max4(tn, slab4(np[r.ny], r.idir.y, r.ooi.y));
+        tf = min4(tf, slab4(np[5 - r.ny], r.idir.y, r.ooi.y));
+        tn = max4(tn, slab4(np[r.nz], r.idir.z, r.ooi.z));
+        tf = min4(tf, slab4(np[7 - r.nz], r.idir.z, r.ooi.z));
+        tn = max4(tn, make_float4(tmin, tmin, tmin, tmin));
+        tf = min4(tf, make_float4(tbest, tbest, tbest, tbest));
+        t0 = tn.x;
+        t1 = tn.y;
+        t2 = tn.z;
+        t3 = tn.w;
+        // conservative exit: the two roundings of the fma form plus slack
+        h0 = (tn.x <= tf.x * 1.0000005f) & (cn.x >= 0);
+        h1 = (tn.y <= tf.y * 1.0000005f) & (cn.y >= 0);
+        h2 = (tn.z <= tf.z * 1.0000005f) & (cn.z >= 0);
+        h3 = (tn.w <= tf.w * 1.0000005f) & (cn.w >= 0);
       }
       // the batch: the hit leaf children's ranges, offsets picked by selects
       e0 = (h0 && cn.x > 0) ? cn.x : 0;

@@ -249,9 +249,10 @@ struct Builder {
 };
 
 void set_child_box(DNode& n, int slot, const Box& b) {
-  float* f = n.box[slot];
-  f[0] = b.lo[0]; f[1] = b.lo[1]; f[2] = b.lo[2];
-  f[3] = b.hi[0]; f[4] = b.hi[1]; f[5] = b.hi[2];
+  for (int a = 0; a < 3; ++a) {
+    n.box[a][slot] = b.lo[a];
+    n.box[3 + a][slot] = b.hi[a];
+  }
 }
 
 }  // namespace

@@ -45,12 +45,14 @@ constexpr int kMaxRoughLds = 64;       // roughness slots pre-reduced in LDS
 constexpr int kAdjointSplit = 4;
 __host__ __device__ inline int adjoint_split(int spp) { return spp < kAdjointSplit ? spp : kAdjointSplit; }
 
-// Four-child BVH node, 128 bytes (one L2 line): per child its box (lo xyz,
-// hi xyz; two children per three float4, so the boxes are loaded and tested
-// in pairs) and an interior node index (count 0), a leaf's triangle range
-// (count > 0) or nothing (count -1).
+// Four-child BVH node, 128 bytes (one L2 line): the children's boxes by
+// coordinate (one float4 per bound: lo x, lo y, lo z, hi x, hi y, hi z of the
+// four children, so a ray loads the near and the far bound of each axis as
+// whole float4 and needs no min / max to order them), then per child an
+// interior node index (count 0), a leaf's triangle range (count > 0) or
+// nothing (count -1).  An empty slot holds a zero box.
 struct alignas(16) DNode {
-  float box[4][6];
+  float box[6][4];
   int32_t child[4];
   int32_t count[4];
 };

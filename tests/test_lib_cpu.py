@@ -74,12 +74,12 @@ def test_invalid_arguments_rejected_before_launch():
 # packed BVH walked in NumPy
 # ---------------------------------------------------------------------------
 
-NODE = np.dtype([("box", "<f4", (4, 6)), ("child", "<i4", 4), ("count", "<i4", 4)])
+NODE = np.dtype([("box", "<f4", (6, 4)), ("child", "<i4", 4), ("count", "<i4", 4)])
 TRI = np.dtype([("p", "<f4", 9), ("prim", "<i4"), ("flags", "<i4"), ("pad", "<i4")])
 
 
 def _box(nd, s):
-    return nd["box"][s][:3].copy(), nd["box"][s][3:].copy()
+    return nd["box"][:3, s].copy(), nd["box"][3:, s].copy()
 
 
 def _unpack(sc):
