@@ -969,6 +969,19 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   }
 }
 
+// Every stream of the vector form is touched once per step and is far larger
+// than the caches: non-temporal loads and stores keep it from displacing
+// other lines (measured 0.31 -> 0.25-0.28 ms on a 4096^2x3 texture).
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+DEV float4 load_nt(const float4* q) {
+  const nt_f4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(q));
+  return make_float4(t.x, t.y, t.z, t.w);
+}
+DEV void store_nt(float4 x, float4* q) {
+  const nt_f4 t = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(t, reinterpret_cast<nt_f4*>(q));
+}
+
 // Vector form: four parameters per thread and iteration (16-byte loads and
 // stores), parameters [0, 4 n4).
 __global__ __launch_bounds__(256) void k_adam4(float4* __restrict__ p, float4* __restrict__ g,
@@ -978,17 +991,17 @@ __global__ __launch_bounds__(256) void k_adam4(float4* __restrict__ p, float4* _
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * 256;
   for (; i < n4; i += stride) {
-    const float4 gi = g[i], pi = p[i];
-    float4 mi = m[i], vi = v[i];
-    if (zero) g[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 gi = load_nt(g + i), pi = load_nt(p + i);
+    float4 mi = load_nt(m + i), vi = load_nt(v + i);
+    if (zero) store_nt(make_float4(0.f, 0.f, 0.f, 0.f), g + i);
     float4 x;
     x.x = adam1(a, pi.x, gi.x, mi.x, vi.x);
     x.y = adam1(a, pi.y, gi.y, mi.y, vi.y);
     x.z = adam1(a, pi.z, gi.z, mi.z, vi.z);
     x.w = adam1(a, pi.w, gi.w, mi.w, vi.w);
-    m[i] = mi;
-    v[i] = vi;
-    p[i] = x;
+    store_nt(mi, m + i);
+    store_nt(vi, v + i);
+    store_nt(x, p + i);
     if (half_out) {
       const uint32_t lo = __half_as_ushort(__float2half_rn(x.x)) |
                           ((uint32_t)__half_as_ushort(__float2half_rn(x.y)) << 16);
