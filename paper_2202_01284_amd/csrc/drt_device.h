@@ -178,21 +178,17 @@ DEV float diff_of_products(float a, float b, float c, float d) {
 }
 
 // Watertight ray/triangle test (no culling), t in (tmin, tmax] -- the caller
-// decides about t == tmax.  tp is the triangle's record (vertex v's
-// component c at tp[3 v + c]); the coordinates are read along the ray's
-// permuted axes kx, ky, kz directly, so the permutation costs three address
-// offsets per ray instead of selects per test.  Each edge function is
+// decides about t == tmax -- on the vertices' components along the ray's
+// permuted axes kx, ky, kz, relative to the origin.  Each edge function is
 // Kahan's difference of products, whose sign is exact: two triangles
 // sharing an edge evaluate the same two products in swapped roles, so they
 // always agree on which side of the edge the ray passes (no cracks from the
 // rounding of a fused multiply-add), and a value is zero only when the exact
 // one is -- which is what the method's higher-precision fallback for zero
 // edge functions secures, so none is needed.
-DEV bool tri_test(const RayPre& r, const float* tp, float tmin, float tmax, float& t_out,
-                  float& b1, float& b2) {
-  const float Akx = tp[r.kx] - r.okx, Aky = tp[r.ky] - r.oky, Akz = tp[r.kz] - r.okz;
-  const float Bkx = tp[3 + r.kx] - r.okx, Bky = tp[3 + r.ky] - r.oky, Bkz = tp[3 + r.kz] - r.okz;
-  const float Ckx = tp[6 + r.kx] - r.okx, Cky = tp[6 + r.ky] - r.oky, Ckz = tp[6 + r.kz] - r.okz;
+DEV bool tri_test_k(const RayPre& r, float Akx, float Aky, float Akz, float Bkx, float Bky,
+                    float Bkz, float Ckx, float Cky, float Ckz, float tmin, float tmax,
+                    float& t_out, float& b1, float& b2) {
   const float Ax = Akx - r.sx * Akz, Ay = Aky - r.sy * Akz;
   const float Bx = Bkx - r.sx * Bkz, By = Bky - r.sy * Bkz;
   const float Cx = Ckx - r.sx * Ckz, Cy = Cky - r.sy * Ckz;
@@ -211,6 +207,29 @@ DEV bool tri_test(const RayPre& r, const float* tp, float tmin, float tmax, floa
   b1 = V * inv;
   b2 = W * inv;
   return !mixed && det != 0.f && t > tmin && t <= tmax;
+}
+
+// The test on a triangle held in registers: the permuted components picked by
+// selects.
+DEV bool tri_test(const RayPre& r, const DTri& T, float tmin, float tmax, float& t_out, float& b1,
+                  float& b2) {
+  const f3 A = mk(T.p0x, T.p0y, T.p0z) - r.o, B = mk(T.p1x, T.p1y, T.p1z) - r.o;
+  const f3 C = mk(T.p2x, T.p2y, T.p2z) - r.o;
+  return tri_test_k(r, comp(A, r.kx), comp(A, r.ky), comp(A, r.kz), comp(B, r.kx), comp(B, r.ky),
+                    comp(B, r.kz), comp(C, r.kx), comp(C, r.ky), comp(C, r.kz), tmin, tmax, t_out,
+                    b1, b2);
+}
+
+// The test on a triangle record in LDS (vertex v's component c at tp[3 v + c]):
+// the permuted components read directly, three address offsets per ray
+// instead of selects per test.  In device memory the same reads would cost
+// 64-bit addresses and registers in the kernels held to 128 VGPRs.
+DEV bool tri_test_lds(const RayPre& r, const float* tp, float tmin, float tmax, float& t_out,
+                      float& b1, float& b2) {
+  return tri_test_k(r, tp[r.kx] - r.okx, tp[r.ky] - r.oky, tp[r.kz] - r.okz,
+                    tp[3 + r.kx] - r.okx, tp[3 + r.ky] - r.oky, tp[3 + r.kz] - r.okz,
+                    tp[6 + r.kx] - r.okx, tp[6 + r.ky] - r.oky, tp[6 + r.kz] - r.okz, tmin, tmax,
+                    t_out, b1, b2);
 }
 
 DEV DTri load_tri(const DScene& s, int i) {
@@ -256,7 +275,13 @@ DEV void cswap(float& ka, int& va, float& kb, int& vb) {
 // triangle loop.  Each lane still does exactly what it did before, in the
 // same order (node, its batch, the next node) -- only the interleaving of
 // lanes changes -- so the nodes visited and the hit found are the same.
-template <bool ST = false>
+// LSC: the scene is the workgroup's LDS copy (triangle components read along
+// the ray's permuted axes).  IDX: the near and far bounds of each axis read
+// by the ray's signs; without it the six bound quadruples are read at fixed
+// offsets and each slab pair ordered by min / max -- the same values, fewer
+// live registers (the indexed form in device memory costs 64-bit addresses,
+// which made the adjoint megakernels, held to 128 VGPRs, spill).
+template <bool ST = false, bool LSC = false, bool IDX = true>
 DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool any, Hit& h,
                   int* stk, Counters& cnt) {
   float tbest = tmax;
@@ -282,11 +307,29 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       // load and cost every node a second memory round trip.  Empty slots hold
       // a zero box, so the test on them is harmless.
       {  // entry (tn) and exit (tf) distances of the four boxes, axis by axis
-        float4 tn = slab4(np[r.nx], r.idir.x, r.ooi.x), tf = slab4(np[3 - r.nx], r.idir.x, r.ooi.x);
-        tn = max4(tn, slab4(np[r.ny], r.idir.y, r.ooi.y));
-        tf = min4(tf, slab4(np[5 - r.ny], r.idir.y, r.ooi.y));
-        tn = max4(tn, slab4(np[r.nz], r.idir.z, r.ooi.z));
-        tf = min4(tf, slab4(np[7 - r.nz], r.idir.z, r.ooi.z));
+        float4 tn, tf;
+        if constexpr (IDX) {
+          // the near and far bounds read by the ray's signs
+          tn = slab4(np[r.nx], r.idir.x, r.ooi.x);
+          tf = slab4(np[3 - r.nx], r.idir.x, r.ooi.x);
+          tn = max4(tn, slab4(np[r.ny], r.idir.y, r.ooi.y));
+          tf = min4(tf, slab4(np[5 - r.ny], r.idir.y, r.ooi.y));
+          tn = max4(tn, slab4(np[r.nz], r.idir.z, r.ooi.z));
+          tf = min4(tf, slab4(np[7 - r.nz], r.idir.z, r.ooi.z));
+        } else {
+          // fixed offsets, each slab pair ordered by min / max
+          float4 a = slab4(np[0], r.idir.x, r.ooi.x), b = slab4(np[3], r.idir.x, r.ooi.x);
+          tn = min4(a, b);
+          tf = max4(a, b);
+          a = slab4(np[1], r.idir.y, r.ooi.y);
+          b = slab4(np[4], r.idir.y, r.ooi.y);
+          tn = max4(tn, min4(a, b));
+          tf = min4(tf, max4(a, b));
+          a = slab4(np[2], r.idir.z, r.ooi.z);
+          b = slab4(np[5], r.idir.z, r.ooi.z);
+          tn = max4(tn, min4(a, b));
+          tf = min4(tf, max4(a, b));
+        }
         tn = max4(tn, make_float4(tmin, tmin, tmin, tmin));
         tf = min4(tf, make_float4(tbest, tbest, tbest, tbest));
         t0 = tn.x;
@@ -365,12 +408,22 @@ DEV bool traverse(const DScene& s, const RayPre& r, float tmin, float tmax, bool
       off = j < e1 ? f1 : off;
       off = j < e0 ? f0 : off;
       const int i = j + off;
-      const float* tp = reinterpret_cast<const float*>(s.tris + i);
-      const int prim = __float_as_int(tp[9]), flags = __float_as_int(tp[10]);
+      int prim, flags;
+      float t, b1, b2;
+      bool ok;
+      if constexpr (LSC) {
+        const float* tp = reinterpret_cast<const float*>(s.tris + i);
+        prim = __float_as_int(tp[9]);
+        flags = __float_as_int(tp[10]);
+        ok = tri_test_lds(r, tp, tmin, tbest, t, b1, b2);
+      } else {
+        const DTri T = load_tri(s, i);
+        prim = T.prim;
+        flags = T.flags;
+        ok = tri_test(r, T, tmin, tbest, t, b1, b2);
+      }
       cnt.tris++;
       if constexpr (ST) cnt.wave_tris += first_active_lane();
-      float t, b1, b2;
-      bool ok = tri_test(r, tp, tmin, tbest, t, b1, b2);
       if (any) {
         // shadow rays pass through null surfaces; the flag is tested after
         // the whole record has been loaded (no second memory round trip)

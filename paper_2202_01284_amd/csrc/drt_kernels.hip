@@ -83,13 +83,16 @@ enum {
   MODE_TRAIN_SELF = 7
 };
 
-template <int MODE, bool HC = false, bool ST = false>
+template <int MODE, bool HC = false, bool ST = false, bool LS = false>
 DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const DRender& R,
                       const LdsTables& tab, int cam, int x, int y, uint64_t g_base, int n_samples,
                       f3 dL, int* stk, Counters& cnt, const Sink& sink, const DNrcIO& io,
                       f3& out, int4* hrec = nullptr, RoughAcc* racc_out = nullptr) {
   constexpr bool ADJ = MODE == MODE_ADJOINT || MODE == MODE_ADJOINT_CACHED;
   constexpr bool JVP = MODE == MODE_JVP;
+  // the indexed node test except where the scene is read from device memory
+  // by the kernels carrying derivatives (held to 128 VGPRs)
+  constexpr bool IDX = LS || !(ADJ || JVP);
   // modes with a record vertex (cache queries, training records, cached replay)
   constexpr bool HOOK = MODE == MODE_CACHED || MODE == MODE_TRAIN || MODE == MODE_CACHED_SAMPLES ||
                         MODE == MODE_ADJOINT_CACHED || MODE == MODE_TRAIN_SELF;
@@ -174,7 +177,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
       } else {
         RayPre rp = ray_pre(o, d);
         cnt.rays++;
-        hit = traverse<ST>(s, rp, 0.f, INFINITY, false, h, stk, cnt);
+        hit = traverse<ST, LS, IDX>(s, rp, 0.f, INFINITY, false, h, stk, cnt);
       }
       if constexpr (HWRITE) {
         rec_tri = hit ? h.tri : -1;
@@ -441,7 +444,7 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
         RayPre rp = ray_pre(so, sd);
         Hit h;
         cnt.shadow++;
-        vis = !traverse<ST>(s, rp, 0.f, stmax, true, h, stk, cnt);
+        vis = !traverse<ST, LS, IDX>(s, rp, 0.f, stmax, true, h, stk, cnt);
       }
       if constexpr (HWRITE) rec_vis = vis;
       if (vis) {
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_render_forward(DScene s, DParams P, 
       const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
       hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
     }
-    render_pixel<MODE, HC, STATS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
+    render_pixel<MODE, HC, STATS, LS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0, s1 - s0,
                                   mk(0, 0, 0), stack + threadIdx.x, cnt, none, io, acc, hrec);
     if (MODE != MODE_CACHED_SAMPLES) {
       const float inv = 1.0f / (float)R.spp;
@@ -717,7 +720,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
           const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
           hrec = R.hits + wg * R.spp * R.max_depth * kBlock + threadIdx.x;
         }
-        render_pixel<MODE, HC, STATS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
+        render_pixel<MODE, HC, STATS, LS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
                                       s1 - s0, dL, stack + threadIdx.x, cnt, sink, io, unused, hrec,
                                       &racc);
       }
