@@ -413,7 +413,19 @@ drt_status build_packed(const drt_scene_desc* d, Packed* P) {
         uv[2 * k] = d->uvs[2 * (size_t)v];
         uv[2 * k + 1] = d->uvs[2 * (size_t)v + 1];
       }
-    sh[t] = DShade{uv[0], uv[1], uv[2], uv[3], uv[4], uv[5], d->tri_material[t], d->tri_emitter[t]};
+    // the geometric normal, in double and rounded once (zero-area triangles,
+    // which the watertight test never reports as hit, get +z)
+    const float* q[3];
+    for (int k = 0; k < 3; ++k) q[k] = &d->positions[3 * (size_t)d->indices[3 * (size_t)t + k]];
+    const double e1[3] = {(double)q[1][0] - q[0][0], (double)q[1][1] - q[0][1], (double)q[1][2] - q[0][2]};
+    const double e2[3] = {(double)q[2][0] - q[0][0], (double)q[2][1] - q[0][1], (double)q[2][2] - q[0][2]};
+    const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    const float n[3] = {len > 0 ? (float)(c[0] / len) : 0.f, len > 0 ? (float)(c[1] / len) : 0.f,
+                        len > 0 ? (float)(c[2] / len) : 1.f};
+    sh[t] = DShade{uv[0], uv[1], uv[2], uv[3], uv[4], uv[5], d->tri_material[t], d->tri_emitter[t],
+                   n[0], n[1], n[2], 0};
   }
   DMaterial* mats = (DMaterial*)&P->bytes[off[3]];
   for (int m = 0; m < d->n_materials; ++m) {

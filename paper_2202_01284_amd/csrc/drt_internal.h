@@ -78,8 +78,10 @@ struct alignas(16) DShade {
   float u0, v0, u1, v1;
   float u2, v2;
   int32_t material, emitter;
+  float nx, ny, nz;  // unit geometric normal, (p1 - p0) x (p2 - p0) normalised
+  int32_t pad;
 };
-static_assert(sizeof(DShade) == 32, "DShade");
+static_assert(sizeof(DShade) == 48, "DShade");
 
 struct alignas(16) DMaterial {
   int32_t type, texture, rough_slot, pad;

@@ -202,9 +202,10 @@ DEV void render_pixel(const DScene& s, const DParams& P, const DCams& C, const D
         f3 p0 = mk(T.p0x, T.p0y, T.p0z), p1 = mk(T.p1x, T.p1y, T.p1z), p2 = mk(T.p2x, T.p2y, T.p2z);
         float b0 = 1.0f - h.b1 - h.b2;
         f3 p = p0 * b0 + p1 * h.b1 + p2 * h.b2;
-        f3 n_g = normalize(cross(p1 - p0, p2 - p0));
         const float4* shp = reinterpret_cast<const float4*>(s.shade + T.prim);
         float4 sb = shp[1];
+        const float4 sn = shp[2];
+        const f3 n_g = mk(sn.x, sn.y, sn.z);
         int mat_id = __float_as_int(sb.z), em_id = __float_as_int(sb.w);
         float cos_y = -dot(d, n_g);
         if (em_id >= 0 && cos_y > 0.f) {
@@ -577,8 +578,8 @@ DEV DScene scene_view(const DScene& s, float4* lds) {
   if constexpr (!LS) {
     return s;
   } else {
-    // float4 per node / triangle / shading record / material / emitter: 8 / 3 / 2 / 4 / 6
-    const int nn = 8 * s.n_nodes, nt = 3 * s.n_tris, ns = 2 * s.n_tris, nm = 4 * s.n_mats;
+    // float4 per node / triangle / shading record / material / emitter: 8 / 3 / 3 / 4 / 6
+    const int nn = 8 * s.n_nodes, nt = 3 * s.n_tris, ns = 3 * s.n_tris, nm = 4 * s.n_mats;
     const int ne = 6 * s.n_ems;
     float4* p = lds;
     lds_fill(p, s.nodes, nn);

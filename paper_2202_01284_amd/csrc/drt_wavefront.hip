@@ -162,9 +162,10 @@ __global__ __launch_bounds__(kWfBlock) void k_wf_shade(DScene s, DParams P, DRen
     f3 p0 = mk(T.p0x, T.p0y, T.p0z), p1 = mk(T.p1x, T.p1y, T.p1z), p2 = mk(T.p2x, T.p2y, T.p2z);
     float b0 = 1.0f - hv.y - hv.z;
     f3 p = p0 * b0 + p1 * hv.y + p2 * hv.z;
-    f3 n_g = normalize(cross(p1 - p0, p2 - p0));
     const float4* shp = reinterpret_cast<const float4*>(s.shade + T.prim);
     float4 sb = shp[1];
+    const float4 sn = shp[2];
+    const f3 n_g = mk(sn.x, sn.y, sn.z);
     int mat_id = __float_as_int(sb.z), em_id = __float_as_int(sb.w);
     float cos_y = -dot(d, n_g);
     if (em_id >= 0 && cos_y > 0.f) {

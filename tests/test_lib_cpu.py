@@ -314,7 +314,7 @@ def test_lds_copy_decision(name):
           "one": lambda: scenes.triangle_soup(1, seed=1)}[name]()
     nodes, tris, info = _unpack(sc)
     levels = max(_depths(nodes).values()) + 1
-    size = (info["n_nodes"] * 128 + info["n_triangles"] * (48 + 32) + info["n_materials"] * 64 +
+    size = (info["n_nodes"] * 128 + info["n_triangles"] * (48 + 48) + info["n_materials"] * 64 +
             info["n_emitters"] * 96)
     want = int(size <= 5120 and 3 * levels <= 16)
     print(name, size, levels, info["lds_copy"], flush=True)
