@@ -90,6 +90,41 @@ def _unpack(sc):
     return nodes, tris, info
 
 
+SHADE = np.dtype([("uv", "<f4", 6), ("material", "<i4"), ("emitter", "<i4"), ("n", "<f4", 3),
+                  ("pad", "<i4")])
+
+
+def _align256(x):
+    return (x + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("name", ["cornell", "zoo", "soup"])
+def test_packed_shading_records(name):
+    """Shading records by original triangle id: the three uv pairs, material
+    and emitter as given, and the unit geometric normal (p1 - p0) x (p2 - p0),
+    computed in double and rounded once, so each component lies within one
+    float ulp of 1 of the exact value; a zero-area triangle (never reported as
+    hit) gets +z."""
+    sc = {"cornell": lambda: scenes.cornell(conductor=True), "zoo": scenes.bsdf_zoo,
+          "soup": lambda: scenes.triangle_soup(300, seed=4)}[name]()
+    buf, info = drt.scene_pack(sc)
+    nt = sc.n_triangles
+    off_shade = _align256(_align256(max(1, nt) * 128) + 48 * nt)
+    sh = np.frombuffer(buf[off_shade:off_shade + 48 * nt].tobytes(), SHADE)
+    tri = np.asarray(sc.indices).reshape(-1, 3)
+    P = np.asarray(sc.positions, np.float64).reshape(-1, 3)
+    c = np.cross(P[tri[:, 1]] - P[tri[:, 0]], P[tri[:, 2]] - P[tri[:, 0]])
+    length = np.linalg.norm(c, axis=1)
+    ok = length > 0
+    assert ok.any()
+    np.testing.assert_allclose(sh["n"][ok], c[ok] / length[ok, None], rtol=0, atol=2.0 ** -24)
+    assert (sh["n"][~ok] == np.array([0, 0, 1], np.float32)).all()
+    np.testing.assert_array_equal(sh["material"], np.asarray(sc.tri_material).reshape(-1))
+    np.testing.assert_array_equal(sh["emitter"], np.asarray(sc.tri_emitter).reshape(-1))
+    uv = np.asarray(sc.uvs, np.float32).reshape(-1, 2)
+    np.testing.assert_array_equal(sh["uv"], uv[tri].reshape(nt, 6))
+
+
 def _depths(nodes):
     depth = {0: 0}
     for k, nd in enumerate(nodes):
