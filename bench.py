@@ -214,6 +214,27 @@ def main():
                  "wavefront_over_megakernel_time": {"primal": round(wf_ms / mk_ms, 3),
                                                     "adjoint": round(wf_adj / mk_adj, 3)}}
 
+    # forward mode (one pass carrying tangents): the image derivative along a
+    # random direction in the texture and the roughness, same workload
+    gen = torch.Generator(device=dev).manual_seed(8)
+    t_tex = torch.randn(tex.shape, generator=gen, device=dev)
+    t_rough = torch.ones_like(rough)
+    jvp_img = torch.empty((1, R, R, 3), dtype=torch.float32, device=dev)
+    drt.render_jvp(gs, [tex], rough, cams, SPP, D, seed=2, tan_textures=[t_tex],
+                   tan_roughness=t_rough, out=jvp_img)
+    e0.record()
+    for k in range(2):
+        drt.render_jvp(gs, [tex], rough, cams, SPP, D, seed=3 + k, tan_textures=[t_tex],
+                       tan_roughness=t_rough, out=jvp_img)
+    e1.record()
+    torch.cuda.synchronize()
+    jvp_ms = e0.elapsed_time(e1) / 2
+    jvp = {"ms": round(jvp_ms, 3), "msamples_s": round(R * R * SPP / (jvp_ms * 1e-3) / 1e6, 3),
+           "primal_ms": round(mk_ms, 3),
+           "what": "forward-mode image derivative along a random texture and roughness direction "
+                   "(k_render_jvp, one pass carrying tangents), same scene, spp and depth"}
+    del t_tex, jvp_img
+
     # algorithmic work of one adjoint launch (stats run, not timed)
     stats = drt.new_stats()
     drt.render_adjoint(gs, [tex], rough, cams, adj, SPP, D, seed=2 * args.warmup + 2,
@@ -282,6 +303,7 @@ def main():
         "cpu_baseline": cpu,
         "cache": cache,
         "wavefront": wavefront,
+        "jvp": jvp,
         "checkpointed": checkpointed,
         "aux": aux,
         "texture_recovery": recovery,

@@ -744,29 +744,45 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
 // Forward-mode derivative of the image along the direction T (tangent
 // textures and roughness): out = (1/spp) sum of the sample radiance tangents.
-__global__ __launch_bounds__(kBlock) void k_render_jvp(DScene s, DParams P, DCams C, DRender R,
-                                                       DGrads T, float* __restrict__ image) {
-  __shared__ int stack[kStackDepth * kBlock];
+// As the primal: LS reads the scene from the workgroup's LDS copy, and a
+// tile's samples may be split over two workgroups adding onto a zeroed image
+// (blockIdx.z = camera x split + part).  Held to 128 VGPRs (4 waves per
+// SIMD): 4.20 -> 3.93 ms against 3 waves at 130 on 1024^2, 16 spp.
+template <bool LS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_render_jvp(
+    DScene s, DParams P, DCams C, DRender R, DGrads T, float* __restrict__ image) {
+  __shared__ int stack[(LS ? kStackDepthSmall : kStackDepth) * kBlock];
   __shared__ LdsTables tab;
+  __shared__ float4 lds_scene[LS ? kLdsSceneBytes / 16 : 1];
   load_tables(tab, s, P, &T);
+  const DScene sv = scene_view<LS>(s, lds_scene);
   __syncthreads();
   const int W = C.width, H = C.height;
   const int x = blockIdx.x * kTile + (threadIdx.x % kTile);
   const int y = blockIdx.y * kTile + (threadIdx.x / kTile);
-  const int cam = blockIdx.z;
+  const int split = (int)gridDim.z / C.n;
+  const int cam = blockIdx.z / split, part = blockIdx.z % split;
+  const int s0 = part * R.spp / split, s1 = (part + 1) * R.spp / split;
   Counters cnt = {};
-  if (x < W && y < H) {
+  if (x < W && y < H && s1 > s0) {
     Sink dir{&tab, nullptr, T.rough};
     DNrcIO none = {};
     f3 acc;
     const uint64_t pix = ((uint64_t)cam * H + y) * W + x;
-    render_pixel<MODE_JVP>(s, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp, R.spp, mk(0, 0, 0),
-                           stack + threadIdx.x, cnt, dir, none, acc);
+    render_pixel<MODE_JVP, false, false, LS>(sv, P, C, R, tab, cam, x, y, pix * (uint64_t)R.spp + s0,
+                                             s1 - s0, mk(0, 0, 0), stack + threadIdx.x, cnt, dir,
+                                             none, acc);
     const float inv = 1.0f / (float)R.spp;
     float* out = image + 3 * pix;
-    out[0] = acc.x * inv;
-    out[1] = acc.y * inv;
-    out[2] = acc.z * inv;
+    if (split == 1) {
+      out[0] = acc.x * inv;
+      out[1] = acc.y * inv;
+      out[2] = acc.z * inv;
+    } else {
+      atomicAdd(out, acc.x * inv);
+      atomicAdd(out + 1, acc.y * inv);
+      atomicAdd(out + 2, acc.z * inv);
+    }
   }
 }
 
@@ -1196,8 +1212,16 @@ hipError_t launch_render_adjoint_cached(const DScene& s, const DParams& p, const
 
 hipError_t launch_render_jvp(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                              const DGrads& t, float* image, hipStream_t st) {
-  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n);
-  hipLaunchKernelGGL(k_render_jvp, grid, dim3(kBlock), 0, st, s, p, c, r, t, image);
+  const int split = r.spp >= 2 ? 2 : 1;
+  if (split > 1) {
+    hipError_t e = launch_zero(image, 3 * (int64_t)c.n * c.width * c.height, st);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(tiles_of(c.width), tiles_of(c.height), c.n * split);
+  if (use_lds_scene(s, r))
+    hipLaunchKernelGGL((k_render_jvp<true>), grid, dim3(kBlock), 0, st, s, p, c, r, t, image);
+  else
+    hipLaunchKernelGGL((k_render_jvp<false>), grid, dim3(kBlock), 0, st, s, p, c, r, t, image);
   return hipGetLastError();
 }
 

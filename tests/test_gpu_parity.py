@@ -586,6 +586,14 @@ def test_lds_scene_copy_equals_device_memory_reads():
     a = drt.render_forward(gs, tex, rough, sc.cameras, 5, 4, seed=3).cpu().numpy()
     b = drt.render_forward(gs, tex, rough, sc.cameras, 5, 4, seed=3, flags=G).cpu().numpy()
     np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    # forward mode likewise (the tangent image bit-identical)
+    tt = [torch.from_numpy(np.random.default_rng(7).normal(size=t.shape).astype(np.float32)).cuda() for t in tex]
+    tr = torch.ones_like(rough)
+    ja = drt.render_jvp(gs, tex, rough, sc.cameras, 5, 4, seed=8, tan_textures=tt, tan_roughness=tr).cpu().numpy()
+    jb = drt.render_jvp(gs, tex, rough, sc.cameras, 5, 4, seed=8, flags=G, tan_textures=tt,
+                        tan_roughness=tr).cpu().numpy()
+    assert np.abs(ja).max() > 0
+    np.testing.assert_array_equal(ja.view(np.uint32), jb.view(np.uint32))
     adj = torch.from_numpy(np.random.default_rng(4).normal(size=(1, 24, 40, 3)).astype(np.float32)).cuda()
     for hits in (None, drt.adjoint_hit_records(sc.cameras, 5, 4)):
         ga, ra = drt.render_adjoint(gs, tex, rough, sc.cameras, adj, 5, 4, seed=6, hit_records=hits)
