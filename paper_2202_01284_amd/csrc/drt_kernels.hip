@@ -788,12 +788,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
 // Training paths of the radiance cache: path j (counter g = j) starts at the
 // pixel chosen by the first word of its camera block dim 2, and writes record
-// j (features, target) and valid[j].
+// j (features, target) and valid[j].  LS: the scene read from the
+// workgroup's LDS copy, as in the megakernels.
+template <bool LS>
 __global__ __launch_bounds__(kBlock) void k_nrc_records(DScene s, DParams P, DCams C, DRender R,
                                                         int64_t n_paths, DNrcIO io) {
-  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ int stack[(LS ? kStackDepthSmall : kStackDepth) * kBlock];
   __shared__ LdsTables tab;
+  __shared__ float4 lds_scene[LS ? kLdsSceneBytes / 16 : 1];
   load_tables(tab, s, P, nullptr);
+  const DScene sv = scene_view<LS>(s, lds_scene);
   __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n_paths) return;
@@ -805,17 +809,20 @@ __global__ __launch_bounds__(kBlock) void k_nrc_records(DScene s, DParams P, DCa
   Counters cnt = {};
   Sink none{&tab, nullptr, nullptr};
   f3 unused;
-  render_pixel<MODE_TRAIN>(s, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
+  render_pixel<MODE_TRAIN, false, false, LS>(sv, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
                            stack + threadIdx.x, cnt, none, io, unused);
 }
 
 // Self-training paths: path j as in k_nrc_records, written by
 // render_pixel<MODE_TRAIN_SELF>.
+template <bool LS>
 __global__ __launch_bounds__(kBlock) void k_nrc_records_self(DScene s, DParams P, DCams C, DRender R,
                                                              int64_t n_paths, DNrcIO io) {
-  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ int stack[(LS ? kStackDepthSmall : kStackDepth) * kBlock];
   __shared__ LdsTables tab;
+  __shared__ float4 lds_scene[LS ? kLdsSceneBytes / 16 : 1];
   load_tables(tab, s, P, nullptr);
+  const DScene sv = scene_view<LS>(s, lds_scene);
   __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n_paths) return;
@@ -827,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_nrc_records_self(DScene s, DParams P
   Counters cnt = {};
   Sink none{&tab, nullptr, nullptr};
   f3 unused;
-  render_pixel<MODE_TRAIN_SELF>(s, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
+  render_pixel<MODE_TRAIN_SELF, false, false, LS>(sv, P, C, R, tab, cam, x, y, (uint64_t)j, 1, mk(0, 0, 0),
                                 stack + threadIdx.x, cnt, none, io, unused);
 }
 
@@ -1106,8 +1113,12 @@ hipError_t launch_render_cached(const DScene& s, const DParams& p, const DCams& 
 hipError_t launch_nrc_records(const DScene& s, const DParams& p, const DCams& c, const DRender& r,
                               int64_t n_paths, const DNrcIO& io, hipStream_t st) {
   int64_t blocks = (n_paths + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_nrc_records, dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c, r,
-                     n_paths, io);
+  if (use_lds_scene(s, r))
+    hipLaunchKernelGGL((k_nrc_records<true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c,
+                       r, n_paths, io);
+  else
+    hipLaunchKernelGGL((k_nrc_records<false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c,
+                       r, n_paths, io);
   return hipGetLastError();
 }
 
@@ -1115,8 +1126,12 @@ hipError_t launch_nrc_records_self(const DScene& s, const DParams& p, const DCam
                                    const DRender& r, int64_t n_paths, const DNrcIO& io,
                                    hipStream_t st) {
   int64_t blocks = (n_paths + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_nrc_records_self, dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p, c, r,
-                     n_paths, io);
+  if (use_lds_scene(s, r))
+    hipLaunchKernelGGL((k_nrc_records_self<true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, s, p,
+                       c, r, n_paths, io);
+  else
+    hipLaunchKernelGGL((k_nrc_records_self<false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, s,
+                       p, c, r, n_paths, io);
   return hipGetLastError();
 }
 
