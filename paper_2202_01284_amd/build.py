@@ -22,7 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-munsafe-fp-atomics",
-    # packed FP32 instructions are not emitted (see DESIGN notes)
+    # no packed FP32 instructions (v_pk_*_f32): some of their forms have given
+    # wrong results on this hardware; the FP32 VALU peak counts them out
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
